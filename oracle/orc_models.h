@@ -1,0 +1,28 @@
+/* AIRPF CPU oracle -- model interface.  TEST INFRASTRUCTURE ONLY (see orc.h). */
+#ifndef ORC_MODELS_H
+#define ORC_MODELS_H
+#include "orc.h"
+
+typedef struct {
+  int kind, dx, dy, P, store_f32;
+  double th[ORC_MAX_P];
+  double c_log;                 /* additive constant of log g per step     */
+  double s0;                    /* SV: stationary sd                       */
+  double q, r, p0, sq, sp0, hr; /* LGD noise scales                        */
+  double H[ORC_MAX_DX * ORC_MAX_DY];
+  double log3;                  /* BIN                                     */
+} orc_model;
+
+void orc_model_setup(orc_model* M, const orc_problem* P, int store_f32);
+int orc_model_noise_dim(const orc_model* M);
+void orc_model_noise(const orc_model* M, uint64_t seed, int64_t n, int32_t k,
+                     int32_t N, double* z);
+void orc_model_init(const orc_model* M, const double* z, double* x);
+void orc_model_prop(const orc_model* M, const double* xp, const double* z, double* x);
+double orc_model_logpot(const orc_model* M, const double* x, const double* y);
+void orc_model_init_tangent(const orc_model* M, const double* z, double* dx0);
+void orc_model_prop_tangent(const orc_model* M, const double* xp, const double* dxp,
+                            const double* z, double* dx);
+void orc_model_logpot_tangent(const orc_model* M, const double* x, const double* dx,
+                              const double* y, double* dlw);
+#endif
