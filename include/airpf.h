@@ -1,0 +1,127 @@
+/*
+ * airpf.h -- C ABI of the MI355X (gfx950) AIRPF library.
+ *
+ * The augmented island resampling particle filter (Algorithm 1 of Heine,
+ * "Augmented Island Resampling Particle Filters for Particle Markov Chain
+ * Monte Carlo", arXiv:2312.06484, Section 2) run on one GPU: m = 2^S
+ * islands of N particles each (the paper's filters of M particles), internal
+ * resampling every step, and S butterfly interaction stages switched on
+ * adaptively by the effective number of filters (ENF < tau).  A call returns
+ * the marginal-likelihood estimate log Zhat = log gamma^N_T(1) (the estimator
+ * defined after Algorithm 1, unbiased by Theorem 1), which a particle
+ * marginal Metropolis-Hastings step consumes once per iteration.
+ *
+ * Problem statement (Section 1.2): a parameterised hidden Markov model
+ * X_0 ~ pi_0, X_n | X_{n-1} ~ K(X_{n-1}, .), Y_n | X_n ~ G(X_n, .) with
+ * observations y_0 .. y_{T-1} fixed; the estimate is of
+ * p(y_0..y_{T-1} | theta) = gamma_T(1).
+ *
+ * Conventions
+ *   - N is the number of particles PER ISLAND (the paper's M); m is the
+ *     number of islands and must be a power of two; 1 <= N <= 2048.
+ *   - Arrays are plain host pointers unless a flag says otherwise; the
+ *     library copies what it needs and keeps no pointer after returning.
+ *   - The context owns all device workspaces; they grow on demand and are
+ *     reused by later calls on the same context.  One context per host
+ *     thread; calls on one context are serialised on its stream.
+ *   - Every call is deterministic: the same inputs, seed and options give
+ *     bit-identical outputs.  All random numbers are Philox4x32-10 draws at
+ *     fixed counters: key = seed, counter = (c0, island, step, tag << 24 | sub).
+ *   - Errors: every function returns an airpf_status.  On
+ *     AIRPF_E_DOMAIN (theta outside its support) *log_z_out is -inf; on other
+ *     errors outputs are set to NaN where they exist.  A run in which every
+ *     island's weight vanishes is a valid estimate: AIRPF_OK, log Zhat = -inf.
+ */
+#ifndef AIRPF_H
+#define AIRPF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AIRPF_OK = 0,
+  AIRPF_E_INVALID_ARG = 1, /* bad size, NaN/Inf input, wrong d_theta, null pointer */
+  AIRPF_E_DOMAIN = 2,      /* theta outside the model's parameter space */
+  AIRPF_E_NOMEM = 3,       /* device workspace could not be allocated */
+  AIRPF_E_DEVICE = 4,      /* a HIP call or a kernel failed */
+  AIRPF_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+} airpf_status;
+
+/* State-space models (concrete instances of the HMM of Section 1.2).
+ *  AIRPF_LG1  x_0 ~ N(0,1), x' = a x + sx e, y = x + sy v;  theta = (a, sx, sy),
+ *             sx > 0, sy > 0.  d_x = d_y = 1, no constants.
+ *  AIRPF_SV   x_0 ~ N(mu, sigma^2/(1-phi^2)), x' = mu + phi (x - mu) + sigma e,
+ *             y = exp(x/2) v;  theta = (mu, phi, sigma), |phi| < 1, sigma > 0.
+ *  AIRPF_LGD  x_0 ~ N(0, p0 I), x' = A x + sqrt(q) e, y = H x + sqrt(r) v;
+ *             theta = vec(A) row-major (d_x^2 entries); consts =
+ *             (q, r, p0, H row-major d_y x d_x), q, r, p0 > 0;
+ *             d_x in {2, 3, 4, 8}, 1 <= d_y <= 8. */
+typedef enum { AIRPF_LG1 = 0, AIRPF_SV = 1, AIRPF_LGD = 2 } airpf_model_kind;
+
+typedef struct {
+  int32_t kind;          /* airpf_model_kind */
+  int32_t dx, dy;        /* state and observation dimensions */
+  const double* consts;  /* model constants (AIRPF_LGD), host memory */
+  int32_t n_consts;
+} airpf_model;
+
+typedef enum { AIRPF_SYSTEMATIC = 0, AIRPF_MULTINOMIAL = 1 } airpf_resampling;
+typedef enum { AIRPF_FP32 = 0, AIRPF_FP64 = 1 } airpf_precision;
+typedef enum { AIRPF_PATHSPACE = 0, AIRPF_PATHWISE = 1 } airpf_score_mode;
+
+#define AIRPF_FLAG_Y_ON_DEVICE 1u /* y is a device pointer (already resident in HBM) */
+
+typedef struct {
+  double tau;         /* ENF threshold of the adaptation line of Algorithm 1:
+                         stage s interacts iff ENF_{n,s} < tau.  tau <= 1/m never
+                         interacts (independent filters), tau > 1 always does. */
+  int32_t resampling; /* airpf_resampling; the GPU implements AIRPF_SYSTEMATIC */
+  int32_t precision;  /* storage precision of the particle state; all particle
+                         arithmetic is double precision either way */
+  int32_t score_mode; /* airpf_score_mode (airpf_score only) */
+  int32_t ckpt_every; /* checkpoint interval of the score's recomputation (0: auto) */
+  uint32_t flags;     /* AIRPF_FLAG_* */
+} airpf_options;
+
+/* Optional per-call trace, host arrays (any may be NULL). */
+typedef struct {
+  int32_t* sstar;    /* [T] interacting stages per step (0 at the last step) */
+  double* enf;       /* [T*(S+1)] ENF_{n,s}; entries not evaluated are NaN */
+  double* lpost;     /* [T*m] island log-weights after each weighting */
+  int32_t* anc;      /* [(T-1)*m*N] within-island ancestors */
+  int32_t* pi;       /* [(T-1)*m] island source map after the stages */
+  uint64_t* digest;  /* [2*T] order-free digests of ancestors and island maps */
+} airpf_trace;
+
+typedef struct airpf_ctx airpf_ctx;
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t, or NULL for the default stream). */
+airpf_status airpf_ctx_create(int device, void* hip_stream, airpf_ctx** out);
+airpf_status airpf_ctx_destroy(airpf_ctx* ctx);
+
+/* Forward filter: *log_z_out = log Zhat(theta).
+ *   theta [d_theta] host; y [T*dy] row-major (host, or device with
+ *   AIRPF_FLAG_Y_ON_DEVICE); m islands (power of two), N per island. */
+airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, const double* theta,
+                       int32_t d_theta, const double* y, int64_t T, int32_t m, int32_t N,
+                       uint64_t seed, const airpf_options* opt, double* log_z_out,
+                       airpf_trace* trace);
+
+const char* airpf_status_str(airpf_status s);
+
+/* Diagnostics used by the tests: evaluate the library's own device
+ * implementations of exp, log, (cos, sin)(2 pi v), Box-Muller and Philox on
+ * host arrays of length n (outputs host).  `which`: 0 exp, 1 log, 2 cossin
+ * (out2 gets sin), 3 Box-Muller of word pairs (in_u32 pairs, out/out2),
+ * 4 Philox (in_u32 = 6 words per item: key0, key1, c0..c3; out_u32 4 per item). */
+airpf_status airpf_debug_eval(airpf_ctx* ctx, int32_t which, int64_t n, const double* in,
+                              const uint32_t* in_u32, double* out, double* out2,
+                              uint32_t* out_u32);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

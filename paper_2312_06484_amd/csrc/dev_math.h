@@ -1,0 +1,181 @@
+// Device-side counter-based draws and elementary functions for gfx950.
+//
+// Contract shared (as a written specification, not as code) with the CPU
+// checker, so that every integer decision of the filter -- fixed-point
+// weights, ancestors, island selections -- comes out identical:
+//  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (seed lo, seed
+//    hi), counter = (c0, island, step, tag << 24 | sub).
+//  * exp, log and (cos, sin)(2 pi v) evaluated with correctly rounded IEEE
+//    double operations only (fma, +, *, /, sqrt, rint): Cody-Waite reduction
+//    with a two-part ln 2 and a degree-13 Taylor polynomial for exp; the
+//    atanh series in s = (f-1)/(f+1) to s^23 for log; Taylor series of sin
+//    and cos on [-pi/4, pi/4] after a quarter-turn reduction of v.
+//  * Box-Muller: u1 = (w0 + 1/2) 2^-32, v = w1 2^-32, r = sqrt(-2 log u1),
+//    (r cos 2 pi v, r sin 2 pi v).
+// This file is compiled with -ffp-contract=off; fused operations are the
+// explicit fma() calls.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace airpf {
+
+enum : uint32_t { kTagNormal = 1, kTagSys = 2, kTagMult = 3, kTagIsl = 4 };
+
+struct Key { uint32_t k0, k1; };
+
+__host__ __device__ inline Key make_key(uint64_t seed) {
+  return Key{static_cast<uint32_t>(seed & 0xffffffffu), static_cast<uint32_t>(seed >> 32)};
+}
+
+// Philox4x32-10 bijection of the 128-bit counter (w) under the key.
+__device__ __forceinline__ void philox4x32_10(uint32_t w[4], Key key) {
+  uint32_t ka = key.k0, kb = key.k1;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t lo0 = w[0] * 0xD2511F53u, hi0 = __umulhi(w[0], 0xD2511F53u);
+    const uint32_t lo1 = w[2] * 0xCD9E8D57u, hi1 = __umulhi(w[2], 0xCD9E8D57u);
+    const uint32_t n0 = hi1 ^ w[1] ^ ka;
+    const uint32_t n2 = hi0 ^ w[3] ^ kb;
+    w[0] = n0; w[1] = lo1; w[2] = n2; w[3] = lo0;
+    ka += 0x9E3779B9u;
+    kb += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ void draw4(Key key, uint32_t c0, uint32_t island, uint32_t step,
+                                      uint32_t tag, uint32_t sub, uint32_t w[4]) {
+  w[0] = c0; w[1] = island; w[2] = step; w[3] = (tag << 24) | (sub & 0xffffffu);
+  philox4x32_10(w, key);
+}
+
+// uniform on [0,1) from 53 bits of (hi, lo)
+__device__ __forceinline__ double uniform53(uint32_t hi, uint32_t lo) {
+  const uint64_t b = (static_cast<uint64_t>(hi) << 32) | lo;
+  return static_cast<double>(b >> 11) * 0x1p-53;
+}
+
+// Uniform integer in [0, Q), Q >= 1: Lemire's multiply-and-reject on 64-bit
+// candidates taken as (w0:w1), (w2:w3) of sub-blocks 0, 1, ..., at most 64
+// sub-blocks (then the last candidate is used as is).
+__device__ inline uint64_t bounded_u64(Key key, uint32_t c0, uint32_t island, uint32_t step,
+                                       uint32_t tag, uint64_t Q) {
+  const uint64_t reject_below = (~Q + 1) % Q;          // 2^64 mod Q
+  uint64_t hi = 0;
+  for (uint32_t sub = 0; sub < 64; ++sub) {
+    uint32_t w[4];
+    draw4(key, c0, island, step, tag, sub, w);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint64_t cand = (static_cast<uint64_t>(w[2 * h]) << 32) | w[2 * h + 1];
+      hi = __umul64hi(cand, Q);
+      const uint64_t lo = cand * Q;
+      if (lo >= reject_below) return hi;
+    }
+  }
+  return hi;
+}
+
+// ---------------------------------------------------------------- exp / log
+
+__host__ __device__ constexpr double factorial(int n) { return n <= 1 ? 1.0 : n * factorial(n - 1); }
+__host__ __device__ constexpr double inv_factorial(int n) { return 1.0 / factorial(n); }
+__host__ __device__ constexpr double inv_odd(int i) { return 1.0 / (2 * i + 1); }
+
+constexpr double kLn2Head = 0x1.62e42fee00000p-1;   // ln 2, 32 significant bits
+constexpr double kLn2Tail = 0x1.a39ef35793c76p-33;  // ln 2 - head
+constexpr double kLn2 = 0x1.62e42fefa39efp-1;
+constexpr double kInvLn2 = 0x1.71547652b82fep+0;
+constexpr double kTwoPi = 0x1.921fb54442d18p+2;
+
+__device__ __forceinline__ double scale2(double p, int k) {  // p * 2^k, -1022 <= k <= 1023
+  return p * __longlong_as_double(static_cast<long long>(k + 1023) << 52);
+}
+
+__device__ inline double dexp(double x) {
+  if (!(x == x)) return x;
+  if (x > 0x1.62e42fefa39efp+9) return __longlong_as_double(0x7ff0000000000000LL);
+  if (x < -0x1.74910d52d3051p+9) return 0.0;
+  const double kd = rint(x * kInvLn2);
+  const double r = fma(-kd, kLn2Tail, fma(-kd, kLn2Head, x));
+  double p = inv_factorial(13);
+#pragma unroll
+  for (int i = 12; i >= 2; --i) p = fma(p, r, inv_factorial(i));
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  const int k = static_cast<int>(kd);
+  if (k > 1023) return scale2(p * 2.0, k - 1);
+  if (k < -1022) return scale2(scale2(p, k + 200), -200);
+  return scale2(p, k);
+}
+
+__device__ inline double dlog(double x) {
+  if (!(x == x) || x < 0.0) return __longlong_as_double(0x7ff8000000000000LL);
+  if (x == 0.0) return -__longlong_as_double(0x7ff0000000000000LL);
+  if (x == __longlong_as_double(0x7ff0000000000000LL)) return x;
+  int e = 0;
+  if (x < 0x1p-1022) { x = x * 0x1p+54; e = -54; }
+  const long long bits = __double_as_longlong(x);
+  e += static_cast<int>((bits >> 52) & 0x7ff) - 1023;
+  double f = __longlong_as_double((bits & 0x000fffffffffffffLL) | 0x3ff0000000000000LL);
+  if (f > 0x1.6a09e667f3bcdp+0) { f = f * 0.5; e += 1; }
+  const double s = (f - 1.0) / (f + 1.0);
+  const double z = s * s;
+  double p = inv_odd(11);
+#pragma unroll
+  for (int i = 10; i >= 1; --i) p = fma(p, z, inv_odd(i));
+  p = fma(p, z, 1.0);
+  double t = s * p;
+  t = t + t;
+  const double ed = static_cast<double>(e);
+  return ed * kLn2Head + (ed * kLn2Tail + t);
+}
+
+__device__ inline void cossin_2pi(double v, double& c, double& s) {
+  const double q = rint(v * 4.0);
+  const double th = (v - q * 0.25) * kTwoPi;
+  const double z = th * th;
+  double ps = -inv_factorial(19);
+#pragma unroll
+  for (int i = 8; i >= 0; --i) ps = fma(ps, z, (i & 1) ? -inv_factorial(2 * i + 1) : inv_factorial(2 * i + 1));
+  const double sn = th * ps;
+  double pc = inv_factorial(20);
+#pragma unroll
+  for (int i = 9; i >= 0; --i) pc = fma(pc, z, (i & 1) ? -inv_factorial(2 * i) : inv_factorial(2 * i));
+  const int quad = static_cast<int>(q) & 3;
+  const double a = (quad & 1) ? -sn : pc;   // cos(th + quad pi/2) for quad 0, 1
+  const double b = (quad & 1) ? pc : sn;    // sin(th + quad pi/2) for quad 0, 1
+  c = (quad & 2) ? -a : a;
+  s = (quad & 2) ? -b : b;
+}
+
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& z0, double& z1) {
+  const double u1 = (static_cast<double>(wa) + 0.5) * 0x1p-32;
+  const double r = sqrt(-2.0 * dlog(u1));
+  double c, s;
+  cossin_2pi(static_cast<double>(wb) * 0x1p-32, c, s);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+// normals 4g .. 4g+3 of (step, island)
+__device__ __forceinline__ void normals4(Key key, uint32_t g, uint32_t island, uint32_t step, double z[4]) {
+  uint32_t w[4];
+  draw4(key, g, island, step, kTagNormal, 0, w);
+  box_muller(w[0], w[1], z[0], z[1]);
+  box_muller(w[2], w[3], z[2], z[3]);
+}
+
+__device__ __forceinline__ uint64_t fmix64(uint64_t h) {
+  h ^= h >> 33; h *= 0xff51afd7ed558ccdULL;
+  h ^= h >> 33; h *= 0xc4ceb9fe1a85ec53ULL;
+  h ^= h >> 33;
+  return h;
+}
+
+// digest term of value v at (step, island, slot); slot 4095 tags island maps
+__device__ __forceinline__ uint64_t digest_term(uint64_t step, uint64_t island, uint64_t slot, uint64_t v) {
+  return fmix64(fmix64((step << 28) ^ (island << 12) ^ slot) ^ v);
+}
+
+}  // namespace airpf

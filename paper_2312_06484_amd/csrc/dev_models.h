@@ -1,0 +1,95 @@
+// State-space models on the device: initial draw, mutation kernel K and the
+// per-particle part of log g_n (Section 1.2's HMM; the concrete models are
+// listed in include/airpf.h).  Arithmetic is double precision; a state kept
+// in binary32 is rounded once when produced, and every later use reads the
+// rounded value.  Operation order is part of the contract with the CPU
+// checker (explicit fma only):
+//   LG1  x_0 = z;  x' = fma(a, x, sx*z);  lw = -0.5*(r*r), r = (y - x)/sy
+//   SV   x_0 = fma(s0, z, mu);  x' = fma(phi, x - mu, fma(sigma, z, mu));
+//        lw = fma(-(0.5*(y*y)), exp(-x), -0.5*x)
+//   LGD  x_0[d] = sqrt(p0)*z_d;  x'[i] = sqrt(q)*z_i then fma(A[i][c], x[c], .)
+//        over c;  e_i = y_i then fma(-H[i][c], x[c], .) over c;
+//        ss = fma(e_i, e_i, ss) over i;  lw = -(ss*(1/(2r)))
+#pragma once
+#include "dev_math.h"
+
+namespace airpf {
+
+constexpr int kMaxTheta = 64;
+constexpr int kMaxDy = 8;
+
+// Parameters of one problem, passed by value as a kernel argument.
+struct ModelArgs {
+  double th[kMaxTheta];
+  double H[kMaxDy * 8];
+  double s0, sq, sp0, hr;
+  int dy;
+};
+
+template <typename Store>
+__device__ __forceinline__ double round_store(double v) {
+  return static_cast<double>(static_cast<Store>(v));
+}
+
+struct LG1 {
+  static constexpr int DX = 1;
+  template <typename Store>
+  __device__ static void init(const ModelArgs&, const double* z, double* x) { x[0] = round_store<Store>(z[0]); }
+  template <typename Store>
+  __device__ static void prop(const ModelArgs& p, const double* xp, const double* z, double* x) {
+    x[0] = round_store<Store>(fma(p.th[0], xp[0], p.th[1] * z[0]));
+  }
+  __device__ static double logpot(const ModelArgs& p, const double* x, const double* y) {
+    const double r = (y[0] - x[0]) / p.th[2];
+    return -0.5 * (r * r);
+  }
+};
+
+struct SV {
+  static constexpr int DX = 1;
+  template <typename Store>
+  __device__ static void init(const ModelArgs& p, const double* z, double* x) {
+    x[0] = round_store<Store>(fma(p.s0, z[0], p.th[0]));
+  }
+  template <typename Store>
+  __device__ static void prop(const ModelArgs& p, const double* xp, const double* z, double* x) {
+    const double mu = p.th[0];
+    x[0] = round_store<Store>(fma(p.th[1], xp[0] - mu, fma(p.th[2], z[0], mu)));
+  }
+  __device__ static double logpot(const ModelArgs&, const double* x, const double* y) {
+    const double h = 0.5 * (y[0] * y[0]);
+    return fma(-h, dexp(-x[0]), -0.5 * x[0]);
+  }
+};
+
+template <int D>
+struct LGD {
+  static constexpr int DX = D;
+  template <typename Store>
+  __device__ static void init(const ModelArgs& p, const double* z, double* x) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[d] = round_store<Store>(p.sp0 * z[d]);
+  }
+  template <typename Store>
+  __device__ static void prop(const ModelArgs& p, const double* xp, const double* z, double* x) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double acc = p.sq * z[i];
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc = fma(p.th[i * D + c], xp[c], acc);
+      x[i] = round_store<Store>(acc);
+    }
+  }
+  __device__ static double logpot(const ModelArgs& p, const double* x, const double* y) {
+    double ss = 0.0;
+    for (int i = 0; i < p.dy; ++i) {
+      double e = y[i];
+#pragma unroll
+      for (int c = 0; c < D; ++c) e = fma(-p.H[i * D + c], x[c], e);
+      ss = fma(e, e, ss);
+    }
+    return -(ss * p.hr);
+  }
+};
+
+}  // namespace airpf

@@ -1,0 +1,573 @@
+// AIRPF forward pass on gfx950: one persistent cooperative launch runs all T
+// filter steps of Algorithm 1 (Heine, arXiv:2312.06484, Section 2).
+//
+// Work decomposition
+//   * A team of TP lanes (power of two, <= 256) owns one island; lane l holds
+//     particles [l*PPT, (l+1)*PPT) of it in registers, PPT >= 4 normals' worth
+//     so that one Philox call feeds whole Box-Muller pairs.
+//   * Block b (256 lanes) owns the c = m/G consecutive islands
+//     [b*c, (b+1)*c) and processes them tpb = 256/TP at a time.
+//   * Per step the only grid-wide dependency is the island-weight cascade
+//     (the ENF test and the pair selections): one grid barrier per step.
+//
+// Step n, per island k (Algorithm 1 in order):
+//   mutation     x_n = K(block pi_{n-1}(k) of step n-1's resampled state)
+//                (or x_0 ~ pi_0), normals at (step n, island k);
+//   weighting    lw = log g_n(x) per particle, q = floor(2^40 exp(lw - max)),
+//                Q = sum q (exact), L_k = Lpre_k + ((max + log Q) + cst);
+//   resampling   systematic on the integer cumulative weights: slot j takes
+//                min{i : N C_i > U + j Q}, U uniform on [0, Q);
+//   island tree  pair means log((W_a + W_b)/2) of aligned blocks, level by
+//                level (the normaliser line of Algorithm 1 applied to a
+//                block's two halves); published with per-level partial sums
+//                of W^2 for the ENF.
+// After the barrier every block evaluates the ENF of each stage from the
+// published partials, s* = the number of leading stages with ENF < tau, and
+// walks each of its islands down the stages s*, ..., 1: at stage s island
+// cur takes its partner cur ^ 2^(s-1) with probability
+// W_p / (W_cur + W_p) (draw at (step, island cur, stage s)).  The island's
+// next weight is its 2^{s*}-block mean.
+//
+// ENF at stage s (W the weights after s-1 interacting stages, B_b the sums of
+// the aligned 2^{s-1}-blocks): ENF_s = 2^{s-1} (sum W)^2 / (m sum_b B_b^2),
+// in logs 2 log sum W - log m - log sum_b exp(2 LT_b) - (s-1) log 2 with
+// LT_b = log(B_b / 2^{s-1}) the pair-mean tree value.
+#include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
+#include <stdint.h>
+
+#include "dev_models.h"
+#include "internal.h"
+
+namespace airpf {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+
+__device__ __forceinline__ int64_t tree_off(int m, int level) {  // level >= 1
+  return 2 * static_cast<int64_t>(m) - ((2 * static_cast<int64_t>(m)) >> (level - 1));
+}
+
+__device__ __forceinline__ double ninf() { return -__longlong_as_double(0x7ff0000000000000LL); }
+
+// log((exp(a) + exp(b)) / 2), symmetric in (a, b)
+__device__ __forceinline__ double pair_mean(double a, double b) {
+  const double hi = a > b ? a : b, lo = a > b ? b : a;
+  if (hi == ninf()) return hi;
+  double t = dexp(lo - hi);
+  t = 1.0 + t;
+  t = dlog(t);
+  return (hi + t) - kLn2;
+}
+
+// probability that an island with log-weight lk takes its partner's block
+__device__ __forceinline__ double take_partner_prob(double lk, double lp) {
+  if (lp == ninf()) return 0.0;
+  if (lk == ninf()) return 1.0;
+  return 1.0 / (1.0 + dexp(lk - lp));
+}
+
+// ------------------------------------------------------------ grid barrier
+// Monotone arrival counter bar[0] and release word bar[1]; the last block of
+// epoch e publishes e.  Spinning is bounded: after ~2^24 polls (seconds) a
+// block gives up, raises status and every block leaves its step loop.
+__device__ bool grid_barrier(unsigned* bar, unsigned G, unsigned& epoch, int* status) {
+  __shared__ int s_ok;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ++epoch;
+    int ok = 1;
+    const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == epoch * G - 1) {
+      __hip_atomic_store(&bar[1], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 1023u) == 0 &&
+            (spins > (1u << 24) || __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+          ok = 0;
+          __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return s_ok != 0;
+}
+
+// ------------------------------------------------------------ team / block reductions
+// A team is TP consecutive lanes (TP a power of two); TP <= 64 stays inside
+// one wave (shuffles only), TP > 64 spans TP/64 whole waves (LDS combine).
+// Every helper is called by the whole block (TP is block-uniform).
+
+template <typename T>
+__device__ __forceinline__ T team_bcast(T v, int TP, T* lds_slot_per_team) {
+  const int tid = threadIdx.x;
+  if (TP <= 64) return __shfl(v, (tid & 63) & ~(TP - 1), 64);
+  const int team = tid / TP;
+  if ((tid & (TP - 1)) == 0) lds_slot_per_team[team] = v;
+  __syncthreads();
+  const T r = lds_slot_per_team[team];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double team_max(double v, int TP, double* red) {
+  const int w = TP < 64 ? TP : 64;
+  for (int d = 1; d < w; d <<= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  if (TP > 64) {
+    const int tid = threadIdx.x;
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    const int w0 = (tid / TP) * (TP >> 6);
+    double r = red[w0];
+    for (int i = 1; i < (TP >> 6); ++i) r = fmax(r, red[w0 + i]);
+    __syncthreads();
+    v = r;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t team_sum_u64(uint64_t v, int TP, uint64_t* red) {
+  const int w = TP < 64 ? TP : 64;
+  for (int d = 1; d < w; d <<= 1) v += __shfl_xor(v, d, 64);
+  if (TP > 64) {
+    const int tid = threadIdx.x;
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    const int w0 = (tid / TP) * (TP >> 6);
+    uint64_t r = 0;
+    for (int i = 0; i < (TP >> 6); ++i) r += red[w0 + i];
+    __syncthreads();
+    v = r;
+  }
+  return v;
+}
+
+// inclusive scan of v over the team's lanes (lane order)
+__device__ __forceinline__ uint64_t team_scan_u64(uint64_t v, int TP, uint64_t* red) {
+  const int tid = threadIdx.x;
+  const int w = TP < 64 ? TP : 64;
+  const int sl = tid & (w - 1);
+  for (int d = 1; d < w; d <<= 1) {
+    const uint64_t t = __shfl_up(v, d, w);
+    if (sl >= d) v += t;
+  }
+  if (TP > 64) {
+    if ((tid & 63) == 63) red[tid >> 6] = v;
+    __syncthreads();
+    const int w0 = (tid / TP) * (TP >> 6);
+    uint64_t add = 0;
+    for (int i = w0; i < (tid >> 6); ++i) add += red[i];
+    __syncthreads();
+    v += add;
+  }
+  return v;
+}
+
+// block-wide reductions with a fixed pattern (identical result in every block)
+__device__ double block_max(double v, double* red) {
+  for (int d = 1; d < 64; d <<= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < kWaves; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_sum(double v, double* red) {
+  for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < kWaves; ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+
+// log sum_i exp(scale * v[i]) over n values (global or LDS), whole block
+__device__ double block_lse(const double* v, int n, double scale, double* red) {
+  double mx = ninf();
+  for (int i = threadIdx.x; i < n; i += kBlock) mx = fmax(mx, scale * v[i]);
+  mx = block_max(mx, red);
+  if (mx == ninf()) return mx;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += dexp(scale * v[i] - mx);
+  s = block_sum(s, red);
+  return mx + dlog(s);
+}
+
+// ------------------------------------------------------------ the kernel
+
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
+  constexpr int DX = Model::DX;
+  constexpr int NZ = PPT * DX;                 // normals per lane per step
+  static_assert(NZ % 4 == 0, "a lane consumes whole Philox blocks");
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red_d[kWaves];
+  __shared__ uint64_t red_u[kWaves];
+  __shared__ uint64_t bc_u[kBlock];
+  __shared__ int bc_i[kBlock];
+  __shared__ int s_sstar;
+
+  const int tid = threadIdx.x;
+  const int TP = a.TP, tpb = kBlock / TP;
+  const int team = tid / TP, lane = tid & (TP - 1);
+  const int m = a.m, N = a.N, S = a.S, c = a.c, lc = a.lc, G = a.G;
+  const int kbase = blockIdx.x * c;
+  const Key key = make_key(a.seed);
+  const int passes = (c + tpb - 1) / tpb;
+
+  Store* sx = reinterpret_cast<Store*>(smem);                                    // [kBlock*NZ]
+  uint64_t* sC = reinterpret_cast<uint64_t*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));
+  double* lv = reinterpret_cast<double*>(sC + kBlock * PPT);                      // [2c]
+  double* up = lv + 2 * c;                                                        // [2G]
+
+  unsigned epoch = 0;
+  const double log_m = dlog(static_cast<double>(m));
+  const double log_c = dlog(static_cast<double>(c));
+
+  auto lt_value = [&](int par, int level, int idx) -> double {   // tree value, level >= 1
+    if (level <= lc + 1) return a.tree[par][tree_off(m, level) + idx];
+    const int u = level - (lc + 1);
+    return up[2 * G - ((2 * G) >> u) + idx];
+  };
+
+  for (int64_t n = 0; n < a.T; ++n) {
+    const int par = static_cast<int>(n & 1), ppar = par ^ 1;
+    if (n > 0) {
+      if (!grid_barrier(a.bar, G, epoch, a.status)) return;
+      // ---- cascade of step n-1 (every block, identical) ----
+      for (int b = tid; b < G; b += kBlock) up[b] = a.tree[ppar][tree_off(m, lc + 1) + b];
+      __syncthreads();
+      for (int u = 1; lc + 1 + u <= S + 1; ++u) {
+        const int cnt = G >> u;
+        const int o_prev = 2 * G - ((2 * G) >> (u - 1)), o = 2 * G - ((2 * G) >> u);
+        for (int i = tid; i < cnt; i += kBlock) up[o + i] = pair_mean(up[o_prev + 2 * i], up[o_prev + 2 * i + 1]);
+        __syncthreads();
+      }
+      const double lsum = block_lse(up, G, 1.0, red_d) + log_c;      // log sum_k W_k
+      if (lsum == ninf()) {                                          // every island dead
+        if (blockIdx.x == 0 && tid == 0) *a.out_logz = ninf();
+        return;
+      }
+      int sstar = 0;
+      if (a.shortcut_all) {
+        sstar = S;
+      } else {
+        // stages interact while ENF < tau; a stage that does not interact leaves
+        // every weight unchanged, so every later stage sees the same ENF and
+        // does not interact either (traced as that same value)
+        for (int s = 1; s <= S; ++s) {
+          const double l2 = (s <= lc + 1) ? block_lse(a.part[ppar] + (int64_t)(s - 1) * G, G, 1.0, red_d)
+                                          : block_lse(up + 2 * G - ((2 * G) >> (s - lc - 1)), m >> (s - 1), 2.0, red_d);
+          const double enf = dexp(2.0 * lsum - log_m - l2 - (s - 1) * kLn2);
+          const bool go = enf < a.tau;
+          if (a.tr_enf && blockIdx.x == 0 && tid == 0)
+            for (int t = s; t <= (go ? s : S); ++t) a.tr_enf[(n - 1) * (S + 1) + t] = enf;
+          if (!go) break;
+          sstar = s;
+        }
+      }
+      if (blockIdx.x == 0 && tid == 0) {
+        if (a.tr_sstar) a.tr_sstar[n - 1] = sstar;
+        if (a.tr_digest) atomicAdd(&a.tr_digest[2 * (n - 1) + 1], (unsigned long long)sstar * 0x9E3779B97F4A7C15ULL);
+      }
+      s_sstar = sstar;
+      __syncthreads();
+    }
+    const int sstar = (n > 0) ? s_sstar : 0;
+
+    for (int p = 0; p < passes; ++p) {
+      const int li = p * tpb + team;
+      const bool active = li < c;
+      const int k = kbase + (active ? li : 0);
+      const int j0 = lane * PPT;
+
+      // ---- mutation (or initial draw) ----
+      double z[NZ];
+      for (int g = 0; g < NZ / 4; ++g) {
+        double t[4];
+        normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
+      }
+      double x[PPT][DX];
+      double Lpre = 0.0;
+      if (n == 0) {
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * DX, x[r]);
+      } else {
+        int src = k;
+        if (lane == 0 && active) {
+          int cur = k;
+          for (int s = sstar; s >= 1; --s) {
+            const int pr = cur ^ (1 << (s - 1));
+            const double lc_ = lt_value(ppar, s, cur >> (s - 1));
+            const double lp_ = lt_value(ppar, s, pr >> (s - 1));
+            uint32_t w[4];
+            draw4(key, static_cast<uint32_t>(s), static_cast<uint32_t>(cur), static_cast<uint32_t>(n - 1), kTagIsl, 0, w);
+            if (uniform53(w[0], w[1]) < take_partner_prob(lc_, lp_)) cur = pr;
+          }
+          src = cur;
+          Lpre = lt_value(ppar, sstar + 1, k >> sstar);
+          if (a.tr_pi) a.tr_pi[(n - 1) * m + k] = src;
+          if (a.tr_digest) atomicAdd(&a.tr_digest[2 * (n - 1) + 1], digest_term(n - 1, k, 4095, src));
+        }
+        src = team_bcast(src, TP, bc_i);
+        const Store* xin = static_cast<const Store*>(a.x1[ppar]) + (static_cast<int64_t>(src) * N) * DX;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const int j = j0 + r;
+          double xp[DX];
+#pragma unroll
+          for (int d = 0; d < DX; ++d) xp[d] = (j < N) ? static_cast<double>(xin[j * DX + d]) : 0.0;
+          Model::template prop<Store>(a.mp, xp, z + r * DX, x[r]);
+        }
+      }
+
+      // ---- weighting ----
+      const double* yn = a.y + n * a.dy;
+      double lw[PPT];
+      double mx = ninf();
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        const bool valid = active && (j0 + r < N);
+        double v = valid ? Model::logpot(a.mp, x[r], yn) : ninf();
+        if (!(v == v)) v = ninf();
+        lw[r] = v;
+        mx = fmax(mx, v);
+      }
+      mx = team_max(mx, TP, red_d);
+      uint64_t q[PPT];
+      uint64_t tsum = 0;
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        q[r] = (mx == ninf()) ? 0 : static_cast<uint64_t>(dexp(lw[r] - mx) * 0x1p40);
+        tsum += q[r];
+      }
+      const uint64_t incl = team_scan_u64(tsum, TP, red_u);
+      const uint64_t Qk = team_sum_u64(tsum, TP, red_u);       // Q = sum_i q_i of the island
+      if (lane == 0 && active) {
+        const double L = (Qk == 0) ? ninf() : Lpre + ((mx + dlog(static_cast<double>(Qk))) + a.cst_q);
+        lv[li] = L;
+        if (a.tr_lpost) a.tr_lpost[n * m + k] = L;
+      }
+
+      // ---- internal resampling ----
+      if (n < a.T - 1) {
+        Store* sxt = sx + team * TP * NZ;
+        uint64_t* sCt = sC + team * TP * PPT;
+        uint64_t run = incl - tsum;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          run += q[r];
+          sCt[j0 + r] = run;
+#pragma unroll
+          for (int d = 0; d < DX; ++d) sxt[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
+        }
+        uint64_t U = 0;
+        if (lane == 0 && active && Qk > 0) U = bounded_u64(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, Qk);
+        U = team_bcast(U, TP, bc_u);
+        __syncthreads();
+        Store* xo = static_cast<Store*>(a.x1[par]) + (static_cast<int64_t>(k) * N) * DX;
+        unsigned long long dig = 0;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const int j = j0 + r;
+          if (active && j < N) {
+            int anc = j;
+            if (Qk > 0) {
+              const uint64_t t = U + static_cast<uint64_t>(j) * Qk;
+              int lo = 0, hi = N - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (static_cast<uint64_t>(N) * sCt[mid] > t) hi = mid; else lo = mid + 1;
+              }
+              anc = lo;
+            }
+#pragma unroll
+            for (int d = 0; d < DX; ++d) xo[j * DX + d] = sxt[anc * DX + d];
+            if (a.tr_anc) a.tr_anc[(n * m + k) * static_cast<int64_t>(N) + j] = anc;
+            if (a.tr_digest) dig += digest_term(n, k, j, anc);
+          }
+        }
+        if (a.tr_digest) {
+          dig = team_sum_u64(dig, TP, red_u);
+          if (lane == 0 && active) atomicAdd(&a.tr_digest[2 * n], dig);
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+
+    // ---- this block's part of the island tree and the ENF partial sums ----
+    for (int l = 2; l <= lc + 1; ++l) {
+      const int cnt = c >> (l - 1);
+      const int o_prev = 2 * c - ((2 * c) >> (l - 2)), o = 2 * c - ((2 * c) >> (l - 1));
+      for (int i = tid; i < cnt; i += kBlock) lv[o + i] = pair_mean(lv[o_prev + 2 * i], lv[o_prev + 2 * i + 1]);
+      __syncthreads();
+    }
+    for (int l = 1; l <= lc + 1; ++l) {
+      const int cnt = c >> (l - 1);
+      const int o = 2 * c - ((2 * c) >> (l - 1));
+      double* dst = a.tree[par] + tree_off(m, l) + (kbase >> (l - 1));
+      for (int i = tid; i < cnt; i += kBlock) dst[i] = lv[o + i];
+    }
+    if (tid <= lc) {
+      const int l = tid + 1;
+      const int cnt = c >> (l - 1);
+      const int o = 2 * c - ((2 * c) >> (l - 1));
+      double mx2 = ninf();
+      for (int i = 0; i < cnt; ++i) mx2 = fmax(mx2, 2.0 * lv[o + i]);
+      double v = mx2;
+      if (mx2 != ninf()) {
+        double s = 0.0;
+        for (int i = 0; i < cnt; ++i) s += dexp(2.0 * lv[o + i] - mx2);
+        v = mx2 + dlog(s);
+      }
+      a.part[par][static_cast<int64_t>(l - 1) * G + blockIdx.x] = v;
+    }
+  }
+
+  // ---- log Zhat after the last weighting ----
+  if (!grid_barrier(a.bar, G, epoch, a.status)) return;
+  if (blockIdx.x == 0) {
+    const int par = static_cast<int>((a.T - 1) & 1);
+    const double lsum = block_lse(a.tree[par] + tree_off(m, lc + 1), G, 1.0, red_d) + log_c;
+    if (tid == 0) {
+      *a.out_logz = lsum - log_m;
+      if (a.tr_sstar) a.tr_sstar[a.T - 1] = 0;
+    }
+  }
+}
+
+}  // namespace airpf
+
+// ============================================================ host launcher
+
+namespace airpf {
+
+static int pow2_ceil(int v) { int p = 1; while (p < v) p <<= 1; return p; }
+static int ilog2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
+
+static size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) {
+  const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
+  return sx + 8 * size_t(kBlock) * ppt + 8 * 2 * size_t(c) + 8 * 2 * size_t(G);
+}
+
+template <class Model, typename Store, int PPT>
+static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
+  auto kern = forward_kernel<Model, Store, PPT>;
+  const int TP = pow2_ceil((a.N + PPT - 1) / PPT);
+  const int tpb = kBlock / TP;
+  int G = a.m / tpb;
+  if (G < 1) G = 1;
+  if (G > L.max_blocks) G = L.max_blocks;
+  G = 1 << ilog2i(G + 1) >> 1;                  // power of two <= G
+  if (G < 1) G = 1;
+  size_t smem = 0;
+  for (; G >= 1; G >>= 1) {
+    const int c = a.m / G;
+    smem = fwd_smem_bytes(sizeof(Store), PPT, Model::DX, c, G);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, smem);
+    if (e != hipSuccess) return e;
+    if (static_cast<long>(per_cu) * L.num_cus >= G) break;
+  }
+  if (G < 1) return hipErrorCooperativeLaunchTooLarge;
+  a.TP = TP;
+  a.G = G;
+  a.c = a.m / G;
+  a.lc = ilog2i(a.c);
+  plan->ppt = PPT; plan->tp = TP; plan->G = G; plan->c = a.c; plan->smem = smem;
+  if (L.plan_only) return hipSuccess;
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(G), dim3(kBlock), args,
+                                    static_cast<unsigned>(smem), L.stream);
+}
+
+// particles per lane: the smallest PPT with PPT*DX a multiple of four (a lane
+// consumes whole Philox blocks) and at most 256 lanes per island
+template <class Model, typename Store>
+static hipError_t dispatch_ppt(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan) {
+  constexpr int DX = Model::DX;
+  if constexpr (DX % 4 == 0) {
+    if (a.N <= 256) return launch_t<Model, Store, 1>(L, a, plan);
+    if (a.N <= 512) return launch_t<Model, Store, 2>(L, a, plan);
+  } else if constexpr (DX % 2 == 0) {
+    if (a.N <= 512) return launch_t<Model, Store, 2>(L, a, plan);
+  }
+  if (a.N <= 1024) return launch_t<Model, Store, 4>(L, a, plan);
+  return launch_t<Model, Store, 8>(L, a, plan);
+}
+
+template <typename Store>
+static hipError_t dispatch_model(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan) {
+  switch (L.kind) {
+    case 0: return dispatch_ppt<LG1, Store>(L, a, plan);
+    case 1: return dispatch_ppt<SV, Store>(L, a, plan);
+    case 2:
+      switch (L.dx) {
+        case 2: return dispatch_ppt<LGD<2>, Store>(L, a, plan);
+        case 3: return dispatch_ppt<LGD<3>, Store>(L, a, plan);
+        case 4: return dispatch_ppt<LGD<4>, Store>(L, a, plan);
+        case 8: return dispatch_ppt<LGD<8>, Store>(L, a, plan);
+      }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_forward(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan) {
+  return L.fp64 ? dispatch_model<double>(L, a, plan) : dispatch_model<float>(L, a, plan);
+}
+
+// ------------------------------------------------------------ small helpers
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+
+hipError_t fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t st) {
+  if (n_words <= 0) return hipSuccess;
+  int64_t blocks = (n_words + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  fill_u32_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st>>>(static_cast<uint32_t*>(p), v, n_words);
+  return hipGetLastError();
+}
+
+__global__ void debug_eval_kernel(int which, int64_t n, const double* in, const uint32_t* in_u32, double* out,
+                                  double* out2, uint32_t* out_u32) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  switch (which) {
+    case 0: out[i] = dexp(in[i]); break;
+    case 1: out[i] = dlog(in[i]); break;
+    case 2: { double c, s; cossin_2pi(in[i], c, s); out[i] = c; out2[i] = s; break; }
+    case 3: { double z0, z1; box_muller(in_u32[2 * i], in_u32[2 * i + 1], z0, z1); out[i] = z0; out2[i] = z1; break; }
+    case 4: {
+      uint32_t w[4] = {in_u32[6 * i + 2], in_u32[6 * i + 3], in_u32[6 * i + 4], in_u32[6 * i + 5]};
+      philox4x32_10(w, Key{in_u32[6 * i], in_u32[6 * i + 1]});
+      for (int r = 0; r < 4; ++r) out_u32[4 * i + r] = w[r];
+      break;
+    }
+  }
+}
+
+hipError_t launch_debug_eval(int which, int64_t n, const double* in, const uint32_t* in_u32, double* out,
+                             double* out2, uint32_t* out_u32, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  debug_eval_kernel<<<dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st>>>(which, n, in, in_u32, out,
+                                                                                       out2, out_u32);
+  return hipGetLastError();
+}
+
+}  // namespace airpf

@@ -1,0 +1,181 @@
+"""GPU parity of the AIRPF forward pass against the CPU oracle (Algorithm 1).
+
+Every case runs the HIP library through its C ABI and the oracle on the same
+seeded inputs and compares:
+  * island log-weights after every weighting: bit-identical (the same
+    double-precision operation sequence on both sides);
+  * within-island ancestors, island source maps, interacting-stage counts and
+    the order-free digests: bit-identical (integer decisions);
+  * log Zhat: to 1e-12 relative (only the final log-sum-exp's summation
+    order differs);
+  * ENF values: to 1e-12 relative (tree vs sequential sums).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from paper_2312_06484_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2312_06484_amd import airpf
+    c = airpf.Context(0)
+    yield c
+    c.close()
+
+
+def make_case(orc, model, m, N, T, seed, dx=None):
+    if model == "lg1":
+        y = W.lg1_data(T)
+        return dict(kind=0, theta=np.array(W.LG1_THETA), y=y, dx=1, dy=1, consts=None), \
+            orc.Problem(orc.LG1, W.LG1_THETA, y, m, N, seed)
+    if model == "sv":
+        y = W.sv_data(T)
+        return dict(kind=1, theta=np.array(W.SV_THETA), y=y, dx=1, dy=1, consts=None), \
+            orc.Problem(orc.SV, W.SV_THETA, y, m, N, seed)
+    dy = 4 if dx == 8 else 2
+    A, H = W.lgd_model(dx=dx, dy=dy, rho=0.95)
+    y = W.lgd_data(A, H, T)
+    cst = W.lgd_consts(H)
+    return dict(kind=2, theta=A.reshape(-1), y=y, dx=dx, dy=dy, consts=cst), \
+        orc.Problem(orc.LGD, A.reshape(-1), y, m, N, seed, dx=dx, dy=dy, consts=cst)
+
+
+def run_both(ctx, orc, model, m, N, T, tau, f64, seed=1, dx=None):
+    from paper_2312_06484_amd import airpf
+    g, P = make_case(orc, model, m, N, T, seed, dx)
+    print("case", model, dx, m, N, T, tau, "f64" if f64 else "f32", flush=True)
+    gt = airpf.Trace(T, m, N)
+    st, lz = ctx.run(g["kind"], g["theta"], g["y"], m, N, seed, tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"],
+                     consts=g["consts"], trace=gt)
+    ot = orc.Trace(P)
+    lo = orc.run(P, tau=tau, store_f32=not f64, trace=ot)
+    return lz, gt, lo, ot, P
+
+
+def assert_parity(lz, gt, lo, ot, P):
+    T, m, N, S = P.T, P.m, P.N, ot.S
+    assert np.isfinite(lo)
+    assert abs(lz - lo) <= 1e-12 * max(1.0, abs(lo)), (lz, lo)
+    np.testing.assert_array_equal(gt.lpost, ot.lpost)
+    if T > 1:
+        np.testing.assert_array_equal(gt.anc, ot.anc[: (T - 1) * m * N])
+        np.testing.assert_array_equal(gt.pi, ot.pi[: (T - 1) * m])
+    np.testing.assert_array_equal(gt.sstar, ot.sstar)
+    np.testing.assert_array_equal(gt.digest[: 2 * (T - 1)], ot.digest[: 2 * (T - 1)])
+    ge = gt.enf.reshape(T, S + 1)[: T - 1, 1:]
+    oe = ot.enf.reshape(T, S + 1)[: T - 1, 1:]
+    np.testing.assert_allclose(ge, oe, rtol=1e-12, atol=0)
+
+
+CASES = [
+    # model, m, N, T, tau, f64, dx
+    ("lg1", 8, 32, 100, 0.3, True, None),      # 1-D linear-Gaussian, T=100, 8 x 32, FP64
+    ("lg1", 16, 37, 50, 0.7, False, None),     # ragged island size
+    ("lg1", 64, 256, 30, 2.0, False, None),    # always interact
+    ("lg1", 1, 100, 20, 0.3, False, None),     # one island = bootstrap filter
+    ("lg1", 4, 1, 10, 0.9, False, None),       # one particle per island
+    ("lg1", 256, 5, 20, 0.9, True, None),      # many tiny islands
+    ("lg1", 2, 3, 1, 0.3, False, None),        # a single observation
+    ("lg1", 1024, 256, 12, 0.0, False, None),  # independent filters at full width
+    ("lg1", 16384, 16, 6, 0.95, False, None),  # deep butterfly, multi-level upper tree
+    ("sv", 32, 128, 40, 0.3, False, None),
+    ("sv", 128, 512, 10, 0.5, False, None),    # two-wave island teams
+    ("sv", 8, 2048, 5, 2.0, True, None),       # largest island
+    ("sv", 4096, 128, 8, 0.6, False, None),    # stochastic volatility width
+    ("lgd", 16, 64, 20, 0.5, False, 8),        # 8-D linear-Gaussian
+    ("lgd", 4, 300, 8, 2.0, True, 8),
+    ("lgd", 8, 33, 10, 0.7, False, 3),
+    ("lgd", 8, 20, 10, 0.8, False, 2),
+    ("lgd", 4, 16, 10, 0.9, True, 4),
+]
+
+
+@pytest.mark.parametrize("model,m,N,T,tau,f64,dx", CASES)
+def test_forward_parity(ctx, orc, model, m, N, T, tau, f64, dx):
+    lz, gt, lo, ot, P = run_both(ctx, orc, model, m, N, T, tau, f64, dx=dx)
+    assert_parity(lz, gt, lo, ot, P)
+
+
+def test_lg1_width_of_the_benchmark_long_run(ctx, orc):
+    # the 1024 x 256 FP32 linear-Gaussian width over 300 observations: the
+    # launch configuration the benchmark times, checked on digests and log Zhat
+    lz, gt, lo, ot, P = run_both(ctx, orc, "lg1", 1024, 256, 300, 0.3, False)
+    assert_parity(lz, gt, lo, ot, P)
+
+
+def test_deterministic(ctx):
+    y = W.sv_data(30)
+    a = ctx.run(1, W.SV_THETA, y, 64, 64, 7)[1]
+    b = ctx.run(1, W.SV_THETA, y, 64, 64, 7)[1]
+    c = ctx.run(1, W.SV_THETA, y, 64, 64, 8)[1]
+    assert a == b and a != c
+
+
+def test_close_to_kalman(ctx):
+    from oracle import kalman
+    T = 1000
+    y = W.lg1_data(T)
+    lzk, _ = kalman.lg1(W.LG1_THETA, y, grad=False)
+    vals = [ctx.run(0, W.LG1_THETA, y, 1024, 256, s)[1] for s in range(1, 6)]
+    # 262144 particles over 1000 steps: standard deviation about 0.1
+    assert abs(np.mean(vals) - lzk) < 0.5, (vals, lzk)
+
+
+def test_math_bit_identical(ctx, orc):
+    g = np.random.default_rng(0)
+    xs = np.concatenate([g.uniform(-745, 709, 20000), g.uniform(-40, 0, 20000),
+                         [0.0, -0.0, -1e-300, 709.78, -745.0, -740.0, 1e-10, np.inf, -np.inf]])
+    ge = ctx.debug_eval(0, xs)
+    oe = np.array([orc.exp(v) for v in xs])
+    np.testing.assert_array_equal(ge.view(np.uint64), oe.view(np.uint64))
+    ls = np.concatenate([np.exp(g.uniform(-700, 700, 20000)), g.uniform(0.5, 2, 20000),
+                         g.integers(1, 2**51, 5000).astype(float), [5e-324, 1.0, 0.0, np.inf]])
+    gl = ctx.debug_eval(1, ls)
+    ol = np.array([orc.log(v) for v in ls])
+    np.testing.assert_array_equal(gl.view(np.uint64), ol.view(np.uint64))
+    vs = g.integers(0, 2**32, 20000) * 2.0**-32
+    gc, gs = ctx.debug_eval(2, vs)
+    oc = np.array([orc.cossin2pi(v) for v in vs])
+    np.testing.assert_array_equal(gc.view(np.uint64), oc[:, 0].copy().view(np.uint64))
+    np.testing.assert_array_equal(gs.view(np.uint64), oc[:, 1].copy().view(np.uint64))
+    words = g.integers(0, 2**32, 40000, dtype=np.uint64).astype(np.uint32)
+    z0, z1 = ctx.debug_eval(3, words=words)
+    ob = np.array([orc.boxmuller(int(words[2 * i]), int(words[2 * i + 1])) for i in range(words.size // 2)])
+    np.testing.assert_array_equal(z0.view(np.uint64), ob[:, 0].copy().view(np.uint64))
+    np.testing.assert_array_equal(z1.view(np.uint64), ob[:, 1].copy().view(np.uint64))
+    pw = g.integers(0, 2**32, 6 * 3000, dtype=np.uint64).astype(np.uint32)
+    gp = ctx.debug_eval(4, words=pw)
+    for i in range(3000):
+        k0, k1, c0, c1, c2, c3 = (int(v) for v in pw[6 * i:6 * i + 6])
+        assert tuple(int(v) for v in gp[i]) == orc.philox((c0, c1, c2, c3), (k0, k1))
+
+
+def test_invalid_arguments(ctx):
+    from paper_2312_06484_amd import airpf
+    y = W.lg1_data(10)
+    th = W.LG1_THETA
+    bad = [dict(m=3, N=4), dict(m=0, N=4), dict(m=4, N=0), dict(m=4, N=4096)]
+    for b in bad:
+        st, v = ctx.run(0, th, y, b["m"], b["N"], 1, raise_on_error=False)
+        assert st == airpf.E_INVALID_ARG and math.isnan(v)
+    st, v = ctx.run(0, th, np.array([0.0, np.nan]), 4, 4, 1, raise_on_error=False)
+    assert st == airpf.E_INVALID_ARG
+    st, v = ctx.run(0, [0.9, 1.0], y, 4, 4, 1, raise_on_error=False)      # wrong d_theta
+    assert st == airpf.E_INVALID_ARG
+    st, v = ctx.run(1, [-1.0, 1.0, 0.3], y, 4, 4, 1, raise_on_error=False)  # phi = 1
+    assert st == airpf.E_DOMAIN and v == -np.inf
+    st, v = ctx.run(0, [0.9, 1.0, -1.0], y, 4, 4, 1, raise_on_error=False)  # sy < 0
+    assert st == airpf.E_DOMAIN and v == -np.inf
+    st, v = ctx.run(2, np.eye(5).ravel(), y, 4, 4, 1, dx=5, dy=1, consts=np.ones(8), raise_on_error=False)
+    assert st == airpf.E_INVALID_ARG
+    # a valid call still works after the failures
+    st, v = ctx.run(0, th, y, 4, 4, 1)
+    assert st == airpf.OK and np.isfinite(v)
