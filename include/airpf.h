@@ -112,6 +112,11 @@ airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, const double* t
 
 const char* airpf_status_str(airpf_status s);
 
+/* Device time, in milliseconds, of the filter kernel of the last successful
+ * call on this context: HIP events recorded on the context's stream right
+ * before and after the persistent launch. */
+airpf_status airpf_ctx_last_kernel_ms(airpf_ctx* ctx, double* ms);
+
 /* Diagnostics used by the tests: evaluate the library's own device
  * implementations of exp, log, (cos, sin)(2 pi v), Box-Muller and Philox on
  * host arrays of length n (outputs host).  `which`: 0 exp, 1 log, 2 cossin

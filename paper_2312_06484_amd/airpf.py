@@ -25,7 +25,7 @@ OK, E_INVALID_ARG, E_DOMAIN, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(6)
 
 # every symbol include/airpf.h declares
 EXPORTS = ["airpf_ctx_create", "airpf_ctx_destroy", "airpf_run", "airpf_status_str",
-           "airpf_debug_eval"]
+           "airpf_ctx_last_kernel_ms", "airpf_debug_eval"]
 
 _dp = C.POINTER(C.c_double)
 _i32p = C.POINTER(C.c_int32)
@@ -75,6 +75,8 @@ def lib():
         L.airpf_run.argtypes = [C.c_void_p, C.POINTER(_Model), _dp, C.c_int32, C.c_void_p, C.c_int64,
                                 C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_Options), _dp,
                                 C.POINTER(_Trace)]
+        L.airpf_ctx_last_kernel_ms.restype = C.c_int
+        L.airpf_ctx_last_kernel_ms.argtypes = [C.c_void_p, _dp]
         L.airpf_debug_eval.restype = C.c_int
         L.airpf_debug_eval.argtypes = [C.c_void_p, C.c_int32, C.c_int64, _dp, _u32p, _dp, _dp, _u32p]
         _lib = L
@@ -169,6 +171,14 @@ class Context:
         if st != OK and raise_on_error:
             raise AirpfError(st, "airpf_run")
         return st, out.value
+
+    def last_kernel_ms(self):
+        """Event-timed device duration of the last call's filter kernel (ms)."""
+        v = C.c_double()
+        st = lib().airpf_ctx_last_kernel_ms(self._h, C.byref(v))
+        if st != OK:
+            raise AirpfError(st, "airpf_ctx_last_kernel_ms")
+        return v.value
 
     def debug_eval(self, which, values=None, words=None):
         """Evaluate the device's own exp (0), log (1), cossin 2 pi (2),

@@ -40,6 +40,8 @@ struct airpf_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   int num_cus = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  double last_kernel_ms = 0.0;
   DevBuf x1[2], tree[2], part[2], misc, ybuf;
   DevBuf t_sstar, t_enf, t_lpost, t_anc, t_pi, t_dig;
   DevBuf dbg_in, dbg_in32, dbg_out, dbg_out2, dbg_out32;
@@ -69,7 +71,8 @@ extern "C" airpf_status airpf_ctx_create(int device, void* hip_stream, airpf_ctx
   auto* c = new airpf_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  if (hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+  if (hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
     delete c;
     return AIRPF_E_DEVICE;
   }
@@ -85,6 +88,7 @@ extern "C" airpf_status airpf_ctx_destroy(airpf_ctx* c) {
                     &c->ybuf, &c->t_sstar, &c->t_enf, &c->t_lpost, &c->t_anc, &c->t_pi, &c->t_dig,
                     &c->dbg_in, &c->dbg_in32, &c->dbg_out, &c->dbg_out2, &c->dbg_out32})
     b->release();
+  for (hipEvent_t e : c->ev) if (e) (void)hipEventDestroy(e);
   delete c;
   return AIRPF_OK;
 }
@@ -204,11 +208,12 @@ extern "C" airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, cons
     a.tree[p] = static_cast<double*>(ctx->tree[p].p);
     a.part[p] = static_cast<double*>(ctx->part[p].p);
   }
-  ST_OK(ctx->misc.ensure(64));
+  // misc: [0,8) log Zhat, [8,12) status, [64, 64 + 4G) barrier flags
+  ST_OK(ctx->misc.ensure(64 + 4 * size_t(plan.G)));
   unsigned char* misc = static_cast<unsigned char*>(ctx->misc.p);
-  a.bar = reinterpret_cast<unsigned*>(misc);              // 2 words
-  a.status = reinterpret_cast<int*>(misc + 8);            // 1 word
-  a.out_logz = reinterpret_cast<double*>(misc + 16);      // 1 double
+  a.out_logz = reinterpret_cast<double*>(misc);
+  a.status = reinterpret_cast<int*>(misc + 8);
+  a.bar = reinterpret_cast<unsigned*>(misc + 64);
   if (y_dev) {
     a.y = y;
   } else {
@@ -216,7 +221,7 @@ extern "C" airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, cons
     HIP_OK(hipMemcpyAsync(ctx->ybuf.p, y, sizeof(double) * size_t(T) * dy, hipMemcpyHostToDevice, s));
     a.y = static_cast<const double*>(ctx->ybuf.p);
   }
-  HIP_OK(airpf::fill_u32(misc, 0u, 4, s));
+  HIP_OK(airpf::fill_u32(misc, 0u, 16 + int64_t(plan.G), s));
 
   if (trace) {
     if (trace->sstar) { ST_OK(ctx->t_sstar.ensure(4 * size_t(T))); a.tr_sstar = static_cast<int32_t*>(ctx->t_sstar.p);
@@ -231,7 +236,9 @@ extern "C" airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, cons
   }
 
   L.plan_only = 0;
+  HIP_OK(hipEventRecord(ctx->ev[0], s));
   if (airpf::launch_forward(L, a, &plan) != hipSuccess) return AIRPF_E_DEVICE;
+  HIP_OK(hipEventRecord(ctx->ev[1], s));
 
   double lz = 0.0;
   int kstatus = 0;
@@ -247,7 +254,16 @@ extern "C" airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, cons
   }
   HIP_OK(hipStreamSynchronize(s));
   if (kstatus != 0) return AIRPF_E_DEVICE;
+  float ms = 0.0f;
+  HIP_OK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+  ctx->last_kernel_ms = ms;
   *log_z_out = lz;
+  return AIRPF_OK;
+}
+
+extern "C" airpf_status airpf_ctx_last_kernel_ms(airpf_ctx* ctx, double* ms) {
+  if (!ctx || !ms) return AIRPF_E_INVALID_ARG;
+  *ms = ctx->last_kernel_ms;
   return AIRPF_OK;
 }
 

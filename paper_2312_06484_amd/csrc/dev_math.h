@@ -78,9 +78,26 @@ __device__ inline uint64_t bounded_u64(Key key, uint32_t c0, uint32_t island, ui
 
 // ---------------------------------------------------------------- exp / log
 
-__host__ __device__ constexpr double factorial(int n) { return n <= 1 ? 1.0 : n * factorial(n - 1); }
-__host__ __device__ constexpr double inv_factorial(int n) { return 1.0 / factorial(n); }
-__host__ __device__ constexpr double inv_odd(int i) { return 1.0 / (2 * i + 1); }
+// Polynomial coefficients, evaluated by the compiler: 1/k! for k = 0..20
+// (k! is exact in double for k <= 22, so each entry is 1/k! correctly
+// rounded) and 1/(2i+1) for i = 0..11.
+struct CoeffTables {
+  double inv_fact[21];
+  double inv_odd[12];
+};
+constexpr CoeffTables make_coeff_tables() {
+  CoeffTables t{};
+  double f = 1.0;
+  for (int k = 0; k <= 20; ++k) {
+    if (k > 0) f *= k;
+    t.inv_fact[k] = 1.0 / f;
+  }
+  for (int i = 0; i < 12; ++i) t.inv_odd[i] = 1.0 / (2 * i + 1);
+  return t;
+}
+constexpr CoeffTables kCoeff = make_coeff_tables();
+template <int K> struct InvFact { static constexpr double value = kCoeff.inv_fact[K]; };
+template <int I> struct InvOdd { static constexpr double value = kCoeff.inv_odd[I]; };
 
 constexpr double kLn2Head = 0x1.62e42fee00000p-1;   // ln 2, 32 significant bits
 constexpr double kLn2Tail = 0x1.a39ef35793c76p-33;  // ln 2 - head
@@ -98,9 +115,18 @@ __device__ inline double dexp(double x) {
   if (x < -0x1.74910d52d3051p+9) return 0.0;
   const double kd = rint(x * kInvLn2);
   const double r = fma(-kd, kLn2Tail, fma(-kd, kLn2Head, x));
-  double p = inv_factorial(13);
-#pragma unroll
-  for (int i = 12; i >= 2; --i) p = fma(p, r, inv_factorial(i));
+  double p = InvFact<13>::value;
+  p = fma(p, r, InvFact<12>::value);
+  p = fma(p, r, InvFact<11>::value);
+  p = fma(p, r, InvFact<10>::value);
+  p = fma(p, r, InvFact<9>::value);
+  p = fma(p, r, InvFact<8>::value);
+  p = fma(p, r, InvFact<7>::value);
+  p = fma(p, r, InvFact<6>::value);
+  p = fma(p, r, InvFact<5>::value);
+  p = fma(p, r, InvFact<4>::value);
+  p = fma(p, r, InvFact<3>::value);
+  p = fma(p, r, InvFact<2>::value);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
   const int k = static_cast<int>(kd);
@@ -121,9 +147,17 @@ __device__ inline double dlog(double x) {
   if (f > 0x1.6a09e667f3bcdp+0) { f = f * 0.5; e += 1; }
   const double s = (f - 1.0) / (f + 1.0);
   const double z = s * s;
-  double p = inv_odd(11);
-#pragma unroll
-  for (int i = 10; i >= 1; --i) p = fma(p, z, inv_odd(i));
+  double p = InvOdd<11>::value;
+  p = fma(p, z, InvOdd<10>::value);
+  p = fma(p, z, InvOdd<9>::value);
+  p = fma(p, z, InvOdd<8>::value);
+  p = fma(p, z, InvOdd<7>::value);
+  p = fma(p, z, InvOdd<6>::value);
+  p = fma(p, z, InvOdd<5>::value);
+  p = fma(p, z, InvOdd<4>::value);
+  p = fma(p, z, InvOdd<3>::value);
+  p = fma(p, z, InvOdd<2>::value);
+  p = fma(p, z, InvOdd<1>::value);
   p = fma(p, z, 1.0);
   double t = s * p;
   t = t + t;
@@ -135,13 +169,29 @@ __device__ inline void cossin_2pi(double v, double& c, double& s) {
   const double q = rint(v * 4.0);
   const double th = (v - q * 0.25) * kTwoPi;
   const double z = th * th;
-  double ps = -inv_factorial(19);
-#pragma unroll
-  for (int i = 8; i >= 0; --i) ps = fma(ps, z, (i & 1) ? -inv_factorial(2 * i + 1) : inv_factorial(2 * i + 1));
+  // sin th = th sum_i (-1)^i z^i / (2i+1)!,  cos th = sum_i (-1)^i z^i / (2i)!
+  double ps = -InvFact<19>::value;
+  ps = fma(ps, z, InvFact<17>::value);
+  ps = fma(ps, z, -InvFact<15>::value);
+  ps = fma(ps, z, InvFact<13>::value);
+  ps = fma(ps, z, -InvFact<11>::value);
+  ps = fma(ps, z, InvFact<9>::value);
+  ps = fma(ps, z, -InvFact<7>::value);
+  ps = fma(ps, z, InvFact<5>::value);
+  ps = fma(ps, z, -InvFact<3>::value);
+  ps = fma(ps, z, 1.0);
   const double sn = th * ps;
-  double pc = inv_factorial(20);
-#pragma unroll
-  for (int i = 9; i >= 0; --i) pc = fma(pc, z, (i & 1) ? -inv_factorial(2 * i) : inv_factorial(2 * i));
+  double pc = InvFact<20>::value;
+  pc = fma(pc, z, -InvFact<18>::value);
+  pc = fma(pc, z, InvFact<16>::value);
+  pc = fma(pc, z, -InvFact<14>::value);
+  pc = fma(pc, z, InvFact<12>::value);
+  pc = fma(pc, z, -InvFact<10>::value);
+  pc = fma(pc, z, InvFact<8>::value);
+  pc = fma(pc, z, -InvFact<6>::value);
+  pc = fma(pc, z, InvFact<4>::value);
+  pc = fma(pc, z, -InvFact<2>::value);
+  pc = fma(pc, z, 1.0);
   const int quad = static_cast<int>(q) & 3;
   const double a = (quad & 1) ? -sn : pc;   // cos(th + quad pi/2) for quad 0, 1
   const double b = (quad & 1) ? pc : sn;    // sin(th + quad pi/2) for quad 0, 1

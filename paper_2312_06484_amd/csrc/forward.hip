@@ -68,37 +68,47 @@ __device__ __forceinline__ double take_partner_prob(double lk, double lp) {
   return 1.0 / (1.0 + dexp(lk - lp));
 }
 
+// ------------------------------------------------------------ cross-block data
+// Everything one block writes for another (resampled blocks, the island tree,
+// the ENF partials, barrier flags) is written and read with device-scope
+// relaxed atomic accesses, which are coherent across the chip's per-XCD L2
+// caches by themselves.  No device-scope fence is ever issued: on this part
+// such a fence writes back or invalidates a whole L2, and an invalidated L2
+// costs every block its cached code and arguments.
+template <typename T>
+__device__ __forceinline__ void put(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+template <typename T>
+__device__ __forceinline__ T get(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ------------------------------------------------------------ grid barrier
-// Monotone arrival counter bar[0] and release word bar[1]; the last block of
-// epoch e publishes e.  Spinning is bounded: after ~2^24 polls (seconds) a
-// block gives up, raises status and every block leaves its step loop.
-__device__ bool grid_barrier(unsigned* bar, unsigned G, unsigned& epoch, int* status) {
-  __shared__ int s_ok;
-  __threadfence();
+// Flag-array barrier: block b publishes the epoch it has reached in flags[b]
+// (its own word, so no two blocks ever update one address), and every block
+// polls all G flags, lane t watching flags t, t + 256, ...  Before a block
+// publishes, every lane waits until all of its memory operations have
+// completed (s_waitcnt 0), so the block's device-scope stores are visible
+// to any device-scope load issued after the flag is seen.  Spinning is
+// bounded: after ~2^24 polls a block raises status and leaves.
+__device__ bool grid_barrier(unsigned* flags, int G, unsigned& epoch, int* status) {
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    ++epoch;
-    int ok = 1;
-    const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == epoch * G - 1) {
-      __hip_atomic_store(&bar[1], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if ((++spins & 1023u) == 0 &&
-            (spins > (1u << 24) || __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
-          ok = 0;
-          __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
+  ++epoch;
+  if (threadIdx.x == 0) put(&flags[blockIdx.x], epoch);
+  int ok = 1;
+  for (int i = threadIdx.x; i < G && ok; i += kBlock) {
+    unsigned spins = 0;
+    while (get(&flags[i]) < epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 1023u) == 0 && (spins > (1u << 24) || get(status) != 0)) {
+        put(status, 1);
+        ok = 0;
+        break;
       }
     }
-    s_ok = ok;
   }
-  __syncthreads();
-  __threadfence();
-  return s_ok != 0;
+  ok = __syncthreads_and(ok);
+  return ok != 0;
 }
 
 // ------------------------------------------------------------ team / block reductions
@@ -192,14 +202,15 @@ __device__ double block_sum(double v, double* red) {
   return r;
 }
 
-// log sum_i exp(scale * v[i]) over n values (global or LDS), whole block
-__device__ double block_lse(const double* v, int n, double scale, double* red) {
+// log sum_i exp(scale * v[i]) over n values, whole block; `shared` says
+// whether v lives in another block's published memory (device-scope reads)
+__device__ double block_lse(const double* v, int n, double scale, double* red, bool shared) {
   double mx = ninf();
-  for (int i = threadIdx.x; i < n; i += kBlock) mx = fmax(mx, scale * v[i]);
+  for (int i = threadIdx.x; i < n; i += kBlock) mx = fmax(mx, scale * (shared ? get(v + i) : v[i]));
   mx = block_max(mx, red);
   if (mx == ninf()) return mx;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) s += dexp(scale * v[i] - mx);
+  for (int i = threadIdx.x; i < n; i += kBlock) s += dexp(scale * (shared ? get(v + i) : v[i]) - mx);
   s = block_sum(s, red);
   return mx + dlog(s);
 }
@@ -236,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
   const double log_c = dlog(static_cast<double>(c));
 
   auto lt_value = [&](int par, int level, int idx) -> double {   // tree value, level >= 1
-    if (level <= lc + 1) return a.tree[par][tree_off(m, level) + idx];
+    if (level <= lc + 1) return get(a.tree[par] + tree_off(m, level) + idx);
     const int u = level - (lc + 1);
     return up[2 * G - ((2 * G) >> u) + idx];
   };
@@ -246,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
     if (n > 0) {
       if (!grid_barrier(a.bar, G, epoch, a.status)) return;
       // ---- cascade of step n-1 (every block, identical) ----
-      for (int b = tid; b < G; b += kBlock) up[b] = a.tree[ppar][tree_off(m, lc + 1) + b];
+      for (int b = tid; b < G; b += kBlock) up[b] = get(a.tree[ppar] + tree_off(m, lc + 1) + b);
       __syncthreads();
       for (int u = 1; lc + 1 + u <= S + 1; ++u) {
         const int cnt = G >> u;
@@ -254,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
         for (int i = tid; i < cnt; i += kBlock) up[o + i] = pair_mean(up[o_prev + 2 * i], up[o_prev + 2 * i + 1]);
         __syncthreads();
       }
-      const double lsum = block_lse(up, G, 1.0, red_d) + log_c;      // log sum_k W_k
+      const double lsum = block_lse(up, G, 1.0, red_d, false) + log_c;   // log sum_k W_k
       if (lsum == ninf()) {                                          // every island dead
         if (blockIdx.x == 0 && tid == 0) *a.out_logz = ninf();
         return;
@@ -267,8 +278,8 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
         // every weight unchanged, so every later stage sees the same ENF and
         // does not interact either (traced as that same value)
         for (int s = 1; s <= S; ++s) {
-          const double l2 = (s <= lc + 1) ? block_lse(a.part[ppar] + (int64_t)(s - 1) * G, G, 1.0, red_d)
-                                          : block_lse(up + 2 * G - ((2 * G) >> (s - lc - 1)), m >> (s - 1), 2.0, red_d);
+          const double l2 = (s <= lc + 1) ? block_lse(a.part[ppar] + (int64_t)(s - 1) * G, G, 1.0, red_d, true)
+                                          : block_lse(up + 2 * G - ((2 * G) >> (s - lc - 1)), m >> (s - 1), 2.0, red_d, false);
           const double enf = dexp(2.0 * lsum - log_m - l2 - (s - 1) * kLn2);
           const bool go = enf < a.tau;
           if (a.tr_enf && blockIdx.x == 0 && tid == 0)
@@ -329,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
           const int j = j0 + r;
           double xp[DX];
 #pragma unroll
-          for (int d = 0; d < DX; ++d) xp[d] = (j < N) ? static_cast<double>(xin[j * DX + d]) : 0.0;
+          for (int d = 0; d < DX; ++d) xp[d] = (j < N) ? static_cast<double>(get(xin + j * DX + d)) : 0.0;
           Model::template prop<Store>(a.mp, xp, z + r * DX, x[r]);
         }
       }
@@ -395,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
               anc = lo;
             }
 #pragma unroll
-            for (int d = 0; d < DX; ++d) xo[j * DX + d] = sxt[anc * DX + d];
+            for (int d = 0; d < DX; ++d) put(xo + j * DX + d, sxt[anc * DX + d]);
             if (a.tr_anc) a.tr_anc[(n * m + k) * static_cast<int64_t>(N) + j] = anc;
             if (a.tr_digest) dig += digest_term(n, k, j, anc);
           }
@@ -420,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
       const int cnt = c >> (l - 1);
       const int o = 2 * c - ((2 * c) >> (l - 1));
       double* dst = a.tree[par] + tree_off(m, l) + (kbase >> (l - 1));
-      for (int i = tid; i < cnt; i += kBlock) dst[i] = lv[o + i];
+      for (int i = tid; i < cnt; i += kBlock) put(dst + i, lv[o + i]);
     }
     if (tid <= lc) {
       const int l = tid + 1;
@@ -434,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
         for (int i = 0; i < cnt; ++i) s += dexp(2.0 * lv[o + i] - mx2);
         v = mx2 + dlog(s);
       }
-      a.part[par][static_cast<int64_t>(l - 1) * G + blockIdx.x] = v;
+      put(a.part[par] + static_cast<int64_t>(l - 1) * G + blockIdx.x, v);
     }
   }
 
@@ -442,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
   if (!grid_barrier(a.bar, G, epoch, a.status)) return;
   if (blockIdx.x == 0) {
     const int par = static_cast<int>((a.T - 1) & 1);
-    const double lsum = block_lse(a.tree[par] + tree_off(m, lc + 1), G, 1.0, red_d) + log_c;
+    const double lsum = block_lse(a.tree[par] + tree_off(m, lc + 1), G, 1.0, red_d, true) + log_c;
     if (tid == 0) {
       *a.out_logz = lsum - log_m;
       if (a.tr_sstar) a.tr_sstar[a.T - 1] = 0;

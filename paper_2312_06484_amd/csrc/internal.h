@@ -19,7 +19,7 @@ struct FwdArgs {
   void* x1[2];                // Store*, resampled blocks, [m*N*DX] particle-major
   double* tree[2];            // [2m] pair-mean tree of island log-weights
   double* part[2];            // [(lc+1)*G] per-block log sum exp(2 LT) per level
-  unsigned* bar;              // [2] grid barrier
+  unsigned* bar;              // [G] grid-barrier flags, zero before the launch
   int* status;                // [1] 0 ok, 1 barrier timed out
   double* out_logz;           // [1]
   int32_t* tr_sstar;
