@@ -29,6 +29,22 @@ HBM_PEAK_GBS = 8000.0
 FWD_BYTES_PER_PARTICLE_STEP = {(1, "f32"): 8, (1, "f64"): 16, (8, "f32"): 64, (8, "f64"): 128}
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed counter record, or None when the
+    kernel sources changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in ["forward.hip", "dev_math.h", "dev_models.h", "internal.h"]:
+        h.update(open(os.path.join(ROOT, "paper_2312_06484_amd", "csrc", f), "rb").read())
+    for key, rec in json.load(open(path)).items():
+        if key.endswith(" " + workload) and rec.get("kernel_sources_sha256") == h.hexdigest():
+            return rec["traffic_bytes_per_launch"]
+    return None
+
+
 def workload_inputs(name):
     from paper_2312_06484_amd import workloads as W
     wl = dict(W.WORKLOADS[name])
@@ -77,6 +93,9 @@ def main():
     ap.add_argument("--tau", type=float, default=0.3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times (the "
+                         "reference reading for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the filter of one parameter value is one "
@@ -86,6 +105,16 @@ def main():
 
     import torch                                     # device memory and the stream
     from paper_2312_06484_amd import airpf
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": 4 * n, "copies": 5}))
+        return
 
     wl, y = workload_inputs(args.workload)
     wl["name"] = args.workload
@@ -147,7 +176,7 @@ def main():
                    "state_storage": "f32" if wl["f32"] else "f64", "mode": "forward",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "kernel": "forward_kernel", "kernel_ms": avg_k,
                      "bytes_per_particle_step": bpp},
         "logz_err": err,

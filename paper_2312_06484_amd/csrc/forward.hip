@@ -239,7 +239,8 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
 
   Store* sx = reinterpret_cast<Store*>(smem);                                    // [kBlock*NZ]
   uint64_t* sC = reinterpret_cast<uint64_t*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));
-  double* lv = reinterpret_cast<double*>(sC + kBlock * PPT);                      // [2c]
+  int* sA = reinterpret_cast<int*>(sC + kBlock * PPT);                             // [kBlock*PPT]
+  double* lv = reinterpret_cast<double*>(sA + kBlock * PPT);                       // [2c]
   double* up = lv + 2 * c;                                                        // [2G]
 
   unsigned epoch = 0;
@@ -390,7 +391,9 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
         U = team_bcast(U, TP, bc_u);
         __syncthreads();
         Store* xo = static_cast<Store*>(a.x1[par]) + (static_cast<int64_t>(k) * N) * DX;
+        int* sAt = sA + team * TP * PPT;
         unsigned long long dig = 0;
+        // ancestors of this lane's slots: min{i : N C_i > U + j Q}
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           const int j = j0 + r;
@@ -405,8 +408,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
               }
               anc = lo;
             }
-#pragma unroll
-            for (int d = 0; d < DX; ++d) put(xo + j * DX + d, sxt[anc * DX + d]);
+            sAt[j] = anc;
             if (a.tr_anc) a.tr_anc[(n * m + k) * static_cast<int64_t>(N) + j] = anc;
             if (a.tr_digest) dig += digest_term(n, k, j, anc);
           }
@@ -414,6 +416,17 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
         if (a.tr_digest) {
           dig = team_sum_u64(dig, TP, red_u);
           if (lane == 0 && active) atomicAdd(&a.tr_digest[2 * n], dig);
+        }
+        __syncthreads();
+        // the resampled block, written word by word with consecutive lanes on
+        // consecutive words so every store instruction covers whole lines
+        if (active) {
+#pragma unroll
+          for (int r = 0; r < NZ; ++r) {
+            const int w = r * TP + lane;
+            const int j = w / DX, d = w - j * DX;
+            if (j < N) put(xo + w, sxt[sAt[j] * DX + d]);
+          }
         }
         __syncthreads();
       }
@@ -472,7 +485,7 @@ static int ilog2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
 
 static size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) {
   const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
-  return sx + 8 * size_t(kBlock) * ppt + 8 * 2 * size_t(c) + 8 * 2 * size_t(G);
+  return sx + 8 * size_t(kBlock) * ppt + 4 * size_t(kBlock) * ppt + 8 * 2 * size_t(c) + 8 * 2 * size_t(G);
 }
 
 template <class Model, typename Store, int PPT>
