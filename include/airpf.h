@@ -110,6 +110,24 @@ airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, const double* t
                        uint64_t seed, const airpf_options* opt, double* log_z_out,
                        airpf_trace* trace);
 
+/* Score: *log_z_out = log Zhat(theta) (the same value airpf_run returns for
+ * the same arguments) and grad_out[d_theta] = the path-space estimate of
+ * d log Z / d theta: the final-weight average over final particles of the
+ * derivative of the summed log g along each particle's ancestral path, with
+ * the noise and every discrete decision of the run held fixed and the
+ * fixed-point weights read as exact (the derivative is not part of the
+ * paper; it is the score a gradient-based PMCMC proposal consumes).
+ * opt->ckpt_every = K: the forward pass keeps a checkpoint every K steps and
+ * the reverse pass recomputes the particle history one segment of K steps at
+ * a time (K = 0: the whole history is kept when it fits the workspace
+ * budget, otherwise K = ceil(sqrt(T))).  Supported: N <= 1024 (LG1, SV),
+ * N <= 512 (LGD); opt->score_mode AIRPF_PATHWISE returns
+ * AIRPF_E_UNSUPPORTED in this build.  grad_out is host memory. */
+airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, const double* theta,
+                         int32_t d_theta, const double* y, int64_t T, int32_t m, int32_t N,
+                         uint64_t seed, const airpf_options* opt, double* log_z_out,
+                         double* grad_out, airpf_trace* trace);
+
 const char* airpf_status_str(airpf_status s);
 
 /* Device time, in milliseconds, of the filter kernel of the last successful

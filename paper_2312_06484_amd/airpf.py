@@ -24,7 +24,7 @@ FLAG_Y_ON_DEVICE = 1
 OK, E_INVALID_ARG, E_DOMAIN, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(6)
 
 # every symbol include/airpf.h declares
-EXPORTS = ["airpf_ctx_create", "airpf_ctx_destroy", "airpf_run", "airpf_status_str",
+EXPORTS = ["airpf_ctx_create", "airpf_ctx_destroy", "airpf_run", "airpf_score", "airpf_status_str",
            "airpf_ctx_last_kernel_ms", "airpf_debug_eval"]
 
 _dp = C.POINTER(C.c_double)
@@ -75,6 +75,10 @@ def lib():
         L.airpf_run.argtypes = [C.c_void_p, C.POINTER(_Model), _dp, C.c_int32, C.c_void_p, C.c_int64,
                                 C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_Options), _dp,
                                 C.POINTER(_Trace)]
+        L.airpf_score.restype = C.c_int
+        L.airpf_score.argtypes = [C.c_void_p, C.POINTER(_Model), _dp, C.c_int32, C.c_void_p, C.c_int64,
+                                  C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_Options), _dp, _dp,
+                                  C.POINTER(_Trace)]
         L.airpf_ctx_last_kernel_ms.restype = C.c_int
         L.airpf_ctx_last_kernel_ms.argtypes = [C.c_void_p, _dp]
         L.airpf_debug_eval.restype = C.c_int
@@ -142,10 +146,8 @@ class Context:
 
     # ------------------------------------------------------------------ calls
 
-    def run(self, kind, theta, y, m, N, seed, tau=0.3, fp64=False, dx=1, dy=1, consts=None,
-            trace=None, y_device_ptr=None, T=None, raise_on_error=True):
-        """airpf_run: returns (status, log Zhat).  ``y`` is a host array, or
-        pass ``y_device_ptr`` (int) and ``T`` for observations already in HBM."""
+    @staticmethod
+    def _args(kind, theta, y, tau, fp64, dx, dy, consts, y_device_ptr, T, score_mode=PATHSPACE, ckpt_every=0):
         theta = np.ascontiguousarray(theta, dtype=np.float64)
         model = _Model()
         model.kind, model.dx, model.dy = int(kind), int(dx), int(dy)
@@ -154,15 +156,24 @@ class Context:
         model.n_consts = 0 if cst is None else cst.size
         opt = _Options()
         opt.tau, opt.resampling, opt.precision = float(tau), SYSTEMATIC, FP64 if fp64 else FP32
-        opt.score_mode, opt.ckpt_every, opt.flags = PATHSPACE, 0, 0
+        opt.score_mode, opt.ckpt_every, opt.flags = int(score_mode), int(ckpt_every), 0
         if y_device_ptr is not None:
             ptr = C.c_void_p(int(y_device_ptr))
             opt.flags |= FLAG_Y_ON_DEVICE
             Tn = int(T)
+            yy = None
         else:
             yy = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
             ptr = yy.ctypes.data_as(C.c_void_p)
             Tn = yy.size // int(dy)
+        return theta, model, cst, opt, ptr, Tn, yy
+
+    def run(self, kind, theta, y, m, N, seed, tau=0.3, fp64=False, dx=1, dy=1, consts=None,
+            trace=None, y_device_ptr=None, T=None, raise_on_error=True):
+        """airpf_run: returns (status, log Zhat).  ``y`` is a host array, or
+        pass ``y_device_ptr`` (int) and ``T`` for observations already in HBM."""
+        theta, model, cst, opt, ptr, Tn, keep = self._args(kind, theta, y, tau, fp64, dx, dy, consts,
+                                                           y_device_ptr, T)
         out = C.c_double(np.nan)
         tr = trace._c() if trace is not None else None
         st = lib().airpf_run(self._h, C.byref(model), _p(theta, _dp), theta.size, ptr, Tn, int(m), int(N),
@@ -171,6 +182,21 @@ class Context:
         if st != OK and raise_on_error:
             raise AirpfError(st, "airpf_run")
         return st, out.value
+
+    def score(self, kind, theta, y, m, N, seed, tau=0.3, fp64=False, dx=1, dy=1, consts=None,
+              ckpt_every=0, score_mode=PATHSPACE, trace=None, y_device_ptr=None, T=None, raise_on_error=True):
+        """airpf_score: returns (status, log Zhat, gradient)."""
+        theta, model, cst, opt, ptr, Tn, keep = self._args(kind, theta, y, tau, fp64, dx, dy, consts,
+                                                           y_device_ptr, T, score_mode, ckpt_every)
+        out = C.c_double(np.nan)
+        grad = np.full(theta.size, np.nan)
+        tr = trace._c() if trace is not None else None
+        st = lib().airpf_score(self._h, C.byref(model), _p(theta, _dp), theta.size, ptr, Tn, int(m), int(N),
+                               C.c_uint64(int(seed)), C.byref(opt), C.byref(out), _p(grad, _dp),
+                               C.byref(tr) if tr is not None else None)
+        if st != OK and raise_on_error:
+            raise AirpfError(st, "airpf_score")
+        return st, out.value, grad
 
     def last_kernel_ms(self):
         """Event-timed device duration of the last call's filter kernel (ms)."""

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libairpf.so")
-SOURCES = ["forward.hip", "capi.hip"]
+SOURCES = ["forward.hip", "score.hip", "capi.hip"]
 ARCH = "gfx950"
 
 

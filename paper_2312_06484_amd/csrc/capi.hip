@@ -44,6 +44,7 @@ struct airpf_ctx {
   double last_kernel_ms = 0.0;
   DevBuf x1[2], tree[2], part[2], misc, ybuf;
   DevBuf t_sstar, t_enf, t_lpost, t_anc, t_pi, t_dig;
+  DevBuf s_pi, s_sstar, s_lpre, s_ckx, s_ckL, s_recx, s_reca, s_lam[2], s_del[2], s_grad;
   DevBuf dbg_in, dbg_in32, dbg_out, dbg_out2, dbg_out32;
 };
 
@@ -86,7 +87,9 @@ extern "C" airpf_status airpf_ctx_destroy(airpf_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
   for (DevBuf* b : {&c->x1[0], &c->x1[1], &c->tree[0], &c->tree[1], &c->part[0], &c->part[1], &c->misc,
                     &c->ybuf, &c->t_sstar, &c->t_enf, &c->t_lpost, &c->t_anc, &c->t_pi, &c->t_dig,
-                    &c->dbg_in, &c->dbg_in32, &c->dbg_out, &c->dbg_out2, &c->dbg_out32})
+                    &c->dbg_in, &c->dbg_in32, &c->dbg_out, &c->dbg_out2, &c->dbg_out32, &c->s_pi,
+                    &c->s_sstar, &c->s_lpre, &c->s_ckx, &c->s_ckL, &c->s_recx, &c->s_reca, &c->s_lam[0],
+                    &c->s_lam[1], &c->s_del[0], &c->s_del[1], &c->s_grad})
     b->release();
   for (hipEvent_t e : c->ev) if (e) (void)hipEventDestroy(e);
   delete c;
@@ -119,6 +122,11 @@ airpf_status prepare_model(const airpf_model* model, const double* theta, int32_
       if (!all_finite(theta, 3)) return AIRPF_E_INVALID_ARG;
       if (!(std::fabs(theta[1]) < 1.0) || !(theta[2] > 0.0)) return AIRPF_E_DOMAIN;
       mp->s0 = theta[2] / std::sqrt(1.0 - theta[1] * theta[1]);
+      {
+        const double om = 1.0 - theta[1] * theta[1];
+        mp->ds0_dphi = theta[2] * theta[1] / (om * std::sqrt(om));
+        mp->ds0_dsig = 1.0 / std::sqrt(om);
+      }
       c_log = -0.5 * LOG2PI;
       break;
     }
@@ -163,53 +171,64 @@ void set_nan(double* p) { if (p) *p = std::nan(""); }
 
 }  // namespace
 
-extern "C" airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, const double* theta, int32_t d_theta,
-                                  const double* y, int64_t T, int32_t m, int32_t N, uint64_t seed,
-                                  const airpf_options* opt_in, double* log_z_out, airpf_trace* trace) {
+namespace {
+
+// Everything airpf_run and airpf_score share: validation, model constants,
+// the launch plan and the forward kernel's workspaces.
+struct Prepared {
+  airpf::FwdArgs a;
+  airpf::FwdLaunch L;
+  airpf::FwdPlan plan;
+  airpf_options opt;
+  int dx = 1, dy = 1, S = 0;
+};
+
+airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* theta, int32_t d_theta,
+                     const double* y, int64_t T, int32_t m, int32_t N, uint64_t seed,
+                     const airpf_options* opt_in, double* log_z_out, int max_blocks, Prepared* P) {
   set_nan(log_z_out);
   if (!ctx || !model || !theta || !y || !log_z_out) return AIRPF_E_INVALID_ARG;
   if (T < 1 || T > (int64_t(1) << 30) || !is_pow2(m) || m > (1 << 24) || N < 1 || N > 2048)
     return AIRPF_E_INVALID_ARG;
-  const airpf_options opt = opt_in ? *opt_in : default_options();
+  P->opt = opt_in ? *opt_in : default_options();
+  const airpf_options& opt = P->opt;
   if (!(opt.tau == opt.tau)) return AIRPF_E_INVALID_ARG;
   if (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) return AIRPF_E_INVALID_ARG;
   if (opt.resampling != AIRPF_SYSTEMATIC) return AIRPF_E_UNSUPPORTED;
 
-  airpf::FwdArgs a;
+  airpf::FwdArgs& a = P->a;
   std::memset(&a, 0, sizeof(a));
-  int dx = 1, dy = 1;
-  const airpf_status st = prepare_model(model, theta, d_theta, N, &a.mp, &a.cst_q, &dx, &dy);
+  const airpf_status st = prepare_model(model, theta, d_theta, N, &a.mp, &a.cst_q, &P->dx, &P->dy);
   if (st == AIRPF_E_DOMAIN) { *log_z_out = -INFINITY; return st; }
   if (st != AIRPF_OK) return st;
   const bool y_dev = (opt.flags & AIRPF_FLAG_Y_ON_DEVICE) != 0;
-  if (!y_dev && !all_finite(y, T * dy)) return AIRPF_E_INVALID_ARG;
+  if (!y_dev && !all_finite(y, T * P->dy)) return AIRPF_E_INVALID_ARG;
 
   HIP_OK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
-  const int S = ilog2(m);
-  const bool want_enf = trace && trace->enf;
-  a.T = T; a.m = m; a.N = N; a.S = S; a.dy = dy; a.seed = seed; a.tau = opt.tau;
-  a.shortcut_all = (opt.tau > 1.0 + 1e-9) && !want_enf;
+  P->S = ilog2(m);
+  a.T = T; a.m = m; a.N = N; a.S = P->S; a.dy = P->dy; a.seed = seed; a.tau = opt.tau;
+  a.n0 = 0; a.n1 = T;
+  a.shortcut_all = opt.tau > 1.0 + 1e-9;
 
-  airpf::FwdLaunch L;
-  L.kind = model->kind; L.dx = dx; L.fp64 = opt.precision == AIRPF_FP64;
-  L.num_cus = ctx->num_cus; L.max_blocks = 1024; L.plan_only = 1; L.stream = s;
-  airpf::FwdPlan plan;
-  HIP_OK(airpf::launch_forward(L, a, &plan));
+  airpf::FwdLaunch& L = P->L;
+  L.kind = model->kind; L.dx = P->dx; L.fp64 = opt.precision == AIRPF_FP64;
+  L.num_cus = ctx->num_cus; L.max_blocks = max_blocks; L.plan_only = 1; L.stream = s;
+  HIP_OK(airpf::launch_forward(L, a, &P->plan));
 
   const size_t store = L.fp64 ? 8 : 4;
-  const size_t nstate = size_t(m) * N * dx * store;
-  const int lc = ilog2(plan.c);
+  const size_t nstate = size_t(m) * N * P->dx * store;
+  const int lc = ilog2(P->plan.c);
   for (int p = 0; p < 2; ++p) {
     ST_OK(ctx->x1[p].ensure(nstate));
     ST_OK(ctx->tree[p].ensure(sizeof(double) * 2 * size_t(m)));
-    ST_OK(ctx->part[p].ensure(sizeof(double) * size_t(lc + 1) * plan.G));
+    ST_OK(ctx->part[p].ensure(sizeof(double) * size_t(lc + 1) * P->plan.G));
     a.x1[p] = ctx->x1[p].p;
     a.tree[p] = static_cast<double*>(ctx->tree[p].p);
     a.part[p] = static_cast<double*>(ctx->part[p].p);
   }
   // misc: [0,8) log Zhat, [8,12) status, [64, 64 + 4G) barrier flags
-  ST_OK(ctx->misc.ensure(64 + 4 * size_t(plan.G)));
+  ST_OK(ctx->misc.ensure(64 + 4 * size_t(P->plan.G)));
   unsigned char* misc = static_cast<unsigned char*>(ctx->misc.p);
   a.out_logz = reinterpret_cast<double*>(misc);
   a.status = reinterpret_cast<int*>(misc + 8);
@@ -217,47 +236,219 @@ extern "C" airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, cons
   if (y_dev) {
     a.y = y;
   } else {
-    ST_OK(ctx->ybuf.ensure(sizeof(double) * size_t(T) * dy));
-    HIP_OK(hipMemcpyAsync(ctx->ybuf.p, y, sizeof(double) * size_t(T) * dy, hipMemcpyHostToDevice, s));
+    ST_OK(ctx->ybuf.ensure(sizeof(double) * size_t(T) * P->dy));
+    HIP_OK(hipMemcpyAsync(ctx->ybuf.p, y, sizeof(double) * size_t(T) * P->dy, hipMemcpyHostToDevice, s));
     a.y = static_cast<const double*>(ctx->ybuf.p);
   }
-  HIP_OK(airpf::fill_u32(misc, 0u, 16 + int64_t(plan.G), s));
+  HIP_OK(airpf::fill_u32(misc, 0u, 16 + int64_t(P->plan.G), s));
+  return AIRPF_OK;
+}
 
-  if (trace) {
-    if (trace->sstar) { ST_OK(ctx->t_sstar.ensure(4 * size_t(T))); a.tr_sstar = static_cast<int32_t*>(ctx->t_sstar.p);
-                        HIP_OK(airpf::fill_u32(a.tr_sstar, 0u, T, s)); }
-    if (trace->enf) { ST_OK(ctx->t_enf.ensure(8 * size_t(T) * (S + 1))); a.tr_enf = static_cast<double*>(ctx->t_enf.p);
-                      HIP_OK(airpf::fill_u32(a.tr_enf, 0x7ff80000u, 2 * int64_t(T) * (S + 1), s)); }
-    if (trace->lpost) { ST_OK(ctx->t_lpost.ensure(8 * size_t(T) * m)); a.tr_lpost = static_cast<double*>(ctx->t_lpost.p); }
-    if (trace->anc && T > 1) { ST_OK(ctx->t_anc.ensure(4 * size_t(T - 1) * m * N)); a.tr_anc = static_cast<int32_t*>(ctx->t_anc.p); }
-    if (trace->pi && T > 1) { ST_OK(ctx->t_pi.ensure(4 * size_t(T - 1) * m)); a.tr_pi = static_cast<int32_t*>(ctx->t_pi.p); }
-    if (trace->digest) { ST_OK(ctx->t_dig.ensure(16 * size_t(T))); a.tr_digest = static_cast<unsigned long long*>(ctx->t_dig.p);
-                         HIP_OK(airpf::fill_u32(a.tr_digest, 0u, 4 * int64_t(T), s)); }
-  }
+// zero the barrier flags before a cooperative launch
+airpf_status reset_flags(airpf_ctx* ctx, const Prepared& P) {
+  HIP_OK(airpf::fill_u32(P.a.bar, 0u, P.plan.G, ctx->stream));
+  return AIRPF_OK;
+}
 
-  L.plan_only = 0;
-  HIP_OK(hipEventRecord(ctx->ev[0], s));
-  if (airpf::launch_forward(L, a, &plan) != hipSuccess) return AIRPF_E_DEVICE;
-  HIP_OK(hipEventRecord(ctx->ev[1], s));
+airpf_status attach_trace(airpf_ctx* ctx, Prepared& P, airpf_trace* trace) {
+  airpf::FwdArgs& a = P.a;
+  if (!trace) return AIRPF_OK;
+  const int64_t T = a.T;
+  const int m = a.m, N = a.N, S = P.S;
+  hipStream_t s = ctx->stream;
+  if (trace->enf) a.shortcut_all = 0;
+  if (trace->sstar) { ST_OK(ctx->t_sstar.ensure(4 * size_t(T))); a.tr_sstar = static_cast<int32_t*>(ctx->t_sstar.p);
+                      HIP_OK(airpf::fill_u32(a.tr_sstar, 0u, T, s)); }
+  if (trace->enf) { ST_OK(ctx->t_enf.ensure(8 * size_t(T) * (S + 1))); a.tr_enf = static_cast<double*>(ctx->t_enf.p);
+                    HIP_OK(airpf::fill_u32(a.tr_enf, 0x7ff80000u, 2 * int64_t(T) * (S + 1), s)); }
+  if (trace->lpost) { ST_OK(ctx->t_lpost.ensure(8 * size_t(T) * m)); a.tr_lpost = static_cast<double*>(ctx->t_lpost.p); }
+  if (trace->anc && T > 1) { ST_OK(ctx->t_anc.ensure(4 * size_t(T - 1) * m * N)); a.tr_anc = static_cast<int32_t*>(ctx->t_anc.p); }
+  if (trace->pi && T > 1) { ST_OK(ctx->t_pi.ensure(4 * size_t(T - 1) * m)); a.tr_pi = static_cast<int32_t*>(ctx->t_pi.p); }
+  if (trace->digest) { ST_OK(ctx->t_dig.ensure(16 * size_t(T))); a.tr_digest = static_cast<unsigned long long*>(ctx->t_dig.p);
+                       HIP_OK(airpf::fill_u32(a.tr_digest, 0u, 4 * int64_t(T), s)); }
+  return AIRPF_OK;
+}
 
+airpf_status copy_trace(airpf_ctx* ctx, const Prepared& P, airpf_trace* trace) {
+  if (!trace) return AIRPF_OK;
+  const airpf::FwdArgs& a = P.a;
+  const int64_t T = a.T;
+  const int m = a.m, N = a.N, S = P.S;
+  hipStream_t s = ctx->stream;
+  if (trace->sstar && a.tr_sstar) HIP_OK(hipMemcpyAsync(trace->sstar, a.tr_sstar, 4 * size_t(T), hipMemcpyDeviceToHost, s));
+  if (trace->enf && a.tr_enf) HIP_OK(hipMemcpyAsync(trace->enf, a.tr_enf, 8 * size_t(T) * (S + 1), hipMemcpyDeviceToHost, s));
+  if (trace->lpost && a.tr_lpost) HIP_OK(hipMemcpyAsync(trace->lpost, a.tr_lpost, 8 * size_t(T) * m, hipMemcpyDeviceToHost, s));
+  if (trace->anc && a.tr_anc) HIP_OK(hipMemcpyAsync(trace->anc, a.tr_anc, 4 * size_t(T - 1) * m * N, hipMemcpyDeviceToHost, s));
+  if (trace->pi && a.tr_pi) HIP_OK(hipMemcpyAsync(trace->pi, a.tr_pi, 4 * size_t(T - 1) * m, hipMemcpyDeviceToHost, s));
+  if (trace->digest && a.tr_digest) HIP_OK(hipMemcpyAsync(trace->digest, a.tr_digest, 16 * size_t(T), hipMemcpyDeviceToHost, s));
+  return AIRPF_OK;
+}
+
+airpf_status finish(airpf_ctx* ctx, const Prepared& P, double* log_z_out) {
   double lz = 0.0;
   int kstatus = 0;
-  HIP_OK(hipMemcpyAsync(&lz, a.out_logz, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(&kstatus, a.status, sizeof(int), hipMemcpyDeviceToHost, s));
-  if (trace) {
-    if (a.tr_sstar) HIP_OK(hipMemcpyAsync(trace->sstar, a.tr_sstar, 4 * size_t(T), hipMemcpyDeviceToHost, s));
-    if (a.tr_enf) HIP_OK(hipMemcpyAsync(trace->enf, a.tr_enf, 8 * size_t(T) * (S + 1), hipMemcpyDeviceToHost, s));
-    if (a.tr_lpost) HIP_OK(hipMemcpyAsync(trace->lpost, a.tr_lpost, 8 * size_t(T) * m, hipMemcpyDeviceToHost, s));
-    if (a.tr_anc) HIP_OK(hipMemcpyAsync(trace->anc, a.tr_anc, 4 * size_t(T - 1) * m * N, hipMemcpyDeviceToHost, s));
-    if (a.tr_pi) HIP_OK(hipMemcpyAsync(trace->pi, a.tr_pi, 4 * size_t(T - 1) * m, hipMemcpyDeviceToHost, s));
-    if (a.tr_digest) HIP_OK(hipMemcpyAsync(trace->digest, a.tr_digest, 16 * size_t(T), hipMemcpyDeviceToHost, s));
-  }
+  hipStream_t s = ctx->stream;
+  HIP_OK(hipMemcpyAsync(&lz, P.a.out_logz, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&kstatus, P.a.status, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   if (kstatus != 0) return AIRPF_E_DEVICE;
   float ms = 0.0f;
   HIP_OK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
   ctx->last_kernel_ms = ms;
   *log_z_out = lz;
+  return AIRPF_OK;
+}
+
+}  // namespace
+
+extern "C" airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, const double* theta, int32_t d_theta,
+                                  const double* y, int64_t T, int32_t m, int32_t N, uint64_t seed,
+                                  const airpf_options* opt_in, double* log_z_out, airpf_trace* trace) {
+  Prepared P;
+  ST_OK(prepare(ctx, model, theta, d_theta, y, T, m, N, seed, opt_in, log_z_out, 1024, &P));
+  ST_OK(attach_trace(ctx, P, trace));
+  P.L.plan_only = 0;
+  HIP_OK(hipEventRecord(ctx->ev[0], ctx->stream));
+  if (airpf::launch_forward(P.L, P.a, &P.plan) != hipSuccess) return AIRPF_E_DEVICE;
+  HIP_OK(hipEventRecord(ctx->ev[1], ctx->stream));
+  ST_OK(copy_trace(ctx, P, trace));
+  return finish(ctx, P, log_z_out);
+}
+
+extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, const double* theta,
+                                    int32_t d_theta, const double* y, int64_t T, int32_t m, int32_t N,
+                                    uint64_t seed, const airpf_options* opt_in, double* log_z_out,
+                                    double* grad_out, airpf_trace* trace) {
+  if (grad_out) for (int i = 0; i < d_theta; ++i) grad_out[i] = std::nan("");
+  if (!grad_out) { set_nan(log_z_out); return AIRPF_E_INVALID_ARG; }
+  const airpf_options opt = opt_in ? *opt_in : default_options();
+  if (opt.score_mode == AIRPF_PATHWISE) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
+  if (opt.score_mode != AIRPF_PATHSPACE || opt.ckpt_every < 0) { set_nan(log_z_out); return AIRPF_E_INVALID_ARG; }
+  if (model && ((model->kind == AIRPF_LGD && N > 512) || (model->kind != AIRPF_LGD && N > 1024))) {
+    set_nan(log_z_out);
+    return AIRPF_E_UNSUPPORTED;
+  }
+  if (ctx) HIP_OK(hipSetDevice(ctx->device));
+
+  // the reverse kernel's co-residency bounds the plan of both launches
+  airpf::BwdArgs b;
+  std::memset(&b, 0, sizeof(b));
+  b.N = N;
+  int bwd_max = 0;
+  if (model && ctx) {
+    airpf::FwdLaunch Lq;
+    Lq.kind = model->kind; Lq.dx = model->kind == AIRPF_LGD ? model->dx : 1;
+    Lq.fp64 = opt.precision == AIRPF_FP64; Lq.num_cus = ctx->num_cus; Lq.max_blocks = 1024; Lq.plan_only = 1;
+    Lq.stream = ctx->stream;
+    if (airpf::launch_backward(Lq, b, &bwd_max) != hipSuccess || bwd_max < 1) {
+      set_nan(log_z_out);
+      return (model->kind == AIRPF_LGD && !(Lq.dx == 2 || Lq.dx == 3 || Lq.dx == 4 || Lq.dx == 8)) ? AIRPF_E_INVALID_ARG
+                                                                                                 : AIRPF_E_DEVICE;
+    }
+  }
+  Prepared P;
+  ST_OK(prepare(ctx, model, theta, d_theta, y, T, m, N, seed, opt_in, log_z_out, bwd_max < 1024 ? bwd_max : 1024, &P));
+  ST_OK(attach_trace(ctx, P, trace));
+  airpf::FwdArgs& a = P.a;
+  hipStream_t s = ctx->stream;
+  const int dx = P.dx;
+  const size_t store = P.L.fp64 ? 8 : 4;
+  const size_t per_step = size_t(m) * N * (dx * store + 2);
+
+  // checkpoint interval
+  int64_t K = opt.ckpt_every;
+  if (K == 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t(8) << 30;
+    const size_t budget = free_b / 3;
+    if (per_step * size_t(T) <= budget) K = T;
+    else { K = 1; while (K * K < T) ++K; }
+  }
+  if (K > T) K = T;
+  const int64_t C = (T + K - 1) / K;
+
+  // workspaces of the score
+  ST_OK(ctx->s_pi.ensure(4 * size_t(T) * m));
+  ST_OK(ctx->s_sstar.ensure(4 * size_t(T)));
+  ST_OK(ctx->s_lpre.ensure(8 * size_t(T) * m));
+  ST_OK(ctx->s_ckx.ensure(size_t(C) * m * N * dx * store));
+  ST_OK(ctx->s_ckL.ensure(8 * size_t(C) * m));
+  ST_OK(ctx->s_recx.ensure(size_t(K) * m * N * dx * store));
+  ST_OK(ctx->s_reca.ensure(2 * size_t(K) * m * N));
+  for (int p = 0; p < 2; ++p) {
+    ST_OK(ctx->s_lam[p].ensure(size_t(m) * N * dx * store));
+    ST_OK(ctx->s_del[p].ensure(size_t(m) * N * store));
+  }
+  const int Pn = d_theta;
+  ST_OK(ctx->s_grad.ensure(8 * size_t(P.plan.G) * Pn));
+
+  // forward: keep island maps, stage counts, entering weights, checkpoints;
+  // with a single segment the particle history is recorded right away
+  int32_t* keep_pi = a.tr_pi;
+  a.tr_pi = static_cast<int32_t*>(ctx->s_pi.p);
+  int32_t* keep_sstar = a.tr_sstar;
+  a.tr_sstar = static_cast<int32_t*>(ctx->s_sstar.p);
+  a.tr_lpre = static_cast<double*>(ctx->s_lpre.p);
+  a.ck_every = K;
+  a.ck_x = ctx->s_ckx.p;
+  a.ck_L = static_cast<double*>(ctx->s_ckL.p);
+  if (C == 1) {
+    a.rec_x = ctx->s_recx.p;
+    a.rec_anc = static_cast<uint16_t*>(ctx->s_reca.p);
+  }
+  P.L.plan_only = 0;
+  HIP_OK(hipEventRecord(ctx->ev[0], s));
+  if (airpf::launch_forward(P.L, a, &P.plan) != hipSuccess) return AIRPF_E_DEVICE;
+  if (keep_pi && T > 1)
+    HIP_OK(hipMemcpyAsync(keep_pi, a.tr_pi, 4 * size_t(T - 1) * m, hipMemcpyDeviceToDevice, s));
+  if (keep_sstar) HIP_OK(hipMemcpyAsync(keep_sstar, a.tr_sstar, 4 * size_t(T), hipMemcpyDeviceToDevice, s));
+
+  // reverse, one segment at a time
+  b.mp = a.mp; b.y = a.y; b.T = T; b.m = m; b.N = N; b.S = P.S; b.c = P.plan.c; b.lc = ilog2(P.plan.c);
+  b.G = P.plan.G; b.dy = P.dy; b.seed = seed;
+  b.log_mN = std::log(static_cast<double>(m) * static_cast<double>(N));
+  b.c_log = a.cst_q + 40.0 * std::log(2.0) + std::log(static_cast<double>(N));
+  b.logz = a.out_logz;
+  b.rec_x = ctx->s_recx.p;
+  b.rec_anc = static_cast<const uint16_t*>(ctx->s_reca.p);
+  b.pi_all = a.tr_pi;
+  b.sstar_all = a.tr_sstar;
+  b.lpre_all = a.tr_lpre;
+  for (int p = 0; p < 2; ++p) { b.lam[p] = ctx->s_lam[p].p; b.del[p] = ctx->s_del[p].p; }
+  b.gpart = static_cast<double*>(ctx->s_grad.p);
+  b.bar = a.bar;
+  b.status = a.status;
+  HIP_OK(airpf::fill_u32(b.gpart, 0u, 2 * int64_t(P.plan.G) * Pn, s));
+  for (int64_t cidx = C - 1; cidx >= 0; --cidx) {
+    const int64_t lo = cidx * K, hi = (cidx + 1) * K < T ? (cidx + 1) * K : T;
+    if (C > 1) {
+      airpf::FwdArgs r = a;
+      r.n0 = lo; r.n1 = hi; r.replay_pi = 1; r.ck_in = lo > 0 ? 1 : 0;
+      r.rec_x = ctx->s_recx.p;
+      r.rec_anc = static_cast<uint16_t*>(ctx->s_reca.p);
+      r.tr_sstar = nullptr; r.tr_enf = nullptr; r.tr_lpost = nullptr; r.tr_anc = nullptr; r.tr_digest = nullptr;
+      r.tr_lpre = nullptr;
+      ST_OK(reset_flags(ctx, P));
+      if (airpf::launch_forward(P.L, r, &P.plan) != hipSuccess) return AIRPF_E_DEVICE;
+    }
+    b.n_lo = lo;
+    b.n_hi = hi;
+    ST_OK(reset_flags(ctx, P));
+    if (airpf::launch_backward(P.L, b, nullptr) != hipSuccess) return AIRPF_E_DEVICE;
+  }
+  HIP_OK(hipEventRecord(ctx->ev[1], s));
+
+  std::vector<double> parts(size_t(P.plan.G) * Pn);
+  HIP_OK(hipMemcpyAsync(parts.data(), b.gpart, 8 * parts.size(), hipMemcpyDeviceToHost, s));
+  a.tr_pi = keep_pi;                 // the caller's trace arrays were filled above
+  a.tr_sstar = keep_sstar;
+  ST_OK(copy_trace(ctx, P, trace));
+  ST_OK(finish(ctx, P, log_z_out));
+  for (int p = 0; p < Pn; ++p) {
+    double g = 0.0;
+    for (int bi = 0; bi < P.plan.G; ++bi) g += parts[size_t(bi) * Pn + p];
+    grad_out[p] = g;
+  }
   return AIRPF_OK;
 }
 

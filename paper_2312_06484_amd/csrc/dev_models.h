@@ -10,6 +10,11 @@
 //   LGD  x_0[d] = sqrt(p0)*z_d;  x'[i] = sqrt(q)*z_i then fma(A[i][c], x[c], .)
 //        over c;  e_i = y_i then fma(-H[i][c], x[c], .) over c;
 //        ss = fma(e_i, e_i, ss) over i;  lw = -(ss*(1/(2r)))
+//
+// Derivatives for the score (plain double arithmetic, no bit-exactness
+// contract): d lw/dx, d log g/d theta (the constant of log g included),
+// and vector-Jacobian products of the mutation x' = F(x, z; theta) and of
+// the initial draw.
 #pragma once
 #include "dev_math.h"
 
@@ -23,6 +28,7 @@ struct ModelArgs {
   double th[kMaxTheta];
   double H[kMaxDy * 8];
   double s0, sq, sp0, hr;
+  double ds0_dphi, ds0_dsig;  // SV: derivatives of the stationary sd
   int dy;
 };
 
@@ -43,6 +49,22 @@ struct LG1 {
     const double r = (y[0] - x[0]) / p.th[2];
     return -0.5 * (r * r);
   }
+  static constexpr int P = 3;
+  __device__ static void dlogpot_dx(const ModelArgs& p, const double* x, const double* y, double* g) {
+    const double sy = p.th[2];
+    g[0] = (y[0] - x[0]) / (sy * sy);
+  }
+  __device__ static void dlogpot_dtheta(const ModelArgs& p, const double* x, const double* y, double w, double* acc) {
+    const double sy = p.th[2], e = y[0] - x[0];
+    acc[2] += w * (e * e / (sy * sy * sy) - 1.0 / sy);
+  }
+  __device__ static void prop_vjp_x(const ModelArgs& p, const double* lam, double* out) { out[0] = p.th[0] * lam[0]; }
+  __device__ static void prop_vjp_theta(const ModelArgs&, const double* xp, const double* z, const double* lam,
+                                        double* acc) {
+    acc[0] += lam[0] * xp[0];
+    acc[1] += lam[0] * z[0];
+  }
+  __device__ static void init_vjp_theta(const ModelArgs&, const double*, const double*, double*) {}
 };
 
 struct SV {
@@ -59,6 +81,23 @@ struct SV {
   __device__ static double logpot(const ModelArgs&, const double* x, const double* y) {
     const double h = 0.5 * (y[0] * y[0]);
     return fma(-h, dexp(-x[0]), -0.5 * x[0]);
+  }
+  static constexpr int P = 3;
+  __device__ static void dlogpot_dx(const ModelArgs&, const double* x, const double* y, double* g) {
+    g[0] = -0.5 + 0.5 * y[0] * y[0] * dexp(-x[0]);
+  }
+  __device__ static void dlogpot_dtheta(const ModelArgs&, const double*, const double*, double, double*) {}
+  __device__ static void prop_vjp_x(const ModelArgs& p, const double* lam, double* out) { out[0] = p.th[1] * lam[0]; }
+  __device__ static void prop_vjp_theta(const ModelArgs& p, const double* xp, const double* z, const double* lam,
+                                        double* acc) {
+    acc[0] += lam[0] * (1.0 - p.th[1]);
+    acc[1] += lam[0] * (xp[0] - p.th[0]);
+    acc[2] += lam[0] * z[0];
+  }
+  __device__ static void init_vjp_theta(const ModelArgs& p, const double* z, const double* lam, double* acc) {
+    acc[0] += lam[0];
+    acc[1] += lam[0] * z[0] * p.ds0_dphi;
+    acc[2] += lam[0] * z[0] * p.ds0_dsig;
   }
 };
 
@@ -90,6 +129,37 @@ struct LGD {
     }
     return -(ss * p.hr);
   }
+  static constexpr int P = D * D;
+  __device__ static void dlogpot_dx(const ModelArgs& p, const double* x, const double* y, double* g) {
+    const double inv_r = 2.0 * p.hr;
+#pragma unroll
+    for (int c = 0; c < D; ++c) g[c] = 0.0;
+    for (int i = 0; i < p.dy; ++i) {
+      double e = y[i];
+#pragma unroll
+      for (int c = 0; c < D; ++c) e -= p.H[i * D + c] * x[c];
+#pragma unroll
+      for (int c = 0; c < D; ++c) g[c] += p.H[i * D + c] * e * inv_r;
+    }
+  }
+  __device__ static void dlogpot_dtheta(const ModelArgs&, const double*, const double*, double, double*) {}
+  __device__ static void prop_vjp_x(const ModelArgs& p, const double* lam, double* out) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) acc += p.th[i * D + c] * lam[i];
+      out[c] = acc;
+    }
+  }
+  __device__ static void prop_vjp_theta(const ModelArgs&, const double* xp, const double*, const double* lam,
+                                        double* acc) {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[i * D + c] += lam[i] * xp[c];
+  }
+  __device__ static void init_vjp_theta(const ModelArgs&, const double*, const double*, double*) {}
 };
 
 }  // namespace airpf

@@ -1,0 +1,207 @@
+// Device helpers shared by the filter kernels: cross-block memory accesses,
+// the grid barrier, team (one island) and block reductions, the island
+// pair-mean and pair-selection probability.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dev_math.h"
+
+namespace airpf {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+
+__device__ __forceinline__ int64_t tree_off(int m, int level) {  // level >= 1
+  return 2 * static_cast<int64_t>(m) - ((2 * static_cast<int64_t>(m)) >> (level - 1));
+}
+
+__device__ __forceinline__ double ninf() { return -__longlong_as_double(0x7ff0000000000000LL); }
+
+// log((exp(a) + exp(b)) / 2), symmetric in (a, b)
+__device__ __forceinline__ double pair_mean(double a, double b) {
+  const double hi = a > b ? a : b, lo = a > b ? b : a;
+  if (hi == ninf()) return hi;
+  double t = dexp(lo - hi);
+  t = 1.0 + t;
+  t = dlog(t);
+  return (hi + t) - kLn2;
+}
+
+// probability that an island with log-weight lk takes its partner's block
+__device__ __forceinline__ double take_partner_prob(double lk, double lp) {
+  if (lp == ninf()) return 0.0;
+  if (lk == ninf()) return 1.0;
+  return 1.0 / (1.0 + dexp(lk - lp));
+}
+
+// ------------------------------------------------------------ cross-block data
+// Everything one block writes for another (resampled blocks, the island tree,
+// the ENF partials, barrier flags) is written and read with device-scope
+// relaxed atomic accesses, which are coherent across the chip's per-XCD L2
+// caches by themselves.  No device-scope fence is ever issued: on this part
+// such a fence writes back or invalidates a whole L2, and an invalidated L2
+// costs every block its cached code and arguments.
+template <typename T>
+__device__ __forceinline__ void put(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+template <typename T>
+__device__ __forceinline__ T get(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------ grid barrier
+// Flag-array barrier: block b publishes the epoch it has reached in flags[b]
+// (its own word, so no two blocks ever update one address), and every block
+// polls all G flags, lane t watching flags t, t + 256, ...  Before a block
+// publishes, every lane waits until all of its memory operations have
+// completed (s_waitcnt 0), so the block's device-scope stores are visible
+// to any device-scope load issued after the flag is seen.  Spinning is
+// bounded: after ~2^24 polls a block raises status and leaves.
+__device__ bool grid_barrier(unsigned* flags, int G, unsigned& epoch, int* status) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  ++epoch;
+  if (threadIdx.x == 0) put(&flags[blockIdx.x], epoch);
+  int ok = 1;
+  for (int i = threadIdx.x; i < G && ok; i += kBlock) {
+    unsigned spins = 0;
+    while (get(&flags[i]) < epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 1023u) == 0 && (spins > (1u << 24) || get(status) != 0)) {
+        put(status, 1);
+        ok = 0;
+        break;
+      }
+    }
+  }
+  ok = __syncthreads_and(ok);
+  return ok != 0;
+}
+
+// ------------------------------------------------------------ team / block reductions
+// A team is TP consecutive lanes (TP a power of two); TP <= 64 stays inside
+// one wave (shuffles only), TP > 64 spans TP/64 whole waves (LDS combine).
+// Every helper is called by the whole block (TP is block-uniform).
+
+template <typename T>
+__device__ __forceinline__ T team_bcast(T v, int TP, T* lds_slot_per_team) {
+  const int tid = threadIdx.x;
+  if (TP <= 64) return __shfl(v, (tid & 63) & ~(TP - 1), 64);
+  const int team = tid / TP;
+  if ((tid & (TP - 1)) == 0) lds_slot_per_team[team] = v;
+  __syncthreads();
+  const T r = lds_slot_per_team[team];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double team_max(double v, int TP, double* red) {
+  const int w = TP < 64 ? TP : 64;
+  for (int d = 1; d < w; d <<= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  if (TP > 64) {
+    const int tid = threadIdx.x;
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    const int w0 = (tid / TP) * (TP >> 6);
+    double r = red[w0];
+    for (int i = 1; i < (TP >> 6); ++i) r = fmax(r, red[w0 + i]);
+    __syncthreads();
+    v = r;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t team_sum_u64(uint64_t v, int TP, uint64_t* red) {
+  const int w = TP < 64 ? TP : 64;
+  for (int d = 1; d < w; d <<= 1) v += __shfl_xor(v, d, 64);
+  if (TP > 64) {
+    const int tid = threadIdx.x;
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    const int w0 = (tid / TP) * (TP >> 6);
+    uint64_t r = 0;
+    for (int i = 0; i < (TP >> 6); ++i) r += red[w0 + i];
+    __syncthreads();
+    v = r;
+  }
+  return v;
+}
+
+// inclusive scan of v over the team's lanes (lane order)
+__device__ __forceinline__ uint64_t team_scan_u64(uint64_t v, int TP, uint64_t* red) {
+  const int tid = threadIdx.x;
+  const int w = TP < 64 ? TP : 64;
+  const int sl = tid & (w - 1);
+  for (int d = 1; d < w; d <<= 1) {
+    const uint64_t t = __shfl_up(v, d, w);
+    if (sl >= d) v += t;
+  }
+  if (TP > 64) {
+    if ((tid & 63) == 63) red[tid >> 6] = v;
+    __syncthreads();
+    const int w0 = (tid / TP) * (TP >> 6);
+    uint64_t add = 0;
+    for (int i = w0; i < (tid >> 6); ++i) add += red[i];
+    __syncthreads();
+    v += add;
+  }
+  return v;
+}
+
+// inclusive scan of a double over the team's lanes (lane order)
+__device__ __forceinline__ double team_scan_f64(double v, int TP, double* red) {
+  const int tid = threadIdx.x;
+  const int w = TP < 64 ? TP : 64;
+  const int sl = tid & (w - 1);
+  for (int d = 1; d < w; d <<= 1) {
+    const double t = __shfl_up(v, d, w);
+    if (sl >= d) v += t;
+  }
+  if (TP > 64) {
+    if ((tid & 63) == 63) red[tid >> 6] = v;
+    __syncthreads();
+    const int w0 = (tid / TP) * (TP >> 6);
+    double add = 0.0;
+    for (int i = w0; i < (tid >> 6); ++i) add += red[i];
+    __syncthreads();
+    v += add;
+  }
+  return v;
+}
+
+// block-wide reductions with a fixed pattern (identical result in every block)
+__device__ double block_max(double v, double* red) {
+  for (int d = 1; d < 64; d <<= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < kWaves; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_sum(double v, double* red) {
+  for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < kWaves; ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+
+// log sum_i exp(scale * v[i]) over n values, whole block; `shared` says
+// whether v lives in another block's published memory (device-scope reads)
+__device__ double block_lse(const double* v, int n, double scale, double* red, bool shared) {
+  double mx = ninf();
+  for (int i = threadIdx.x; i < n; i += kBlock) mx = fmax(mx, scale * (shared ? get(v + i) : v[i]));
+  mx = block_max(mx, red);
+  if (mx == ninf()) return mx;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += dexp(scale * (shared ? get(v + i) : v[i]) - mx);
+  s = block_sum(s, red);
+  return mx + dlog(s);
+}
+
+}  // namespace airpf

@@ -37,183 +37,10 @@
 #include <stdint.h>
 
 #include "dev_models.h"
+#include "dev_sync.h"
 #include "internal.h"
 
 namespace airpf {
-
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-
-
-__device__ __forceinline__ int64_t tree_off(int m, int level) {  // level >= 1
-  return 2 * static_cast<int64_t>(m) - ((2 * static_cast<int64_t>(m)) >> (level - 1));
-}
-
-__device__ __forceinline__ double ninf() { return -__longlong_as_double(0x7ff0000000000000LL); }
-
-// log((exp(a) + exp(b)) / 2), symmetric in (a, b)
-__device__ __forceinline__ double pair_mean(double a, double b) {
-  const double hi = a > b ? a : b, lo = a > b ? b : a;
-  if (hi == ninf()) return hi;
-  double t = dexp(lo - hi);
-  t = 1.0 + t;
-  t = dlog(t);
-  return (hi + t) - kLn2;
-}
-
-// probability that an island with log-weight lk takes its partner's block
-__device__ __forceinline__ double take_partner_prob(double lk, double lp) {
-  if (lp == ninf()) return 0.0;
-  if (lk == ninf()) return 1.0;
-  return 1.0 / (1.0 + dexp(lk - lp));
-}
-
-// ------------------------------------------------------------ cross-block data
-// Everything one block writes for another (resampled blocks, the island tree,
-// the ENF partials, barrier flags) is written and read with device-scope
-// relaxed atomic accesses, which are coherent across the chip's per-XCD L2
-// caches by themselves.  No device-scope fence is ever issued: on this part
-// such a fence writes back or invalidates a whole L2, and an invalidated L2
-// costs every block its cached code and arguments.
-template <typename T>
-__device__ __forceinline__ void put(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-template <typename T>
-__device__ __forceinline__ T get(const T* p) {
-  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ------------------------------------------------------------ grid barrier
-// Flag-array barrier: block b publishes the epoch it has reached in flags[b]
-// (its own word, so no two blocks ever update one address), and every block
-// polls all G flags, lane t watching flags t, t + 256, ...  Before a block
-// publishes, every lane waits until all of its memory operations have
-// completed (s_waitcnt 0), so the block's device-scope stores are visible
-// to any device-scope load issued after the flag is seen.  Spinning is
-// bounded: after ~2^24 polls a block raises status and leaves.
-__device__ bool grid_barrier(unsigned* flags, int G, unsigned& epoch, int* status) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  ++epoch;
-  if (threadIdx.x == 0) put(&flags[blockIdx.x], epoch);
-  int ok = 1;
-  for (int i = threadIdx.x; i < G && ok; i += kBlock) {
-    unsigned spins = 0;
-    while (get(&flags[i]) < epoch) {
-      __builtin_amdgcn_s_sleep(1);
-      if ((++spins & 1023u) == 0 && (spins > (1u << 24) || get(status) != 0)) {
-        put(status, 1);
-        ok = 0;
-        break;
-      }
-    }
-  }
-  ok = __syncthreads_and(ok);
-  return ok != 0;
-}
-
-// ------------------------------------------------------------ team / block reductions
-// A team is TP consecutive lanes (TP a power of two); TP <= 64 stays inside
-// one wave (shuffles only), TP > 64 spans TP/64 whole waves (LDS combine).
-// Every helper is called by the whole block (TP is block-uniform).
-
-template <typename T>
-__device__ __forceinline__ T team_bcast(T v, int TP, T* lds_slot_per_team) {
-  const int tid = threadIdx.x;
-  if (TP <= 64) return __shfl(v, (tid & 63) & ~(TP - 1), 64);
-  const int team = tid / TP;
-  if ((tid & (TP - 1)) == 0) lds_slot_per_team[team] = v;
-  __syncthreads();
-  const T r = lds_slot_per_team[team];
-  __syncthreads();
-  return r;
-}
-
-__device__ __forceinline__ double team_max(double v, int TP, double* red) {
-  const int w = TP < 64 ? TP : 64;
-  for (int d = 1; d < w; d <<= 1) v = fmax(v, __shfl_xor(v, d, 64));
-  if (TP > 64) {
-    const int tid = threadIdx.x;
-    if ((tid & 63) == 0) red[tid >> 6] = v;
-    __syncthreads();
-    const int w0 = (tid / TP) * (TP >> 6);
-    double r = red[w0];
-    for (int i = 1; i < (TP >> 6); ++i) r = fmax(r, red[w0 + i]);
-    __syncthreads();
-    v = r;
-  }
-  return v;
-}
-
-__device__ __forceinline__ uint64_t team_sum_u64(uint64_t v, int TP, uint64_t* red) {
-  const int w = TP < 64 ? TP : 64;
-  for (int d = 1; d < w; d <<= 1) v += __shfl_xor(v, d, 64);
-  if (TP > 64) {
-    const int tid = threadIdx.x;
-    if ((tid & 63) == 0) red[tid >> 6] = v;
-    __syncthreads();
-    const int w0 = (tid / TP) * (TP >> 6);
-    uint64_t r = 0;
-    for (int i = 0; i < (TP >> 6); ++i) r += red[w0 + i];
-    __syncthreads();
-    v = r;
-  }
-  return v;
-}
-
-// inclusive scan of v over the team's lanes (lane order)
-__device__ __forceinline__ uint64_t team_scan_u64(uint64_t v, int TP, uint64_t* red) {
-  const int tid = threadIdx.x;
-  const int w = TP < 64 ? TP : 64;
-  const int sl = tid & (w - 1);
-  for (int d = 1; d < w; d <<= 1) {
-    const uint64_t t = __shfl_up(v, d, w);
-    if (sl >= d) v += t;
-  }
-  if (TP > 64) {
-    if ((tid & 63) == 63) red[tid >> 6] = v;
-    __syncthreads();
-    const int w0 = (tid / TP) * (TP >> 6);
-    uint64_t add = 0;
-    for (int i = w0; i < (tid >> 6); ++i) add += red[i];
-    __syncthreads();
-    v += add;
-  }
-  return v;
-}
-
-// block-wide reductions with a fixed pattern (identical result in every block)
-__device__ double block_max(double v, double* red) {
-  for (int d = 1; d < 64; d <<= 1) v = fmax(v, __shfl_xor(v, d, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = red[0];
-  for (int i = 1; i < kWaves; ++i) r = fmax(r, red[i]);
-  __syncthreads();
-  return r;
-}
-
-__device__ double block_sum(double v, double* red) {
-  for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = red[0];
-  for (int i = 1; i < kWaves; ++i) r += red[i];
-  __syncthreads();
-  return r;
-}
-
-// log sum_i exp(scale * v[i]) over n values, whole block; `shared` says
-// whether v lives in another block's published memory (device-scope reads)
-__device__ double block_lse(const double* v, int n, double scale, double* red, bool shared) {
-  double mx = ninf();
-  for (int i = threadIdx.x; i < n; i += kBlock) mx = fmax(mx, scale * (shared ? get(v + i) : v[i]));
-  mx = block_max(mx, red);
-  if (mx == ninf()) return mx;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) s += dexp(scale * (shared ? get(v + i) : v[i]) - mx);
-  s = block_sum(s, red);
-  return mx + dlog(s);
-}
 
 // ------------------------------------------------------------ the kernel
 
@@ -253,10 +80,13 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
     return up[2 * G - ((2 * G) >> u) + idx];
   };
 
-  for (int64_t n = 0; n < a.T; ++n) {
+  const bool replay = a.replay_pi != 0;
+  for (int64_t n = a.n0; n < a.n1; ++n) {
     const int par = static_cast<int>(n & 1), ppar = par ^ 1;
-    if (n > 0) {
+    if (n > a.n0) {
       if (!grid_barrier(a.bar, G, epoch, a.status)) return;
+    }
+    if (n > a.n0 && !replay) {
       // ---- cascade of step n-1 (every block, identical) ----
       for (int b = tid; b < G; b += kBlock) up[b] = get(a.tree[ppar] + tree_off(m, lc + 1) + b);
       __syncthreads();
@@ -296,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
       s_sstar = sstar;
       __syncthreads();
     }
-    const int sstar = (n > 0) ? s_sstar : 0;
+    const int sstar = (n > a.n0 && !replay) ? s_sstar : 0;
 
     for (int p = 0; p < passes; ++p) {
       const int li = p * tpb + team;
@@ -314,12 +144,23 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
       }
       double x[PPT][DX];
       double Lpre = 0.0;
-      if (n == 0) {
+      if (n == a.n0 && a.ck_in) {
+        // restart from the checkpoint taken entering this step
+        const Store* xc = static_cast<const Store*>(a.ck_x) + (n / a.ck_every) * (static_cast<int64_t>(m) * N * DX) +
+                          static_cast<int64_t>(k) * N * DX;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r)
+#pragma unroll
+          for (int d = 0; d < DX; ++d) x[r][d] = (j0 + r < N) ? static_cast<double>(xc[(j0 + r) * DX + d]) : 0.0;
+        if (lane == 0) Lpre = a.ck_L[(n / a.ck_every) * m + k];
+      } else if (n == 0) {
 #pragma unroll
         for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * DX, x[r]);
       } else {
         int src = k;
-        if (lane == 0 && active) {
+        if (replay) {
+          if (lane == 0 && active) src = a.tr_pi[(n - 1) * m + k];
+        } else if (lane == 0 && active) {
           int cur = k;
           for (int s = sstar; s >= 1; --s) {
             const int pr = cur ^ (1 << (s - 1));
@@ -346,6 +187,29 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
         }
       }
 
+      // ---- what the score records: the state entering this weighting ----
+      if (active) {
+        if (a.rec_x) {
+          Store* rx = static_cast<Store*>(a.rec_x) + ((n - a.n0) * m + k) * static_cast<int64_t>(N) * DX;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r)
+#pragma unroll
+            for (int d = 0; d < DX; ++d)
+              if (j0 + r < N) rx[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
+        }
+        if (a.ck_every > 0 && n % a.ck_every == 0 && !replay && a.ck_x) {
+          Store* xc = static_cast<Store*>(a.ck_x) + (n / a.ck_every) * (static_cast<int64_t>(m) * N * DX) +
+                      static_cast<int64_t>(k) * N * DX;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r)
+#pragma unroll
+            for (int d = 0; d < DX; ++d)
+              if (j0 + r < N) xc[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
+          if (lane == 0) a.ck_L[(n / a.ck_every) * m + k] = Lpre;
+        }
+        if (lane == 0 && a.tr_lpre && !replay) a.tr_lpre[n * m + k] = Lpre;
+      }
+
       // ---- weighting ----
       const double* yn = a.y + n * a.dy;
       double lw[PPT];
@@ -368,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
       }
       const uint64_t incl = team_scan_u64(tsum, TP, red_u);
       const uint64_t Qk = team_sum_u64(tsum, TP, red_u);       // Q = sum_i q_i of the island
-      if (lane == 0 && active) {
+      if (lane == 0 && active && !replay) {
         const double L = (Qk == 0) ? ninf() : Lpre + ((mx + dlog(static_cast<double>(Qk))) + a.cst_q);
         lv[li] = L;
         if (a.tr_lpost) a.tr_lpost[n * m + k] = L;
@@ -410,6 +274,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
             }
             sAt[j] = anc;
             if (a.tr_anc) a.tr_anc[(n * m + k) * static_cast<int64_t>(N) + j] = anc;
+            if (a.rec_anc) a.rec_anc[((n - a.n0) * m + k) * static_cast<int64_t>(N) + j] = static_cast<uint16_t>(anc);
             if (a.tr_digest) dig += digest_term(n, k, j, anc);
           }
         }
@@ -432,6 +297,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
       }
     }
     __syncthreads();
+    if (replay) continue;
 
     // ---- this block's part of the island tree and the ENF partial sums ----
     for (int l = 2; l <= lc + 1; ++l) {
@@ -463,6 +329,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
   }
 
   // ---- log Zhat after the last weighting ----
+  if (replay || a.n1 < a.T) return;
   if (!grid_barrier(a.bar, G, epoch, a.status)) return;
   if (blockIdx.x == 0) {
     const int par = static_cast<int>((a.T - 1) & 1);

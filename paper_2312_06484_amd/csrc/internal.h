@@ -28,8 +28,41 @@ struct FwdArgs {
   int32_t* tr_anc;
   int32_t* tr_pi;
   unsigned long long* tr_digest;
+  // ---- what the score needs (all optional) ----
+  int64_t n0, n1;             // steps [n0, n1) of this launch (0, T for a plain run)
+  int replay_pi;              // 1: island maps from tr_pi, no cascade, no island weights
+  int64_t ck_every;           // checkpoint interval K (0: none)
+  void* ck_x;                 // Store*, [ceil(T/K)][m*N*DX] state entering step c*K
+  double* ck_L;               // [ceil(T/K)][m] island log-weights entering step c*K
+  int ck_in;                  // 1: step n0 starts from checkpoint n0/K (else n0 == 0: initial draw)
+  double* tr_lpre;            // [T*m] island log-weights entering each weighting
+  void* rec_x;                // Store*, [(n1-n0)][m*N*DX] state entering each weighting
+  uint16_t* rec_anc;          // [(n1-n0)][m*N] within-island ancestors
 };
 
+
+// Kernel argument block of the reverse (adjoint) launch over steps
+// [n_lo, n_hi), processed from n_hi - 1 down to n_lo.
+struct BwdArgs {
+  ModelArgs mp;
+  const double* y;
+  int64_t T;
+  int m, N, S, TP, c, lc, G, dy;
+  uint64_t seed;
+  double log_mN, c_log;       // log(m N) and the constant of log g
+  const double* logz;         // [1] log Zhat of the forward run (device)
+  int64_t n_lo, n_hi;
+  const void* rec_x;          // Store*, [(n_hi-n_lo)][m*N*DX], index n - n_lo
+  const uint16_t* rec_anc;    // [(n_hi-n_lo)][m*N]
+  const int32_t* pi_all;      // [T*m] island source maps
+  const int32_t* sstar_all;   // [T] interacting stages
+  const double* lpre_all;     // [T*m] island log-weights entering each weighting
+  void* lam[2];               // Store*, [m*N*DX] adjoint of the state, by step parity
+  void* del[2];               // Store*, [m*N] descendant final-weight mass, by step parity
+  double* gpart;              // [G*P] per-block gradient sums (accumulated across launches)
+  unsigned* bar;
+  int* status;
+};
 
 struct FwdLaunch {
   int kind, dx, fp64;
@@ -44,6 +77,8 @@ struct FwdPlan {
 };
 
 hipError_t launch_forward(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
+// max_blocks_out != nullptr: only report how many blocks can be co-resident
+hipError_t launch_backward(const FwdLaunch& L, const BwdArgs& a, int* max_blocks_out);
 hipError_t fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t st);
 hipError_t launch_debug_eval(int which, int64_t n, const double* in, const uint32_t* in_u32, double* out,
                              double* out2, uint32_t* out_u32, hipStream_t st);

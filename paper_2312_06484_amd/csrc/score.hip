@@ -1,0 +1,323 @@
+// Adjoint of the AIRPF filter for the score d log Zhat / d theta (not part
+// of the paper: the estimator differentiated here is the path-space one).
+//
+// With the noise and every discrete decision of the forward run held fixed,
+// the path-space score is
+//   G = sum over final particles of Wbar_i * (d/dtheta of the sum of log g
+//       along particle i's ancestral path, x reparameterised by its noise).
+// Reverse accumulation over steps n = T-1 .. 0, per particle (k, i):
+//   D_n(k,i)  = final weight carried by the descendants of (k,i):
+//               D_{T-1} = Wbar;  D_n(k,i) = sum over children (k', j) of D_{n+1}(k', j)
+//   lam_n(k,i) = D_n(k,i) dlw/dx (x_n^{k,i}) + sum_children (dF/dx)^T lam_{n+1}(k', j)
+//   G += D_n dlogg/dtheta + sum over mutations lam_{n+1} . dF/dtheta + lam_0 . dx_0/dtheta
+// Children of (n, k, i): slots j of islands k' with pi_n(k') = k and
+// a_{n,k}(j) = i.  The islands with pi_n(k') = k all lie in k's aligned
+// 2^{s*_n}-block, so each source island scans that block (ballot, ascending
+// order); within the island the ancestors are sorted, so the slots of one
+// particle form a run and their sums come from one prefix sum.  Nothing is
+// accumulated with atomics: the result is bit-reproducible.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dev_models.h"
+#include "dev_sync.h"
+#include "internal.h"
+
+namespace airpf {
+
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void backward_kernel(BwdArgs a) {
+  constexpr int DX = Model::DX;
+  constexpr int NZ = PPT * DX;
+  constexpr int P = Model::P;
+  constexpr int NV = DX + 1;                   // per slot: lam (DX) and D
+  static_assert(NZ % 4 == 0, "a lane consumes whole Philox blocks");
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red_d[kWaves];
+
+  const int tid = threadIdx.x;
+  const int TP = a.TP, tpb = kBlock / TP;
+  const int team = tid / TP, lane = tid & (TP - 1);
+  const int m = a.m, N = a.N, c = a.c;
+  const int kbase = blockIdx.x * c;
+  const Key key = make_key(a.seed);
+  const int passes = (c + tpb - 1) / tpb;
+
+  Store* sx = reinterpret_cast<Store*>(smem);                                        // [kBlock*NZ]
+  double* sP = reinterpret_cast<double*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));  // [kBlock*PPT*NV]
+  int* sA = reinterpret_cast<int*>(sP + kBlock * PPT * NV);                          // [kBlock*PPT]
+  int* sS = sA + kBlock * PPT;                                                       // [kBlock*PPT] run start
+  int* sE = sS + kBlock * PPT;                                                       // [kBlock*PPT] run end
+
+  double acc[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) acc[p] = 0.0;
+  unsigned epoch = 0;
+  const double logz = *a.logz;
+
+  for (int64_t n = a.n_hi - 1; n >= a.n_lo; --n) {
+    if (n < a.n_hi - 1 && !grid_barrier(a.bar, a.G, epoch, a.status)) return;
+    const bool last = (n == a.T - 1);
+    const int B = last ? 1 : (1 << a.sstar_all[n]);
+    const int par = static_cast<int>(n & 1), npar = par ^ 1;
+    const double* yn = a.y + n * a.dy;
+
+    for (int p = 0; p < passes; ++p) {
+      const int li = p * tpb + team;
+      const bool active = li < c;
+      const int k = kbase + (active ? li : 0);
+      const int j0 = lane * PPT;
+      Store* sxt = sx + team * TP * NZ;
+      double* sPt = sP + team * TP * PPT * NV;
+      int* sAt = sA + team * TP * PPT;
+      int* sSt = sS + team * TP * PPT;
+      int* sEt = sE + team * TP * PPT;
+
+      // ---- the state entering step n and its per-particle log-potential ----
+      const Store* xs = static_cast<const Store*>(a.rec_x) + ((n - a.n_lo) * m + k) * static_cast<int64_t>(N) * DX;
+      double x[PPT][DX], lw[PPT];
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        const bool valid = active && (j0 + r < N);
+#pragma unroll
+        for (int d = 0; d < DX; ++d) {
+          const Store v = valid ? xs[(j0 + r) * DX + d] : Store(0);
+          x[r][d] = static_cast<double>(v);
+          sxt[(j0 + r) * DX + d] = v;
+        }
+        double v = valid ? Model::logpot(a.mp, x[r], yn) : ninf();
+        if (!(v == v)) v = ninf();
+        lw[r] = v;
+      }
+
+      double lam[PPT][DX], D[PPT];
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        D[r] = 0.0;
+#pragma unroll
+        for (int d = 0; d < DX; ++d) lam[r][d] = 0.0;
+      }
+
+      if (last) {
+        // final normalised weights: Wbar = exp(Lpre_k + log g - log(m N) - log Zhat)
+        const double lpre = a.lpre_all[n * m + k];
+#pragma unroll
+        for (int r = 0; r < PPT; ++r)
+          D[r] = (active && j0 + r < N && lw[r] != ninf()) ? dexp(lpre + lw[r] + a.c_log - a.log_mN - logz) : 0.0;
+      } else {
+        // ancestors of this island's slots at step n
+        const uint16_t* an = a.rec_anc + ((n - a.n_lo) * m + k) * static_cast<int64_t>(N);
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) sAt[j0 + r] = (active && j0 + r < N) ? static_cast<int>(an[j0 + r]) : 0x7fffffff;
+        __syncthreads();
+
+        double sl[PPT][NV];                      // per slot: sum over children of (lam, D)
+#pragma unroll
+        for (int r = 0; r < PPT; ++r)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sl[r][v] = 0.0;
+        double xp[PPT][DX];                      // parent value of each slot: x_n[k][a(j)]
+#pragma unroll
+        for (int r = 0; r < PPT; ++r)
+#pragma unroll
+          for (int d = 0; d < DX; ++d)
+            xp[r][d] = (active && j0 + r < N) ? static_cast<double>(sxt[sAt[j0 + r] * DX + d]) : 0.0;
+
+        // ---- children: islands k' of k's 2^{s*}-block with pi_n(k') = k ----
+        const int W = TP < 64 ? TP : 64;
+        const int sl_lane = TP < 64 ? lane : (tid & 63);
+        const int seg0 = TP < 64 ? ((tid & 63) & ~(TP - 1)) : 0;
+        const int blo = k & ~(B - 1);
+        const Store* lam_in = static_cast<const Store*>(a.lam[npar]);
+        const Store* del_in = static_cast<const Store*>(a.del[npar]);
+        for (int it = 0; it < B; it += W) {
+          const int cand = blo + it + sl_lane;
+          const bool match = active && (it + sl_lane < B) && a.pi_all[n * m + cand] == k;
+          const unsigned long long ball = __ballot(match);
+          unsigned long long seg = (W == 64) ? ball : ((ball >> seg0) & ((1ull << W) - 1));
+          while (seg) {
+            const int b = __builtin_ctzll(seg);
+            seg &= seg - 1;
+            const int child = blo + it + b;
+            double z[NZ];
+            for (int g = 0; g < NZ / 4; ++g) {
+              double t[4];
+              normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(child),
+                       static_cast<uint32_t>(n + 1), t);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) z[4 * g + q] = t[q];
+            }
+#pragma unroll
+            for (int r = 0; r < PPT; ++r) {
+              const int j = j0 + r;
+              if (j < N) {
+                double lc[DX];
+#pragma unroll
+                for (int d = 0; d < DX; ++d) {
+                  lc[d] = static_cast<double>(get(lam_in + (static_cast<int64_t>(child) * N + j) * DX + d));
+                  sl[r][d] += lc[d];
+                }
+                sl[r][DX] += static_cast<double>(get(del_in + static_cast<int64_t>(child) * N + j));
+                Model::prop_vjp_theta(a.mp, xp[r], z + r * DX, lc, acc);
+              }
+            }
+          }
+        }
+
+        // ---- back through the internal resampling: runs of equal ancestors ----
+        double run_v[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) run_v[v] = 0.0;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) run_v[v] += sl[r][v];
+        double base[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) base[v] = team_scan_f64(run_v[v], TP, red_d) - run_v[v];
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          sSt[j0 + r] = -1;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            base[v] += sl[r][v];
+            sPt[(j0 + r) * NV + v] = base[v];          // inclusive prefix over slots
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const int j = j0 + r;
+          if (active && j < N) {
+            const int aj = sAt[j];
+            if (j == 0 || sAt[j - 1] != aj) sSt[aj] = j;
+            if (j == N - 1 || sAt[j + 1] != aj) sEt[aj] = j;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const int i = j0 + r;
+          if (active && i < N && sSt[i] >= 0) {
+            const int s0 = sSt[i], e0 = sEt[i];
+            double tot[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) tot[v] = sPt[e0 * NV + v] - (s0 > 0 ? sPt[(s0 - 1) * NV + v] : 0.0);
+            Model::prop_vjp_x(a.mp, tot, lam[r]);
+            D[r] = tot[DX];
+          }
+        }
+      }
+
+      // ---- the weighting terms of step n ----
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        if (active && j0 + r < N && D[r] != 0.0) {
+          double gx[DX];
+          Model::dlogpot_dx(a.mp, x[r], yn, gx);
+#pragma unroll
+          for (int d = 0; d < DX; ++d) lam[r][d] += D[r] * gx[d];
+          Model::dlogpot_dtheta(a.mp, x[r], yn, D[r], acc);
+        }
+      }
+      if (n == 0) {
+        double z[NZ];
+        for (int g = 0; g < NZ / 4; ++g) {
+          double t[4];
+          normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), 0u, t);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) z[4 * g + q] = t[q];
+        }
+#pragma unroll
+        for (int r = 0; r < PPT; ++r)
+          if (active && j0 + r < N) Model::init_vjp_theta(a.mp, z + r * DX, lam[r], acc);
+      } else if (active) {
+        Store* lo = static_cast<Store*>(a.lam[par]) + static_cast<int64_t>(k) * N * DX;
+        Store* dl = static_cast<Store*>(a.del[par]) + static_cast<int64_t>(k) * N;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const int i = j0 + r;
+          if (i < N) {
+#pragma unroll
+            for (int d = 0; d < DX; ++d) put(lo + i * DX + d, static_cast<Store>(lam[r][d]));
+            put(dl + i, static_cast<Store>(D[r]));
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- this block's gradient contribution, added in a fixed order ----
+  for (int p = 0; p < P; ++p) {
+    const double v = block_sum(acc[p], red_d);
+    if (tid == 0) a.gpart[static_cast<int64_t>(blockIdx.x) * P + p] += v;
+  }
+}
+
+// ============================================================ host launcher
+
+static int pow2_ceil_b(int v) { int p = 1; while (p < v) p <<= 1; return p; }
+
+static size_t bwd_smem_bytes(size_t store_bytes, int ppt, int dx) {
+  const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
+  return sx + 8 * size_t(kBlock) * ppt * (dx + 1) + 3 * 4 * size_t(kBlock) * ppt;
+}
+
+template <class Model, typename Store, int PPT>
+static hipError_t launch_b(const FwdLaunch& L, const BwdArgs& a0, int* plan_p) {
+  BwdArgs a = a0;
+  auto kern = backward_kernel<Model, Store, PPT>;
+  const size_t smem = bwd_smem_bytes(sizeof(Store), PPT, Model::DX);
+  if (plan_p) {
+    // the block count must be the forward plan's (same islands per block)
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, smem);
+    if (e != hipSuccess) return e;
+    *plan_p = per_cu * L.num_cus;
+    return hipSuccess;
+  }
+  a.TP = pow2_ceil_b((a.N + PPT - 1) / PPT);
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(a.G), dim3(kBlock), args,
+                                    static_cast<unsigned>(smem), L.stream);
+}
+
+// same particles-per-lane choice as the forward launcher
+template <class Model, typename Store>
+static hipError_t dispatch_b(const FwdLaunch& L, const BwdArgs& a, int* plan_p) {
+  constexpr int DX = Model::DX;
+  if constexpr (DX % 4 == 0) {
+    if (a.N <= 256) return launch_b<Model, Store, 1>(L, a, plan_p);
+    if (a.N <= 512) return launch_b<Model, Store, 2>(L, a, plan_p);
+    return hipErrorInvalidValue;
+  } else if constexpr (DX % 2 == 0) {
+    if (a.N <= 512) return launch_b<Model, Store, 2>(L, a, plan_p);
+    return hipErrorInvalidValue;
+  } else {
+    if (a.N <= 1024) return launch_b<Model, Store, 4>(L, a, plan_p);
+    return hipErrorInvalidValue;
+  }
+}
+
+template <typename Store>
+static hipError_t dispatch_bm(const FwdLaunch& L, const BwdArgs& a, int* plan_p) {
+  switch (L.kind) {
+    case 0: return dispatch_b<LG1, Store>(L, a, plan_p);
+    case 1: return dispatch_b<SV, Store>(L, a, plan_p);
+    case 2:
+      switch (L.dx) {
+        case 2: return dispatch_b<LGD<2>, Store>(L, a, plan_p);
+        case 3: return dispatch_b<LGD<3>, Store>(L, a, plan_p);
+        case 4: return dispatch_b<LGD<4>, Store>(L, a, plan_p);
+        case 8: return dispatch_b<LGD<8>, Store>(L, a, plan_p);
+      }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_backward(const FwdLaunch& L, const BwdArgs& a, int* max_blocks_out) {
+  return L.fp64 ? dispatch_bm<double>(L, a, max_blocks_out) : dispatch_bm<float>(L, a, max_blocks_out);
+}
+
+}  // namespace airpf
