@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -211,6 +212,12 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   a.n0 = 0; a.n1 = T;
   a.shortcut_all = opt.tau > 1.0 + 1e-9;
 
+  // AIRPF_MAX_BLOCKS caps the blocks of a launch (tiling tests); results do
+  // not depend on it
+  if (const char* env = std::getenv("AIRPF_MAX_BLOCKS")) {
+    const int cap = std::atoi(env);
+    if (cap >= 1 && cap < max_blocks) max_blocks = cap;
+  }
   airpf::FwdLaunch& L = P->L;
   L.kind = model->kind; L.dx = P->dx; L.fp64 = opt.precision == AIRPF_FP64;
   L.num_cus = ctx->num_cus; L.max_blocks = max_blocks; L.plan_only = 1; L.stream = s;
@@ -222,7 +229,7 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   for (int p = 0; p < 2; ++p) {
     ST_OK(ctx->x1[p].ensure(nstate));
     ST_OK(ctx->tree[p].ensure(sizeof(double) * 2 * size_t(m)));
-    ST_OK(ctx->part[p].ensure(sizeof(double) * size_t(lc + 1) * P->plan.G));
+    ST_OK(ctx->part[p].ensure(sizeof(double) * 3 * size_t(lc + 1) * P->plan.G));
     a.x1[p] = ctx->x1[p].p;
     a.tree[p] = static_cast<double*>(ctx->tree[p].p);
     a.part[p] = static_cast<double*>(ctx->part[p].p);
@@ -380,7 +387,7 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
     ST_OK(ctx->s_del[p].ensure(size_t(m) * N * store));
   }
   const int Pn = d_theta;
-  ST_OK(ctx->s_grad.ensure(8 * size_t(P.plan.G) * Pn));
+  ST_OK(ctx->s_grad.ensure(8 * size_t(m) * Pn + 8 * 64));
 
   // forward: keep island maps, stage counts, entering weights, checkpoints;
   // with a single segment the particle history is recorded right away
@@ -415,10 +422,11 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   b.sstar_all = a.tr_sstar;
   b.lpre_all = a.tr_lpre;
   for (int p = 0; p < 2; ++p) { b.lam[p] = ctx->s_lam[p].p; b.del[p] = ctx->s_del[p].p; }
-  b.gpart = static_cast<double*>(ctx->s_grad.p);
+  b.gisl = static_cast<double*>(ctx->s_grad.p);
+  double* gsum = b.gisl + size_t(m) * Pn;
   b.bar = a.bar;
   b.status = a.status;
-  HIP_OK(airpf::fill_u32(b.gpart, 0u, 2 * int64_t(P.plan.G) * Pn, s));
+  HIP_OK(airpf::fill_u32(b.gisl, 0u, 2 * int64_t(m) * Pn, s));
   for (int64_t cidx = C - 1; cidx >= 0; --cidx) {
     const int64_t lo = cidx * K, hi = (cidx + 1) * K < T ? (cidx + 1) * K : T;
     if (C > 1) {
@@ -436,20 +444,15 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
     ST_OK(reset_flags(ctx, P));
     if (airpf::launch_backward(P.L, b, nullptr) != hipSuccess) return AIRPF_E_DEVICE;
   }
+  HIP_OK(airpf::launch_island_grad_sum(b.gisl, m, Pn, gsum, s));
   HIP_OK(hipEventRecord(ctx->ev[1], s));
-
-  std::vector<double> parts(size_t(P.plan.G) * Pn);
-  HIP_OK(hipMemcpyAsync(parts.data(), b.gpart, 8 * parts.size(), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(grad_out, gsum, 8 * size_t(Pn), hipMemcpyDeviceToHost, s));
   a.tr_pi = keep_pi;                 // the caller's trace arrays were filled above
   a.tr_sstar = keep_sstar;
   ST_OK(copy_trace(ctx, P, trace));
-  ST_OK(finish(ctx, P, log_z_out));
-  for (int p = 0; p < Pn; ++p) {
-    double g = 0.0;
-    for (int bi = 0; bi < P.plan.G; ++bi) g += parts[size_t(bi) * Pn + p];
-    grad_out[p] = g;
-  }
-  return AIRPF_OK;
+  const airpf_status fs = finish(ctx, P, log_z_out);
+  if (fs != AIRPF_OK) for (int p = 0; p < Pn; ++p) grad_out[p] = std::nan("");
+  return fs;
 }
 
 extern "C" airpf_status airpf_ctx_last_kernel_ms(airpf_ctx* ctx, double* ms) {

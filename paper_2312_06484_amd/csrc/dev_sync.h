@@ -29,6 +29,16 @@ __device__ __forceinline__ double pair_mean(double a, double b) {
   return (hi + t) - kLn2;
 }
 
+// log(exp(a) + exp(b)), symmetric in (a, b)
+__device__ __forceinline__ double log_add_exp(double a, double b) {
+  const double hi = a > b ? a : b, lo = a > b ? b : a;
+  if (hi == ninf()) return hi;
+  double t = dexp(lo - hi);
+  t = 1.0 + t;
+  t = dlog(t);
+  return hi + t;
+}
+
 // probability that an island with log-weight lk takes its partner's block
 __device__ __forceinline__ double take_partner_prob(double lk, double lp) {
   if (lp == ninf()) return 0.0;
@@ -58,11 +68,11 @@ __device__ __forceinline__ T get(const T* p) {
 // completed (s_waitcnt 0), so the block's device-scope stores are visible
 // to any device-scope load issued after the flag is seen.  Spinning is
 // bounded: after ~2^24 polls a block raises status and leaves.
-__device__ bool grid_barrier(unsigned* flags, int G, unsigned& epoch, int* status) {
+__device__ bool grid_barrier(unsigned* flags, int G, int bid, unsigned& epoch, int* status) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   ++epoch;
-  if (threadIdx.x == 0) put(&flags[blockIdx.x], epoch);
+  if (threadIdx.x == 0) put(&flags[bid], epoch);
   int ok = 1;
   for (int i = threadIdx.x; i < G && ok; i += kBlock) {
     unsigned spins = 0;
@@ -149,6 +159,23 @@ __device__ __forceinline__ uint64_t team_scan_u64(uint64_t v, int TP, uint64_t* 
   return v;
 }
 
+// sum of a double over the team's lanes (fixed pattern; every lane gets it)
+__device__ __forceinline__ double team_sum_f64(double v, int TP, double* red) {
+  const int w = TP < 64 ? TP : 64;
+  for (int d = 1; d < w; d <<= 1) v += __shfl_xor(v, d, 64);
+  if (TP > 64) {
+    const int tid = threadIdx.x;
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    const int w0 = (tid / TP) * (TP >> 6);
+    double r = 0.0;
+    for (int i = 0; i < (TP >> 6); ++i) r += red[w0 + i];
+    __syncthreads();
+    v = r;
+  }
+  return v;
+}
+
 // inclusive scan of a double over the team's lanes (lane order)
 __device__ __forceinline__ double team_scan_f64(double v, int TP, double* red) {
   const int tid = threadIdx.x;
@@ -168,6 +195,47 @@ __device__ __forceinline__ double team_scan_f64(double v, int TP, double* red) {
     v += add;
   }
   return v;
+}
+
+// ENF sums of a set of island log-weights L: the record (M, a, b) holds
+// M = max L, a = sum exp(L - M), b = sum exp(L - M)^2.  Records of two
+// halves combine by rescaling to the larger maximum; a member at the maximum
+// contributes exactly 1, as in the definition ENF = (m^-1 sum W)^2 / (m^-1 sum W^2)
+// evaluated with W = exp(L - max L).
+struct EnfRec { double M, a, b; };
+
+__device__ __forceinline__ EnfRec enf_leaf(double L) {
+  return L == ninf() ? EnfRec{L, 0.0, 0.0} : EnfRec{L, 1.0, 1.0};
+}
+
+__device__ __forceinline__ EnfRec enf_join(const EnfRec& x, const EnfRec& y) {
+  if (x.M == ninf()) return y;
+  if (y.M == ninf()) return x;
+  const double M = x.M > y.M ? x.M : y.M;
+  const double fx = dexp(x.M - M), fy = dexp(y.M - M);
+  return EnfRec{M, x.a * fx + y.a * fy, x.b * (fx * fx) + y.b * (fy * fy)};
+}
+
+// reduce n = 2^q records in LDS (arrays M, A, B) by adjacent pairs, whole
+// block; w* are scratch arrays of n/2.  The pairing depends only on the
+// indices, so records of aligned index ranges combine to the same value
+// however the range is split across blocks.
+__device__ EnfRec block_pair_enf(double* M, double* A, double* B, double* wM, double* wA, double* wB, int n) {
+  double *sm = M, *sa = A, *sb = B, *dm = wM, *da = wA, *db = wB;
+  for (int h = n >> 1; h >= 1; h >>= 1) {
+    for (int i = threadIdx.x; i < h; i += kBlock) {
+      const EnfRec r = enf_join(EnfRec{sm[2 * i], sa[2 * i], sb[2 * i]}, EnfRec{sm[2 * i + 1], sa[2 * i + 1], sb[2 * i + 1]});
+      dm[i] = r.M; da[i] = r.a; db[i] = r.b;
+    }
+    __syncthreads();
+    double* t;
+    t = sm; sm = dm; dm = t;
+    t = sa; sa = da; da = t;
+    t = sb; sb = db; db = t;
+  }
+  const EnfRec r{sm[0], sa[0], sb[0]};
+  __syncthreads();
+  return r;
 }
 
 // block-wide reductions with a fixed pattern (identical result in every block)

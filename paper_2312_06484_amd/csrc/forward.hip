@@ -44,8 +44,10 @@ namespace airpf {
 
 // ------------------------------------------------------------ the kernel
 
+// One problem's filter, run by the G blocks of its sub-grid; `bid` is this
+// block's index within them.
 template <class Model, typename Store, int PPT>
-__global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
+__device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;                 // normals per lane per step
   static_assert(NZ % 4 == 0, "a lane consumes whole Philox blocks");
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
   const int TP = a.TP, tpb = kBlock / TP;
   const int team = tid / TP, lane = tid & (TP - 1);
   const int m = a.m, N = a.N, S = a.S, c = a.c, lc = a.lc, G = a.G;
-  const int kbase = blockIdx.x * c;
+  const int kbase = bid * c;
   const Key key = make_key(a.seed);
   const int passes = (c + tpb - 1) / tpb;
 
@@ -69,10 +71,24 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
   int* sA = reinterpret_cast<int*>(sC + kBlock * PPT);                             // [kBlock*PPT]
   double* lv = reinterpret_cast<double*>(sA + kBlock * PPT);                       // [2c]
   double* up = lv + 2 * c;                                                        // [2G]
+  double* scr = up + 2 * G;                                                       // [max(12c, 6G)]
 
   unsigned epoch = 0;
-  const double log_m = dlog(static_cast<double>(m));
-  const double log_c = dlog(static_cast<double>(c));
+
+  // levels lc+1 .. S+1 of the island tree in `up` from the G published block
+  // roots (identical in every block); returns the root, log of the mean
+  // island weight
+  auto upper_tree = [&](int par) -> double {
+    for (int b = tid; b < G; b += kBlock) up[b] = get(a.tree[par] + tree_off(m, lc + 1) + b);
+    __syncthreads();
+    for (int u = 1; lc + 1 + u <= S + 1; ++u) {
+      const int cnt = G >> u;
+      const int o_prev = 2 * G - ((2 * G) >> (u - 1)), o = 2 * G - ((2 * G) >> u);
+      for (int i = tid; i < cnt; i += kBlock) up[o + i] = pair_mean(up[o_prev + 2 * i], up[o_prev + 2 * i + 1]);
+      __syncthreads();
+    }
+    return up[2 * G - 2];
+  };
 
   auto lt_value = [&](int par, int level, int idx) -> double {   // tree value, level >= 1
     if (level <= lc + 1) return get(a.tree[par] + tree_off(m, level) + idx);
@@ -84,21 +100,13 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
   for (int64_t n = a.n0; n < a.n1; ++n) {
     const int par = static_cast<int>(n & 1), ppar = par ^ 1;
     if (n > a.n0) {
-      if (!grid_barrier(a.bar, G, epoch, a.status)) return;
+      if (!grid_barrier(a.bar, G, bid, epoch, a.status)) return;
     }
     if (n > a.n0 && !replay) {
       // ---- cascade of step n-1 (every block, identical) ----
-      for (int b = tid; b < G; b += kBlock) up[b] = get(a.tree[ppar] + tree_off(m, lc + 1) + b);
-      __syncthreads();
-      for (int u = 1; lc + 1 + u <= S + 1; ++u) {
-        const int cnt = G >> u;
-        const int o_prev = 2 * G - ((2 * G) >> (u - 1)), o = 2 * G - ((2 * G) >> u);
-        for (int i = tid; i < cnt; i += kBlock) up[o + i] = pair_mean(up[o_prev + 2 * i], up[o_prev + 2 * i + 1]);
-        __syncthreads();
-      }
-      const double lsum = block_lse(up, G, 1.0, red_d, false) + log_c;   // log sum_k W_k
-      if (lsum == ninf()) {                                          // every island dead
-        if (blockIdx.x == 0 && tid == 0) *a.out_logz = ninf();
+      const double lroot = upper_tree(ppar);                         // log mean_k W_k
+      if (lroot == ninf()) {                                         // every island dead
+        if (bid == 0 && tid == 0) *a.out_logz = ninf();
         return;
       }
       int sstar = 0;
@@ -109,17 +117,37 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
         // every weight unchanged, so every later stage sees the same ENF and
         // does not interact either (traced as that same value)
         for (int s = 1; s <= S; ++s) {
-          const double l2 = (s <= lc + 1) ? block_lse(a.part[ppar] + (int64_t)(s - 1) * G, G, 1.0, red_d, true)
-                                          : block_lse(up + 2 * G - ((2 * G) >> (s - lc - 1)), m >> (s - 1), 2.0, red_d, false);
-          const double enf = dexp(2.0 * lsum - log_m - l2 - (s - 1) * kLn2);
+          // ENF of the weights after s-1 interacting stages: every island holds
+          // its 2^{s-1}-block mean, so sum_k W_k = 2^{s-1} sum_b w_b and
+          // sum_k W_k^2 = 2^{s-1} sum_b w_b^2 over the level-s tree values
+          EnfRec r;
+          double* rm = scr;
+          double* ra = scr + G;
+          double* rb = scr + 2 * G;
+          double* w0 = scr + 3 * G;
+          if (s <= lc + 1) {
+            const double* ps = a.part[ppar] + static_cast<int64_t>(s - 1) * 3 * G;
+            for (int b = tid; b < G; b += kBlock) { rm[b] = get(ps + b); ra[b] = get(ps + G + b); rb[b] = get(ps + 2 * G + b); }
+            __syncthreads();
+            r = block_pair_enf(rm, ra, rb, w0, w0 + G / 2, w0 + G, G);
+          } else {
+            const int cnt = G >> (s - lc - 1);
+            const double* lvl = up + 2 * G - ((2 * G) >> (s - lc - 1));
+            for (int i = tid; i < cnt; i += kBlock) { const EnfRec e = enf_leaf(lvl[i]); rm[i] = e.M; ra[i] = e.a; rb[i] = e.b; }
+            __syncthreads();
+            r = block_pair_enf(rm, ra, rb, w0, w0 + G / 2, w0 + G, cnt);
+          }
+          const double blk = static_cast<double>(1 << (s - 1));
+          const double am = (blk * r.a) / static_cast<double>(m), bm = (blk * r.b) / static_cast<double>(m);
+          const double enf = (am * am) / bm;
           const bool go = enf < a.tau;
-          if (a.tr_enf && blockIdx.x == 0 && tid == 0)
+          if (a.tr_enf && bid == 0 && tid == 0)
             for (int t = s; t <= (go ? s : S); ++t) a.tr_enf[(n - 1) * (S + 1) + t] = enf;
           if (!go) break;
           sstar = s;
         }
       }
-      if (blockIdx.x == 0 && tid == 0) {
+      if (bid == 0 && tid == 0) {
         if (a.tr_sstar) a.tr_sstar[n - 1] = sstar;
         if (a.tr_digest) atomicAdd(&a.tr_digest[2 * (n - 1) + 1], (unsigned long long)sstar * 0x9E3779B97F4A7C15ULL);
       }
@@ -312,33 +340,82 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
       double* dst = a.tree[par] + tree_off(m, l) + (kbase >> (l - 1));
       for (int i = tid; i < cnt; i += kBlock) put(dst + i, lv[o + i]);
     }
-    if (tid <= lc) {
-      const int l = tid + 1;
-      const int cnt = c >> (l - 1);
-      const int o = 2 * c - ((2 * c) >> (l - 1));
-      double mx2 = ninf();
-      for (int i = 0; i < cnt; ++i) mx2 = fmax(mx2, 2.0 * lv[o + i]);
-      double v = mx2;
-      if (mx2 != ninf()) {
-        double s = 0.0;
-        for (int i = 0; i < cnt; ++i) s += dexp(2.0 * lv[o + i] - mx2);
-        v = mx2 + dlog(s);
+    // per level l: the ENF record of this block's level-l tree values, by
+    // adjacent pairs; all levels reduce together, one level per item, in lc
+    // rounds alternating between two copies of the level layout
+    {
+      double* M0 = scr;
+      double* A0 = scr + 2 * c;
+      double* B0 = scr + 4 * c;
+      double* M1 = scr + 6 * c;
+      double* A1 = scr + 8 * c;
+      double* B1 = scr + 10 * c;
+      for (int i = tid; i < 2 * c - 1; i += kBlock) {
+        const EnfRec e = enf_leaf(lv[i]);
+        M0[i] = e.M; A0[i] = e.a; B0[i] = e.b;
       }
-      put(a.part[par] + static_cast<int64_t>(l - 1) * G + blockIdx.x, v);
+      __syncthreads();
+      for (int t = 1; t <= lc; ++t) {
+        double* sm = (t & 1) ? M0 : M1;
+        double* sa = (t & 1) ? A0 : A1;
+        double* sb = (t & 1) ? B0 : B1;
+        double* dm = (t & 1) ? M1 : M0;
+        double* da = (t & 1) ? A1 : A0;
+        double* db = (t & 1) ? B1 : B0;
+        for (int it = tid; it < c; it += kBlock) {
+          int i = it;
+          for (int l = 1; l <= lc + 1; ++l) {
+            const int cnt = (c >> (l - 1)) >> t;
+            if (i < cnt) {
+              const int o = 2 * c - ((2 * c) >> (l - 1));
+              const EnfRec r = enf_join(EnfRec{sm[o + 2 * i], sa[o + 2 * i], sb[o + 2 * i]},
+                                        EnfRec{sm[o + 2 * i + 1], sa[o + 2 * i + 1], sb[o + 2 * i + 1]});
+              dm[o + i] = r.M; da[o + i] = r.a; db[o + i] = r.b;
+              break;
+            }
+            i -= cnt;
+          }
+        }
+        __syncthreads();
+      }
+      if (tid <= lc) {
+        const int l = tid + 1;
+        const int rounds = lc + 1 - l;                 // log2 of the level's count
+        const int o = 2 * c - ((2 * c) >> (l - 1));
+        const bool odd = rounds & 1;
+        double* pl = a.part[par] + static_cast<int64_t>(l - 1) * 3 * G;
+        put(pl + bid, odd ? M1[o] : M0[o]);
+        put(pl + G + bid, odd ? A1[o] : A0[o]);
+        put(pl + 2 * G + bid, odd ? B1[o] : B0[o]);
+      }
+      __syncthreads();
     }
   }
 
-  // ---- log Zhat after the last weighting ----
+  // ---- log Zhat after the last weighting: log of the mean island weight,
+  // the root of the island tree ----
   if (replay || a.n1 < a.T) return;
-  if (!grid_barrier(a.bar, G, epoch, a.status)) return;
-  if (blockIdx.x == 0) {
-    const int par = static_cast<int>((a.T - 1) & 1);
-    const double lsum = block_lse(a.tree[par] + tree_off(m, lc + 1), G, 1.0, red_d, true) + log_c;
+  if (!grid_barrier(a.bar, G, bid, epoch, a.status)) return;
+  if (bid == 0) {
+    const double lroot = upper_tree(static_cast<int>((a.T - 1) & 1));
     if (tid == 0) {
-      *a.out_logz = lsum - log_m;
+      *a.out_logz = lroot;
       if (a.tr_sstar) a.tr_sstar[a.T - 1] = 0;
     }
   }
+}
+
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
+  forward_body<Model, Store, PPT>(a, static_cast<int>(blockIdx.x));
+}
+
+// Several problems in one cooperative launch: block b runs block bmap[b].y of
+// problem bmap[b].x; each problem synchronises only its own blocks.
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void forward_batch_kernel(const FwdArgs* probs, const int2* bmap) {
+  const int2 pb = bmap[blockIdx.x];
+  forward_body<Model, Store, PPT>(probs[pb.x], pb.y);
 }
 
 }  // namespace airpf
@@ -352,7 +429,8 @@ static int ilog2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
 
 static size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) {
   const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
-  return sx + 8 * size_t(kBlock) * ppt + 4 * size_t(kBlock) * ppt + 8 * 2 * size_t(c) + 8 * 2 * size_t(G);
+  const size_t scr = 12 * size_t(c) > 6 * size_t(G) ? 12 * size_t(c) : 6 * size_t(G);
+  return sx + 8 * size_t(kBlock) * ppt + 4 * size_t(kBlock) * ppt + 8 * 2 * size_t(c) + 8 * 2 * size_t(G) + 8 * scr;
 }
 
 template <class Model, typename Store, int PPT>

@@ -18,7 +18,7 @@ struct FwdArgs {
   int shortcut_all;
   void* x1[2];                // Store*, resampled blocks, [m*N*DX] particle-major
   double* tree[2];            // [2m] pair-mean tree of island log-weights
-  double* part[2];            // [(lc+1)*G] per-block log sum exp(2 LT) per level
+  double* part[2];            // [(lc+1)*3*G] per level: the blocks' ENF records (max, sum w, sum w^2)
   unsigned* bar;              // [G] grid-barrier flags, zero before the launch
   int* status;                // [1] 0 ok, 1 barrier timed out
   double* out_logz;           // [1]
@@ -59,7 +59,7 @@ struct BwdArgs {
   const double* lpre_all;     // [T*m] island log-weights entering each weighting
   void* lam[2];               // Store*, [m*N*DX] adjoint of the state, by step parity
   void* del[2];               // Store*, [m*N] descendant final-weight mass, by step parity
-  double* gpart;              // [G*P] per-block gradient sums (accumulated across launches)
+  double* gisl;               // [m*P] per-island gradient sums (accumulated across launches)
   unsigned* bar;
   int* status;
 };
@@ -79,6 +79,7 @@ struct FwdPlan {
 hipError_t launch_forward(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
 // max_blocks_out != nullptr: only report how many blocks can be co-resident
 hipError_t launch_backward(const FwdLaunch& L, const BwdArgs& a, int* max_blocks_out);
+hipError_t launch_island_grad_sum(const double* gisl, int m, int P, double* out, hipStream_t st);
 hipError_t fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t st);
 hipError_t launch_debug_eval(int which, int64_t n, const double* in, const uint32_t* in_u32, double* out,
                              double* out2, uint32_t* out_u32, hipStream_t st);

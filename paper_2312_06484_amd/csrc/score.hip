@@ -26,7 +26,7 @@
 namespace airpf {
 
 template <class Model, typename Store, int PPT>
-__global__ __launch_bounds__(kBlock) void backward_kernel(BwdArgs a) {
+__device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;
   constexpr int P = Model::P;
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(BwdArgs a) {
   const int TP = a.TP, tpb = kBlock / TP;
   const int team = tid / TP, lane = tid & (TP - 1);
   const int m = a.m, N = a.N, c = a.c;
-  const int kbase = blockIdx.x * c;
+  const int kbase = bid * c;
   const Key key = make_key(a.seed);
   const int passes = (c + tpb - 1) / tpb;
 
@@ -49,14 +49,11 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(BwdArgs a) {
   int* sS = sA + kBlock * PPT;                                                       // [kBlock*PPT] run start
   int* sE = sS + kBlock * PPT;                                                       // [kBlock*PPT] run end
 
-  double acc[P];
-#pragma unroll
-  for (int p = 0; p < P; ++p) acc[p] = 0.0;
   unsigned epoch = 0;
   const double logz = *a.logz;
 
   for (int64_t n = a.n_hi - 1; n >= a.n_lo; --n) {
-    if (n < a.n_hi - 1 && !grid_barrier(a.bar, a.G, epoch, a.status)) return;
+    if (n < a.n_hi - 1 && !grid_barrier(a.bar, a.G, bid, epoch, a.status)) return;
     const bool last = (n == a.T - 1);
     const int B = last ? 1 : (1 << a.sstar_all[n]);
     const int par = static_cast<int>(n & 1), npar = par ^ 1;
@@ -72,6 +69,9 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(BwdArgs a) {
       int* sAt = sA + team * TP * PPT;
       int* sSt = sS + team * TP * PPT;
       int* sEt = sE + team * TP * PPT;
+      double acc[P];                             // this island's contribution at step n
+#pragma unroll
+      for (int q = 0; q < P; ++q) acc[q] = 0.0;
 
       // ---- the state entering step n and its per-particle log-potential ----
       const Store* xs = static_cast<const Store*>(a.rec_x) + ((n - a.n_lo) * m + k) * static_cast<int64_t>(N) * DX;
@@ -244,14 +244,50 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(BwdArgs a) {
           }
         }
       }
+      // the island's gradient contribution, summed over its lanes in a fixed
+      // pattern and added to the island's own accumulator (in step order)
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const double v = team_sum_f64(acc[q], TP, red_d);
+        if (lane == 0 && active) a.gisl[static_cast<int64_t>(k) * P + q] += v;
+      }
       __syncthreads();
     }
   }
+}
 
-  // ---- this block's gradient contribution, added in a fixed order ----
-  for (int p = 0; p < P; ++p) {
-    const double v = block_sum(acc[p], red_d);
-    if (tid == 0) a.gpart[static_cast<int64_t>(blockIdx.x) * P + p] += v;
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void backward_kernel(BwdArgs a) {
+  backward_body<Model, Store, PPT>(a, static_cast<int>(blockIdx.x));
+}
+
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void backward_batch_kernel(const BwdArgs* probs, const int2* bmap) {
+  const int2 pb = bmap[blockIdx.x];
+  backward_body<Model, Store, PPT>(probs[pb.x], pb.y);
+}
+
+// grad[q] = sum over islands of gisl[k*P + q]: lane t adds islands
+// [t m/256, (t+1) m/256) in order, then the 256 partials by adjacent pairs.
+// The order depends on m only.
+__global__ __launch_bounds__(kBlock) void island_grad_sum_kernel(const double* gisl, int m, int P, double* out) {
+  __shared__ double v[kBlock];
+  __shared__ double w[kBlock / 2];
+  const int per = (m + kBlock - 1) / kBlock;
+  for (int q = 0; q < P; ++q) {
+    double acc = 0.0;
+    for (int i = threadIdx.x * per; i < (threadIdx.x + 1) * per && i < m; ++i) acc += gisl[static_cast<int64_t>(i) * P + q];
+    v[threadIdx.x] = acc;
+    __syncthreads();
+    double* src = v;
+    double* dst = w;
+    for (int h = kBlock / 2; h >= 1; h >>= 1) {
+      if (threadIdx.x < h) dst[threadIdx.x] = src[2 * threadIdx.x] + src[2 * threadIdx.x + 1];
+      __syncthreads();
+      double* t = src; src = dst; dst = t;
+    }
+    if (threadIdx.x == 0) out[q] = src[0];
+    __syncthreads();
   }
 }
 
@@ -314,6 +350,11 @@ static hipError_t dispatch_bm(const FwdLaunch& L, const BwdArgs& a, int* plan_p)
       }
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_island_grad_sum(const double* gisl, int m, int P, double* out, hipStream_t st) {
+  island_grad_sum_kernel<<<dim3(1), dim3(kBlock), 0, st>>>(gisl, m, P, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_backward(const FwdLaunch& L, const BwdArgs& a, int* max_blocks_out) {

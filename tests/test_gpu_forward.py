@@ -179,3 +179,13 @@ def test_invalid_arguments(ctx):
     # a valid call still works after the failures
     st, v = ctx.run(0, th, y, 4, 4, 1)
     assert st == airpf.OK and np.isfinite(v)
+
+
+@pytest.mark.parametrize("tau", [0.5, 0.25, 0.125])
+def test_enf_threshold_at_a_stage_bound(ctx, orc, tau):
+    # after s-1 interacting stages the ENF of stage s cannot fall below
+    # 2^(s-1)/m, and it sits exactly on that bound whenever one block's weight
+    # swamps the others' (common with sharp 8-D likelihoods); tau equal to
+    # such a bound must be decided as the definition decides it (not < tau)
+    lz, gt, lo, ot, P = run_both(ctx, orc, "lgd", 16, 64, 25, tau, False, dx=8)
+    assert_parity(lz, gt, lo, ot, P)
