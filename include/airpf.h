@@ -128,6 +128,32 @@ airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, const double*
                          uint64_t seed, const airpf_options* opt, double* log_z_out,
                          double* grad_out, airpf_trace* trace);
 
+/* One problem of a batch: its own parameter, data, sizes and seed. */
+typedef struct {
+  const double* theta;   /* [d_theta], host */
+  int32_t d_theta;
+  const double* y;       /* [T*dy], host (device with AIRPF_FLAG_Y_ON_DEVICE) */
+  int64_t T;
+  int32_t m, N;          /* islands (power of two), particles per island */
+  uint64_t seed;
+} airpf_problem;
+
+/* Batched multi-theta call (e.g. the proposals of many PMMH chains): every
+ * problem of the batch runs in ONE cooperative persistent launch, each on a
+ * sub-grid of blocks of its own chosen by the library's tiler (the slowest
+ * problem's modelled time is minimised under the device's co-residency);
+ * with want_score the reverse passes are batched too, segment by segment.
+ * All problems share `model` and `opt`; T, m, N, theta and seed may differ.
+ * Outputs: log_z_out[B]; grad_out[B*d_theta] (packed in problem order) when
+ * want_score; item_status[B] per problem (an invalid problem is reported
+ * there and skipped, the others still run).  Each item's results are
+ * bit-identical to the same problem run alone with airpf_run / airpf_score.
+ * The call's return value is AIRPF_OK unless the batch as a whole failed. */
+airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model, int32_t B,
+                             const airpf_problem* probs, const airpf_options* opt,
+                             int32_t want_score, double* log_z_out, double* grad_out,
+                             airpf_status* item_status);
+
 const char* airpf_status_str(airpf_status s);
 
 /* Device time, in milliseconds, of the filter kernel of the last successful

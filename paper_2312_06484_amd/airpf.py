@@ -24,8 +24,8 @@ FLAG_Y_ON_DEVICE = 1
 OK, E_INVALID_ARG, E_DOMAIN, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(6)
 
 # every symbol include/airpf.h declares
-EXPORTS = ["airpf_ctx_create", "airpf_ctx_destroy", "airpf_run", "airpf_score", "airpf_status_str",
-           "airpf_ctx_last_kernel_ms", "airpf_debug_eval"]
+EXPORTS = ["airpf_ctx_create", "airpf_ctx_destroy", "airpf_run", "airpf_score", "airpf_run_batch",
+           "airpf_status_str", "airpf_ctx_last_kernel_ms", "airpf_debug_eval"]
 
 _dp = C.POINTER(C.c_double)
 _i32p = C.POINTER(C.c_int32)
@@ -47,6 +47,11 @@ class _Model(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("tau", C.c_double), ("resampling", C.c_int32), ("precision", C.c_int32),
                 ("score_mode", C.c_int32), ("ckpt_every", C.c_int32), ("flags", C.c_uint32)]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("theta", _dp), ("d_theta", C.c_int32), ("y", C.c_void_p), ("T", C.c_int64),
+                ("m", C.c_int32), ("N", C.c_int32), ("seed", C.c_uint64)]
 
 
 class _Trace(C.Structure):
@@ -79,6 +84,9 @@ def lib():
         L.airpf_score.argtypes = [C.c_void_p, C.POINTER(_Model), _dp, C.c_int32, C.c_void_p, C.c_int64,
                                   C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_Options), _dp, _dp,
                                   C.POINTER(_Trace)]
+        L.airpf_run_batch.restype = C.c_int
+        L.airpf_run_batch.argtypes = [C.c_void_p, C.POINTER(_Model), C.c_int32, C.POINTER(_Problem),
+                                      C.POINTER(_Options), C.c_int32, _dp, _dp, C.POINTER(C.c_int)]
         L.airpf_ctx_last_kernel_ms.restype = C.c_int
         L.airpf_ctx_last_kernel_ms.argtypes = [C.c_void_p, _dp]
         L.airpf_debug_eval.restype = C.c_int
@@ -197,6 +205,44 @@ class Context:
         if st != OK and raise_on_error:
             raise AirpfError(st, "airpf_score")
         return st, out.value, grad
+
+    def run_batch(self, kind, problems, tau=0.3, fp64=False, dx=1, dy=1, consts=None, want_score=False,
+                  ckpt_every=0, y_on_device=False, raise_on_error=True):
+        """airpf_run_batch.  ``problems``: dicts with theta, y (host array, or a
+        device pointer int with ``y_on_device`` and then T), m, N, seed.
+        Returns (status, log_z[B], grad[B, d_theta] or None, item_status[B])."""
+        B = len(problems)
+        model = _Model()
+        model.kind, model.dx, model.dy = int(kind), int(dx), int(dy)
+        cst = None if consts is None else np.ascontiguousarray(consts, dtype=np.float64)
+        model.consts = _p(cst, _dp)
+        model.n_consts = 0 if cst is None else cst.size
+        opt = _Options()
+        opt.tau, opt.resampling, opt.precision = float(tau), SYSTEMATIC, FP64 if fp64 else FP32
+        opt.score_mode, opt.ckpt_every = PATHSPACE, int(ckpt_every)
+        opt.flags = FLAG_Y_ON_DEVICE if y_on_device else 0
+        arr = (_Problem * max(B, 1))()
+        keep = []
+        for i, pr in enumerate(problems):
+            th = np.ascontiguousarray(pr["theta"], dtype=np.float64)
+            keep.append(th)
+            arr[i].theta, arr[i].d_theta = _p(th, _dp), th.size
+            if y_on_device:
+                arr[i].y, arr[i].T = C.c_void_p(int(pr["y"])), int(pr["T"])
+            else:
+                yy = np.ascontiguousarray(pr["y"], dtype=np.float64).reshape(-1)
+                keep.append(yy)
+                arr[i].y, arr[i].T = yy.ctypes.data_as(C.c_void_p), yy.size // int(dy)
+            arr[i].m, arr[i].N, arr[i].seed = int(pr["m"]), int(pr["N"]), int(pr["seed"])
+        P = int(dx) * int(dx) if kind == LGD else 3
+        lz = np.full(max(B, 1), np.nan)
+        gr = np.full((max(B, 1), P), np.nan) if want_score else None
+        ist = (C.c_int * max(B, 1))()
+        st = lib().airpf_run_batch(self._h, C.byref(model), B, arr, C.byref(opt), int(bool(want_score)),
+                                   _p(lz, _dp), _p(gr, _dp) if gr is not None else None, ist)
+        if st != OK and raise_on_error:
+            raise AirpfError(st, "airpf_run_batch")
+        return st, lz[:B], (gr[:B] if gr is not None else None), np.array(ist[:B])
 
     def last_kernel_ms(self):
         """Event-timed device duration of the last call's filter kernel (ms)."""

@@ -4,8 +4,11 @@
 
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "airpf.h"
@@ -47,6 +50,7 @@ struct airpf_ctx {
   DevBuf t_sstar, t_enf, t_lpost, t_anc, t_pi, t_dig;
   DevBuf s_pi, s_sstar, s_lpre, s_ckx, s_ckL, s_recx, s_reca, s_lam[2], s_del[2], s_grad;
   DevBuf dbg_in, dbg_in32, dbg_out, dbg_out2, dbg_out32;
+  DevBuf batch;
 };
 
 #define HIP_OK(expr) do { if ((expr) != hipSuccess) return AIRPF_E_DEVICE; } while (0)
@@ -90,7 +94,7 @@ extern "C" airpf_status airpf_ctx_destroy(airpf_ctx* c) {
                     &c->ybuf, &c->t_sstar, &c->t_enf, &c->t_lpost, &c->t_anc, &c->t_pi, &c->t_dig,
                     &c->dbg_in, &c->dbg_in32, &c->dbg_out, &c->dbg_out2, &c->dbg_out32, &c->s_pi,
                     &c->s_sstar, &c->s_lpre, &c->s_ckx, &c->s_ckL, &c->s_recx, &c->s_reca, &c->s_lam[0],
-                    &c->s_lam[1], &c->s_del[0], &c->s_del[1], &c->s_grad})
+                    &c->s_lam[1], &c->s_del[0], &c->s_del[1], &c->s_grad, &c->batch})
     b->release();
   for (hipEvent_t e : c->ev) if (e) (void)hipEventDestroy(e);
   delete c;
@@ -486,5 +490,363 @@ extern "C" airpf_status airpf_debug_eval(airpf_ctx* ctx, int32_t which, int64_t 
   if (uses_out2) HIP_OK(hipMemcpyAsync(out2, ctx->dbg_out2.p, 8 * size_t(n), hipMemcpyDeviceToHost, s));
   if (which == 4) HIP_OK(hipMemcpyAsync(out_u32, ctx->dbg_out32.p, 16 * size_t(n), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  return AIRPF_OK;
+}
+
+// ======================================================================
+// Batched multi-theta calls
+// ======================================================================
+namespace {
+
+int pow2_ceil_i(int64_t v) { int p = 1; while (p < v) p <<= 1; return p; }
+
+// Bump allocator of one context buffer (256-byte aligned pieces).
+struct Arena {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = (off + 255) & ~size_t(255);
+    off = o + (bytes ? bytes : 1);
+    return o;
+  }
+};
+
+// One valid problem of a batch and its workspace (offsets into the arena).
+struct Item {
+  int idx = 0;
+  airpf::ModelArgs mp;
+  double cst_q = 0.0;
+  int64_t T = 0, K = 0, C = 0;
+  int m = 0, N = 0, S = 0, TP = 0, tpb = 0, G = 1;
+  uint64_t seed = 0;
+  const double* y_dev = nullptr;
+  size_t o_y = 0, o_x1[2] = {0, 0}, o_tree[2] = {0, 0}, o_part[2] = {0, 0}, o_flags = 0;
+  size_t o_pi = 0, o_sstar = 0, o_lpre = 0, o_ckx = 0, o_ckL = 0, o_recx = 0, o_reca = 0;
+  size_t o_lam[2] = {0, 0}, o_del[2] = {0, 0}, o_gisl = 0, o_gsum = 0;
+};
+
+// Tiler.  Modelled time of a problem over `steps` filter steps on G blocks:
+// steps * (alpha + beta * passes), passes = ceil(islands per block / islands
+// per pass).  alpha (the per-step grid synchronisation and island cascade)
+// and beta (one pass of island work) default to values measured on MI355X
+// and can be replaced through AIRPF_TILER="alpha,beta" (microseconds).
+// Start from the fewest blocks that keep a block's islands within the LDS
+// plan (<= 256) and double the block count of the slowest problem while the
+// device's co-residency allows.
+bool tile(std::vector<Item*>& its, const std::vector<int64_t>& steps, int capacity) {
+  double alpha = 12.0, beta = 4.0;
+  if (const char* env = std::getenv("AIRPF_TILER")) {
+    double a = 0, b = 0;
+    if (std::sscanf(env, "%lf,%lf", &a, &b) == 2 && a >= 0 && b > 0) { alpha = a; beta = b; }
+  }
+  auto passes = [](const Item* it, int G) { const int c = it->m / G; return (c + it->tpb - 1) / it->tpb; };
+  auto cost = [&](size_t i, int G) { return double(steps[i]) * (alpha + beta * passes(its[i], G)); };
+  int used = 0;
+  for (Item* it : its) {
+    int g = pow2_ceil_i((it->m + 255) / 256);
+    if (g > it->m) g = it->m;
+    it->G = g;
+    used += g;
+  }
+  if (used > capacity) return false;
+  for (;;) {
+    int best = -1;
+    double worst = -1.0;
+    for (size_t i = 0; i < its.size(); ++i) {
+      Item* it = its[i];
+      const int G2 = it->G * 2;
+      if (G2 > it->m || G2 > 256 || passes(it, it->G) <= 1 || used + it->G > capacity) continue;
+      const double c0 = cost(i, it->G);
+      if (c0 > worst) { worst = c0; best = int(i); }
+    }
+    if (best < 0) break;
+    // only grow the problem that bounds the batch; stop when it cannot grow
+    double top = -1.0;
+    for (size_t i = 0; i < its.size(); ++i) top = std::max(top, cost(i, its[i]->G));
+    if (worst < top) break;
+    used += its[best]->G;
+    its[best]->G *= 2;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model, int32_t B,
+                                        const airpf_problem* probs, const airpf_options* opt_in,
+                                        int32_t want_score, double* log_z_out, double* grad_out,
+                                        airpf_status* item_status) {
+  if (!ctx || !model || B < 0 || (B > 0 && (!probs || !log_z_out || !item_status))) return AIRPF_E_INVALID_ARG;
+  const airpf_options opt = opt_in ? *opt_in : default_options();
+  if (want_score && !grad_out) return AIRPF_E_INVALID_ARG;
+  if (!(opt.tau == opt.tau) || (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) || opt.ckpt_every < 0)
+    return AIRPF_E_INVALID_ARG;
+  if (opt.resampling != AIRPF_SYSTEMATIC) return AIRPF_E_UNSUPPORTED;
+  if (want_score && opt.score_mode != AIRPF_PATHSPACE)
+    return opt.score_mode == AIRPF_PATHWISE ? AIRPF_E_UNSUPPORTED : AIRPF_E_INVALID_ARG;
+  const bool y_dev = (opt.flags & AIRPF_FLAG_Y_ON_DEVICE) != 0;
+  const bool fp64 = opt.precision == AIRPF_FP64;
+  const size_t store = fp64 ? 8 : 4;
+
+  // ---- validation, model constants ----
+  std::vector<Item> items;
+  items.reserve(B);
+  int dx = 1, dy = 1, n_max = 1;
+  // parameters per problem, fixed by the model: the packing of grad_out
+  const int Pn = model->kind == AIRPF_LGD ? model->dx * model->dx : 3;
+  if (Pn < 1 || Pn > airpf::kMaxTheta) return AIRPF_E_INVALID_ARG;
+  for (int32_t i = 0; i < B; ++i) {
+    const airpf_problem& pr = probs[i];
+    log_z_out[i] = std::nan("");
+    if (want_score) for (int q = 0; q < Pn; ++q) grad_out[size_t(i) * Pn + q] = std::nan("");
+    Item it;
+    airpf_status st = AIRPF_OK;
+    if (!pr.theta || !pr.y || pr.T < 1 || pr.T > (int64_t(1) << 30) || !is_pow2(pr.m) || pr.m > (1 << 24) || pr.N < 1 ||
+        pr.N > 2048)
+      st = AIRPF_E_INVALID_ARG;
+    if (st == AIRPF_OK) st = prepare_model(model, pr.theta, pr.d_theta, pr.N, &it.mp, &it.cst_q, &dx, &dy);
+    if (st == AIRPF_OK && pr.d_theta != Pn) st = AIRPF_E_INVALID_ARG;
+    if (st == AIRPF_OK && !y_dev && !all_finite(pr.y, pr.T * dy)) st = AIRPF_E_INVALID_ARG;
+    if (st == AIRPF_OK && want_score && airpf::backward_ppt(model->kind, dx, pr.N) == 0) st = AIRPF_E_UNSUPPORTED;
+    item_status[i] = st;
+    if (st == AIRPF_E_DOMAIN) log_z_out[i] = -INFINITY;
+    if (st != AIRPF_OK) continue;
+    it.idx = i; it.T = pr.T; it.m = pr.m; it.N = pr.N; it.S = ilog2(pr.m); it.seed = pr.seed;
+    it.y_dev = y_dev ? pr.y : nullptr;
+    if (pr.N > n_max) n_max = pr.N;
+    items.push_back(it);
+  }
+  if (items.empty()) return AIRPF_OK;
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+
+  const int ppt_f = airpf::forward_ppt(model->kind, dx, n_max);
+  const int ppt_b = want_score ? airpf::backward_ppt(model->kind, dx, n_max) : 0;
+  for (Item& it : items) {
+    it.TP = pow2_ceil_i((it.N + ppt_f - 1) / ppt_f);
+    it.tpb = 256 / it.TP;
+  }
+  airpf::BatchLaunch BL;
+  BL.kind = model->kind; BL.dx = dx; BL.fp64 = fp64; BL.n_max = n_max; BL.num_cus = ctx->num_cus;
+  BL.stream = s; BL.blocks = 0; BL.probs = nullptr; BL.bmap = nullptr;
+  BL.smem = airpf::forward_smem(fp64, ppt_f, dx, 256, 256);     // bound of any tiling below
+  int cap_f = 0;
+  HIP_OK(airpf::forward_batch_capacity(BL, &cap_f));
+  int cap_b = 0;
+  if (want_score) {
+    airpf::BatchLaunch BB = BL;
+    BB.smem = airpf::backward_smem(fp64, ppt_b, dx);
+    HIP_OK(airpf::backward_batch_capacity(BB, &cap_b));
+  }
+
+  // ---- checkpoint intervals ----
+  if (want_score) {
+    size_t need = 0;
+    for (const Item& it : items) need += size_t(it.T) * it.m * it.N * (dx * store + 2);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t(8) << 30;
+    for (Item& it : items) {
+      int64_t K = opt.ckpt_every;
+      if (K == 0) {
+        if (need <= free_b / 3) K = it.T;
+        else { K = 1; while (K * K < it.T) ++K; }
+      }
+      if (K > it.T) K = it.T;
+      it.K = K;
+      it.C = (it.T + K - 1) / K;
+    }
+  }
+
+  // ---- workspace: one arena ----
+  Arena ar;
+  const size_t o_logz = ar.take(8 * items.size());
+  const size_t o_status = ar.take(64);
+  const size_t o_args = ar.take(sizeof(airpf::FwdArgs) * items.size() + sizeof(airpf::BwdArgs) * items.size());
+  size_t o_bmap = 0;
+  {
+    int64_t blocks_max = 0;
+    for (const Item& it : items) blocks_max += it.m;
+    o_bmap = ar.take(sizeof(int2) * size_t(std::min<int64_t>(blocks_max, int64_t(cap_f > cap_b ? cap_f : cap_b) + 1)));
+  }
+  for (Item& it : items) {
+    const size_t mN = size_t(it.m) * it.N;
+    if (!y_dev) it.o_y = ar.take(8 * size_t(it.T) * dy);
+    for (int p = 0; p < 2; ++p) {
+      it.o_x1[p] = ar.take(mN * dx * store);
+      it.o_tree[p] = ar.take(8 * 2 * size_t(it.m));
+      it.o_part[p] = ar.take(8 * 3 * size_t(it.S + 1) * size_t(std::min(it.m, 256)));
+    }
+    it.o_flags = ar.take(4 * size_t(std::min(it.m, 256)));
+    if (want_score) {
+      it.o_pi = ar.take(4 * size_t(it.T) * it.m);
+      it.o_sstar = ar.take(4 * size_t(it.T));
+      it.o_lpre = ar.take(8 * size_t(it.T) * it.m);
+      it.o_ckx = ar.take(size_t(it.C) * mN * dx * store);
+      it.o_ckL = ar.take(8 * size_t(it.C) * it.m);
+      it.o_recx = ar.take(size_t(it.K) * mN * dx * store);
+      it.o_reca = ar.take(2 * size_t(it.K) * mN);
+      for (int p = 0; p < 2; ++p) {
+        it.o_lam[p] = ar.take(mN * dx * store);
+        it.o_del[p] = ar.take(mN * store);
+      }
+      it.o_gisl = ar.take(8 * size_t(it.m) * Pn);
+      it.o_gsum = ar.take(8 * size_t(Pn));
+    }
+  }
+  ST_OK(ctx->batch.ensure(ar.off));
+  unsigned char* base = static_cast<unsigned char*>(ctx->batch.p);
+  auto at = [&](size_t o) { return static_cast<void*>(base + o); };
+  int* d_status = static_cast<int*>(at(o_status));
+  HIP_OK(airpf::fill_u32(d_status, 0u, 16, s));
+  for (Item& it : items)
+    if (!y_dev)
+      HIP_OK(hipMemcpyAsync(at(it.o_y), probs[it.idx].y, 8 * size_t(it.T) * dy, hipMemcpyHostToDevice, s));
+
+  std::vector<airpf::FwdArgs> fa;
+  std::vector<airpf::BwdArgs> ba;
+  std::vector<int2> bmap;
+  // launch helper: tile the given items, upload arguments and block map, zero
+  // their barrier flags, launch forward (mode 0) or reverse (mode 1)
+  auto launch = [&](std::vector<Item*>& act, const std::vector<int64_t>& steps, int mode,
+                    const std::function<void(Item&, airpf::FwdArgs&)>& fwd_fill,
+                    const std::function<void(Item&, airpf::BwdArgs&)>& bwd_fill) -> airpf_status {
+    if (act.empty()) return AIRPF_OK;
+    if (!tile(act, steps, mode == 0 ? cap_f : cap_b)) return AIRPF_E_UNSUPPORTED;
+    bmap.clear();
+    fa.clear();
+    ba.clear();
+    int c_max = 1, G_max = 1;
+    for (size_t i = 0; i < act.size(); ++i) {
+      Item& it = *act[i];
+      for (int b = 0; b < it.G; ++b) bmap.push_back(make_int2(int(i), b));
+      c_max = std::max(c_max, it.m / it.G);
+      G_max = std::max(G_max, it.G);
+      HIP_OK(airpf::fill_u32(at(it.o_flags), 0u, it.G, s));
+      if (mode == 0) {
+        airpf::FwdArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.mp = it.mp; a.y = y_dev ? it.y_dev : static_cast<const double*>(at(it.o_y));
+        a.T = it.T; a.m = it.m; a.N = it.N; a.S = it.S; a.TP = it.TP; a.G = it.G; a.c = it.m / it.G;
+        a.lc = ilog2(a.c); a.dy = dy; a.seed = it.seed; a.tau = opt.tau; a.cst_q = it.cst_q;
+        a.shortcut_all = opt.tau > 1.0 + 1e-9;
+        for (int p = 0; p < 2; ++p) {
+          a.x1[p] = at(it.o_x1[p]);
+          a.tree[p] = static_cast<double*>(at(it.o_tree[p]));
+          a.part[p] = static_cast<double*>(at(it.o_part[p]));
+        }
+        a.bar = static_cast<unsigned*>(at(it.o_flags));
+        a.status = d_status;
+        a.out_logz = static_cast<double*>(at(o_logz)) + (&it - items.data());
+        a.n0 = 0; a.n1 = it.T;
+        fwd_fill(it, a);
+        fa.push_back(a);
+      } else {
+        airpf::BwdArgs b;
+        std::memset(&b, 0, sizeof(b));
+        b.mp = it.mp; b.y = y_dev ? it.y_dev : static_cast<const double*>(at(it.o_y));
+        b.T = it.T; b.m = it.m; b.N = it.N; b.S = it.S; b.G = it.G; b.c = it.m / it.G; b.lc = ilog2(b.c);
+        b.TP = pow2_ceil_i((it.N + ppt_b - 1) / ppt_b);
+        b.dy = dy; b.seed = it.seed;
+        b.log_mN = std::log(static_cast<double>(it.m) * static_cast<double>(it.N));
+        b.c_log = it.cst_q + 40.0 * std::log(2.0) + std::log(static_cast<double>(it.N));
+        b.logz = static_cast<const double*>(at(o_logz)) + (&it - items.data());
+        b.rec_x = at(it.o_recx);
+        b.rec_anc = static_cast<const uint16_t*>(at(it.o_reca));
+        b.pi_all = static_cast<const int32_t*>(at(it.o_pi));
+        b.sstar_all = static_cast<const int32_t*>(at(it.o_sstar));
+        b.lpre_all = static_cast<const double*>(at(it.o_lpre));
+        for (int p = 0; p < 2; ++p) { b.lam[p] = at(it.o_lam[p]); b.del[p] = at(it.o_del[p]); }
+        b.gisl = static_cast<double*>(at(it.o_gisl));
+        b.bar = static_cast<unsigned*>(at(it.o_flags));
+        b.status = d_status;
+        bwd_fill(it, b);
+        ba.push_back(b);
+      }
+    }
+    // the batched forward kernel's LDS plan must cover every problem's tiling
+    airpf::BatchLaunch L = BL;
+    L.blocks = int(bmap.size());
+    L.smem = mode == 0 ? airpf::forward_smem(fp64, ppt_f, dx, c_max, G_max) : airpf::backward_smem(fp64, ppt_b, dx);
+    void* d_args = at(o_args);
+    if (mode == 0) HIP_OK(hipMemcpyAsync(d_args, fa.data(), sizeof(airpf::FwdArgs) * fa.size(), hipMemcpyHostToDevice, s));
+    else HIP_OK(hipMemcpyAsync(d_args, ba.data(), sizeof(airpf::BwdArgs) * ba.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(at(o_bmap), bmap.data(), sizeof(int2) * bmap.size(), hipMemcpyHostToDevice, s));
+    L.probs = d_args;
+    L.bmap = static_cast<const int2*>(at(o_bmap));
+    const hipError_t e = mode == 0 ? airpf::launch_forward_batch(L) : airpf::launch_backward_batch(L);
+    // the argument and map uploads are reused by the next launch: wait here
+    HIP_OK(hipStreamSynchronize(s));
+    return e == hipSuccess ? AIRPF_OK : AIRPF_E_DEVICE;
+  };
+
+  std::vector<Item*> all;
+  std::vector<int64_t> steps;
+  for (Item& it : items) { all.push_back(&it); steps.push_back(it.T); }
+  HIP_OK(hipEventRecord(ctx->ev[0], s));
+  auto no_bwd = [](Item&, airpf::BwdArgs&) {};
+  airpf_status st = launch(all, steps, 0, [&](Item& it, airpf::FwdArgs& a) {
+    if (!want_score) return;
+    a.tr_pi = static_cast<int32_t*>(at(it.o_pi));
+    a.tr_sstar = static_cast<int32_t*>(at(it.o_sstar));
+    a.tr_lpre = static_cast<double*>(at(it.o_lpre));
+    a.ck_every = it.K;
+    a.ck_x = at(it.o_ckx);
+    a.ck_L = static_cast<double*>(at(it.o_ckL));
+    if (it.C == 1) { a.rec_x = at(it.o_recx); a.rec_anc = static_cast<uint16_t*>(at(it.o_reca)); }
+  }, no_bwd);
+  if (st != AIRPF_OK) { for (const Item& it : items) item_status[it.idx] = st; return st; }
+
+  if (want_score) {
+    for (Item& it : items) HIP_OK(airpf::fill_u32(at(it.o_gisl), 0u, 2 * int64_t(it.m) * Pn, s));
+    int64_t Cmax = 0;
+    for (const Item& it : items) Cmax = std::max(Cmax, it.C);
+    for (int64_t j = 0; j < Cmax && st == AIRPF_OK; ++j) {
+      std::vector<Item*> act, rec;
+      std::vector<int64_t> st_act, st_rec;
+      for (Item& it : items) {
+        const int64_t cidx = it.C - 1 - j;
+        if (cidx < 0) continue;
+        const int64_t lo = cidx * it.K, hi = std::min(it.T, (cidx + 1) * it.K);
+        act.push_back(&it);
+        st_act.push_back(hi - lo);
+        if (it.C > 1) { rec.push_back(&it); st_rec.push_back(hi - lo); }
+      }
+      st = launch(rec, st_rec, 0, [&](Item& it, airpf::FwdArgs& a) {
+        const int64_t cidx = it.C - 1 - j;
+        a.n0 = cidx * it.K; a.n1 = std::min(it.T, (cidx + 1) * it.K);
+        a.replay_pi = 1; a.ck_in = a.n0 > 0 ? 1 : 0; a.ck_every = it.K;
+        a.ck_x = at(it.o_ckx); a.ck_L = static_cast<double*>(at(it.o_ckL));
+        a.tr_pi = static_cast<int32_t*>(at(it.o_pi));
+        a.rec_x = at(it.o_recx); a.rec_anc = static_cast<uint16_t*>(at(it.o_reca));
+      }, no_bwd);
+      if (st != AIRPF_OK) break;
+      st = launch(act, st_act, 1, [](Item&, airpf::FwdArgs&) {}, [&](Item& it, airpf::BwdArgs& b) {
+        const int64_t cidx = it.C - 1 - j;
+        b.n_lo = cidx * it.K; b.n_hi = std::min(it.T, (cidx + 1) * it.K);
+      });
+    }
+    if (st == AIRPF_OK)
+      for (Item& it : items)
+        HIP_OK(airpf::launch_island_grad_sum(static_cast<const double*>(at(it.o_gisl)), it.m, Pn,
+                                             static_cast<double*>(at(it.o_gsum)), s));
+  }
+  HIP_OK(hipEventRecord(ctx->ev[1], s));
+  if (st != AIRPF_OK) { for (const Item& it : items) item_status[it.idx] = st; return st; }
+
+  std::vector<double> lz(items.size());
+  int kstatus = 0;
+  HIP_OK(hipMemcpyAsync(lz.data(), at(o_logz), 8 * lz.size(), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&kstatus, d_status, 4, hipMemcpyDeviceToHost, s));
+  if (want_score)
+    for (const Item& it : items)
+      HIP_OK(hipMemcpyAsync(grad_out + size_t(it.idx) * Pn, at(it.o_gsum), 8 * size_t(Pn), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (kstatus != 0) {
+    for (const Item& it : items) item_status[it.idx] = AIRPF_E_DEVICE;
+    return AIRPF_E_DEVICE;
+  }
+  float ms = 0.0f;
+  HIP_OK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+  ctx->last_kernel_ms = ms;
+  for (size_t i = 0; i < items.size(); ++i) log_z_out[items[i].idx] = lz[i];
   return AIRPF_OK;
 }

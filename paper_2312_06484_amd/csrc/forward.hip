@@ -499,6 +499,74 @@ hipError_t launch_forward(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan) {
   return L.fp64 ? dispatch_model<double>(L, a, plan) : dispatch_model<float>(L, a, plan);
 }
 
+// ------------------------------------------------------------ batched launches
+
+int forward_ppt(int kind, int dx, int n) {
+  const int DX = kind == 2 ? dx : 1;
+  if (DX % 4 == 0) {
+    if (n <= 256) return 1;
+    if (n <= 512) return 2;
+  } else if (DX % 2 == 0) {
+    if (n <= 512) return 2;
+  }
+  return n <= 1024 ? 4 : 8;
+}
+
+size_t forward_smem(int fp64, int ppt, int dx, int c, int G) {
+  return fwd_smem_bytes(fp64 ? 8 : 4, ppt, dx, c, G);
+}
+
+template <class Model, typename Store, int PPT>
+static hipError_t batch_fwd_t(const BatchLaunch& L, int* cap) {
+  auto kern = forward_batch_kernel<Model, Store, PPT>;
+  if (cap) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, L.smem);
+    *cap = per_cu * L.num_cus;
+    return e;
+  }
+  const void* probs = L.probs;
+  const int2* bmap = L.bmap;
+  void* args[] = {&probs, &bmap};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(L.blocks), dim3(kBlock), args,
+                                    static_cast<unsigned>(L.smem), L.stream);
+}
+
+template <class Model, typename Store>
+static hipError_t batch_fwd_ppt(const BatchLaunch& L, int* cap) {
+  switch (forward_ppt(L.kind, L.dx, L.n_max)) {
+    case 1: if constexpr (Model::DX % 4 == 0) return batch_fwd_t<Model, Store, 1>(L, cap); break;
+    case 2: if constexpr (Model::DX % 2 == 0) return batch_fwd_t<Model, Store, 2>(L, cap); break;
+    case 4: return batch_fwd_t<Model, Store, 4>(L, cap);
+    case 8: return batch_fwd_t<Model, Store, 8>(L, cap);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename Store>
+static hipError_t batch_fwd_model(const BatchLaunch& L, int* cap) {
+  switch (L.kind) {
+    case 0: return batch_fwd_ppt<LG1, Store>(L, cap);
+    case 1: return batch_fwd_ppt<SV, Store>(L, cap);
+    case 2:
+      switch (L.dx) {
+        case 2: return batch_fwd_ppt<LGD<2>, Store>(L, cap);
+        case 3: return batch_fwd_ppt<LGD<3>, Store>(L, cap);
+        case 4: return batch_fwd_ppt<LGD<4>, Store>(L, cap);
+        case 8: return batch_fwd_ppt<LGD<8>, Store>(L, cap);
+      }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t forward_batch_capacity(const BatchLaunch& L, int* blocks) {
+  return L.fp64 ? batch_fwd_model<double>(L, blocks) : batch_fwd_model<float>(L, blocks);
+}
+
+hipError_t launch_forward_batch(const BatchLaunch& L) {
+  return L.fp64 ? batch_fwd_model<double>(L, nullptr) : batch_fwd_model<float>(L, nullptr);
+}
+
 // ------------------------------------------------------------ small helpers
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {

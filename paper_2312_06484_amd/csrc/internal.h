@@ -81,6 +81,27 @@ hipError_t launch_forward(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
 hipError_t launch_backward(const FwdLaunch& L, const BwdArgs& a, int* max_blocks_out);
 hipError_t launch_island_grad_sum(const double* gisl, int m, int P, double* out, hipStream_t st);
 hipError_t fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t st);
+
+// ---- batched launches: one cooperative grid, block b runs local block
+// bmap[b].y of problem bmap[b].x ----
+struct BatchLaunch {
+  int kind, dx, fp64;
+  int n_max;                  // largest N of the batch (picks particles per lane)
+  int num_cus;
+  size_t smem;                // dynamic LDS per block
+  int blocks;                 // total blocks
+  const void* probs;          // device array of FwdArgs or BwdArgs
+  const int2* bmap;           // device [blocks]
+  hipStream_t stream;
+};
+int forward_ppt(int kind, int dx, int n_max);
+size_t forward_smem(int fp64, int ppt, int dx, int c, int G);
+hipError_t forward_batch_capacity(const BatchLaunch& L, int* blocks);   // co-resident blocks at L.smem
+hipError_t launch_forward_batch(const BatchLaunch& L);
+int backward_ppt(int kind, int dx, int n_max);                          // 0: unsupported
+size_t backward_smem(int fp64, int ppt, int dx);
+hipError_t backward_batch_capacity(const BatchLaunch& L, int* blocks);
+hipError_t launch_backward_batch(const BatchLaunch& L);
 hipError_t launch_debug_eval(int which, int64_t n, const double* in, const uint32_t* in_u32, double* out,
                              double* out2, uint32_t* out_u32, hipStream_t st);
 

@@ -352,6 +352,67 @@ static hipError_t dispatch_bm(const FwdLaunch& L, const BwdArgs& a, int* plan_p)
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------------------ batched launches
+
+int backward_ppt(int kind, int dx, int n) {
+  const int DX = kind == 2 ? dx : 1;
+  if (DX % 4 == 0) return n <= 256 ? 1 : (n <= 512 ? 2 : 0);
+  if (DX % 2 == 0) return n <= 512 ? 2 : 0;
+  return n <= 1024 ? 4 : 0;
+}
+
+size_t backward_smem(int fp64, int ppt, int dx) { return bwd_smem_bytes(fp64 ? 8 : 4, ppt, dx); }
+
+template <class Model, typename Store, int PPT>
+static hipError_t batch_bwd_t(const BatchLaunch& L, int* cap) {
+  auto kern = backward_batch_kernel<Model, Store, PPT>;
+  if (cap) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, L.smem);
+    *cap = per_cu * L.num_cus;
+    return e;
+  }
+  const void* probs = L.probs;
+  const int2* bmap = L.bmap;
+  void* args[] = {&probs, &bmap};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(L.blocks), dim3(kBlock), args,
+                                    static_cast<unsigned>(L.smem), L.stream);
+}
+
+template <class Model, typename Store>
+static hipError_t batch_bwd_ppt(const BatchLaunch& L, int* cap) {
+  switch (backward_ppt(L.kind, L.dx, L.n_max)) {
+    case 1: if constexpr (Model::DX % 4 == 0) return batch_bwd_t<Model, Store, 1>(L, cap); break;
+    case 2: if constexpr (Model::DX % 2 == 0) return batch_bwd_t<Model, Store, 2>(L, cap); break;
+    case 4: if constexpr (Model::DX % 4 != 0 && Model::DX % 2 != 0) return batch_bwd_t<Model, Store, 4>(L, cap); break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename Store>
+static hipError_t batch_bwd_model(const BatchLaunch& L, int* cap) {
+  switch (L.kind) {
+    case 0: return batch_bwd_ppt<LG1, Store>(L, cap);
+    case 1: return batch_bwd_ppt<SV, Store>(L, cap);
+    case 2:
+      switch (L.dx) {
+        case 2: return batch_bwd_ppt<LGD<2>, Store>(L, cap);
+        case 3: return batch_bwd_ppt<LGD<3>, Store>(L, cap);
+        case 4: return batch_bwd_ppt<LGD<4>, Store>(L, cap);
+        case 8: return batch_bwd_ppt<LGD<8>, Store>(L, cap);
+      }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t backward_batch_capacity(const BatchLaunch& L, int* blocks) {
+  return L.fp64 ? batch_bwd_model<double>(L, blocks) : batch_bwd_model<float>(L, blocks);
+}
+
+hipError_t launch_backward_batch(const BatchLaunch& L) {
+  return L.fp64 ? batch_bwd_model<double>(L, nullptr) : batch_bwd_model<float>(L, nullptr);
+}
+
 hipError_t launch_island_grad_sum(const double* gisl, int m, int P, double* out, hipStream_t st) {
   island_grad_sum_kernel<<<dim3(1), dim3(kBlock), 0, st>>>(gisl, m, P, out);
   return hipGetLastError();

@@ -1,0 +1,86 @@
+"""Batched multi-theta launch: every item of a batch is bit-identical to the
+same problem run alone (forward log Zhat and path-space score), whatever the
+mix of T, m, N and theta in the batch; invalid items are reported and
+skipped without disturbing the others."""
+import numpy as np
+import pytest
+
+from paper_2312_06484_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2312_06484_amd import airpf
+    c = airpf.Context(0)
+    yield c
+    c.close()
+
+
+def sv_batch(n, seed=0):
+    g = np.random.default_rng(seed)
+    thetas = W.sv_chain_thetas(n)
+    Ts = [40, 25, 60]
+    Ns = [32, 64, 128, 256, 37]
+    ms = [16, 64, 256]
+    ys = {T: W.sv_data(T) for T in Ts}
+    items = []
+    for i in range(n):
+        T = Ts[i % 3]
+        items.append(dict(theta=thetas[i], y=ys[T], m=ms[(i // 3) % 3], N=Ns[(i // 2) % 5], seed=int(g.integers(1, 1 << 40))))
+    return items
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_batch_forward_matches_single(ctx, fp64):
+    items = sv_batch(12, seed=1)
+    st, lz, _, ist = ctx.run_batch(1, items, tau=0.5, fp64=fp64)
+    assert (ist == 0).all()
+    for it, v in zip(items, lz):
+        _, ref = ctx.run(1, it["theta"], it["y"], it["m"], it["N"], it["seed"], tau=0.5, fp64=fp64)
+        assert v == ref
+
+
+@pytest.mark.parametrize("K", [0, 7])
+def test_batch_score_matches_single(ctx, K):
+    items = sv_batch(9, seed=2)
+    st, lz, gr, ist = ctx.run_batch(1, items, tau=0.6, want_score=True, ckpt_every=K)
+    assert (ist == 0).all()
+    for it, v, g in zip(items, lz, gr):
+        _, ref, gref = ctx.score(1, it["theta"], it["y"], it["m"], it["N"], it["seed"], tau=0.6, ckpt_every=K)
+        assert v == ref
+        assert np.array_equal(g, gref)
+
+
+def test_batch_lgd_and_invalid_items(ctx):
+    from paper_2312_06484_amd import airpf
+    A, H = W.lgd_model(dx=8, dy=4)
+    y = W.lgd_data(A, H, 15)
+    cst = W.lgd_consts(H)
+    items = [dict(theta=A.reshape(-1), y=y, m=16, N=64, seed=1),
+             dict(theta=A.reshape(-1), y=y, m=3, N=64, seed=2),          # m not a power of two
+             dict(theta=(0.9 * A).reshape(-1), y=y, m=64, N=32, seed=3),
+             dict(theta=A.reshape(-1)[:10], y=y, m=16, N=64, seed=4)]   # wrong d_theta
+    st, lz, gr, ist = ctx.run_batch(2, items, tau=0.7, dx=8, dy=4, consts=cst, want_score=True)
+    assert list(ist) == [0, airpf.E_INVALID_ARG, 0, airpf.E_INVALID_ARG]
+    assert np.isnan(lz[1]) and np.isnan(lz[3]) and np.isnan(gr[1]).all()
+    for i in (0, 2):
+        it = items[i]
+        _, ref, gref = ctx.score(2, it["theta"], y, it["m"], it["N"], it["seed"], tau=0.7, dx=8, dy=4, consts=cst)
+        assert lz[i] == ref and np.array_equal(gr[i], gref)
+
+
+def test_batch_of_sixty_four_proposals_shape(ctx):
+    # the 64-chain proposal workload's size mix (T in {500,1000,2000},
+    # N in {64..512}, m in {256,1024}) shortened to T/25 so a single-item
+    # reference run of each stays cheap
+    items = []
+    for it in W.batch_c4(64):
+        T = it["T"] // 25
+        items.append(dict(theta=it["theta"], y=W.sv_data(it["T"])[:T], m=it["m"], N=it["N"], seed=it["seed"]))
+    st, lz, _, ist = ctx.run_batch(1, items, tau=0.3)
+    assert (ist == 0).all()
+    for it, v in list(zip(items, lz))[::7]:
+        _, ref = ctx.run(1, it["theta"], it["y"], it["m"], it["N"], it["seed"], tau=0.3)
+        assert v == ref

@@ -91,3 +91,18 @@ def test_score_unsupported_and_invalid(ctx):
     assert st == airpf.E_UNSUPPORTED
     st, lz, g = ctx.score(0, W.LG1_THETA, y, 3, 4, 1, raise_on_error=False)
     assert st == airpf.E_INVALID_ARG
+
+
+def test_torch_autograd_wrapper(ctx):
+    import torch
+    from paper_2312_06484_amd import torch_ops, workloads as W
+    y = W.sv_data(20)
+    prob = torch_ops.Problem(1, y, 32, 64, 9, tau=0.4)
+    th = torch.tensor(W.SV_THETA, dtype=torch.float64, requires_grad=True)
+    lz = torch_ops.log_z(th, prob)
+    lz.backward()
+    _, ref, gref = ctx.score(1, W.SV_THETA, y, 32, 64, 9, tau=0.4)
+    assert float(lz) == ref
+    assert np.array_equal(th.grad.numpy(), gref)
+    with torch.no_grad():
+        assert float(torch_ops.log_z(th.detach(), prob)) == ref
