@@ -84,6 +84,58 @@ def cpu_baseline(wl, y, gpu_ctx, budget_steps):
         abs(lg - lo)
 
 
+def measure_extras(ctx, torch):
+    """Forward+score on the stochastic-volatility workload, and the 64-chain
+    proposal batch (forward+score) run in one batched call versus one theta
+    at a time.  Each is timed once after one warm-up call."""
+    from paper_2312_06484_amd import workloads as W
+    out = {}
+    # forward + path-space score, SV, T = 2000, 4096 x 128, checkpoints every 100 steps
+    T, m, N = 2000, 4096, 128
+    y = W.sv_data(T)
+    yd = torch.tensor(y, dtype=torch.float64, device="cuda")
+    run = lambda seed: ctx.score(1, W.SV_THETA, None, m, N, seed, tau=0.3, ckpt_every=100,
+                                 y_device_ptr=yd.data_ptr(), T=T)
+    run(99)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, lz, g = run(1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["fwd_score_sv_t2000_m4096_n128_k100"] = {
+        "value": m * N * T / dt, "unit": "particle-steps/s", "ms": dt * 1e3, "device_ms": ctx.last_kernel_ms(),
+        "log_z": lz, "grad": list(g)}
+    # 64 chains' proposals, uneven T, m, N: forward + score
+    items = W.batch_c4(64)
+    ydev = {}
+    probs = []
+    for it in items:
+        if it["T"] not in ydev:
+            ydev[it["T"]] = torch.tensor(W.sv_data(it["T"]), dtype=torch.float64, device="cuda")
+        probs.append(dict(theta=it["theta"], y=ydev[it["T"]].data_ptr(), T=it["T"], m=it["m"], N=it["N"],
+                          seed=it["seed"]))
+    total = sum(it["m"] * it["N"] * it["T"] for it in items)
+    ctx.run_batch(1, probs[:4], tau=0.3, want_score=True, ckpt_every=100, y_on_device=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, lzb, grb, ist = ctx.run_batch(1, probs, tau=0.3, want_score=True, ckpt_every=100, y_on_device=True)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    out["batched_sv_64_chains_fwd_score"] = {"value": total / tb, "unit": "particle-steps/s", "ms": tb * 1e3,
+                                             "particle_steps": total, "items_ok": int((ist == 0).sum())}
+    t0 = time.perf_counter()
+    same = True
+    for p, lzv, gv in zip(probs, lzb, grb):
+        _, l1, g1 = ctx.score(1, p["theta"], None, p["m"], p["N"], p["seed"], tau=0.3, ckpt_every=100,
+                              y_device_ptr=p["y"], T=p["T"])
+        same = same and (l1 == lzv) and bool((g1 == gv).all())
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    out["plain_sv_64_chains_fwd_score"] = {"value": total / tp, "unit": "particle-steps/s", "ms": tp * 1e3,
+                                           "batched_speedup": tp / tb, "batched_items_bit_identical": same}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +145,8 @@ def main():
     ap.add_argument("--tau", type=float, default=0.3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the forward+score and batched-vs-plain measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the "
                          "reference reading for the HBM byte counters) and exit")
@@ -159,6 +213,8 @@ def main():
         cpu, d = cpu_baseline(wl, y, ctx, args.cpu_sample_steps)
         err["max_abs_vs_oracle_on_sample"] = d
 
+    extras = None if args.no_extras else measure_extras(ctx, torch)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -181,6 +237,7 @@ def main():
                      "bytes_per_particle_step": bpp},
         "logz_err": err,
         "cpu_baseline": cpu,
+        "modes": extras,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
