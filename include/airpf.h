@@ -18,7 +18,8 @@
  *
  * Conventions
  *   - N is the number of particles PER ISLAND (the paper's M); m is the
- *     number of islands and must be a power of two; 1 <= N <= 2048.
+ *     number of islands and must be a power of two; 1 <= N <= 2048;
+ *     m <= 65536 on one device (larger m: AIRPF_E_UNSUPPORTED).
  *   - Arrays are plain host pointers unless a flag says otherwise; the
  *     library copies what it needs and keeps no pointer after returning.
  *   - The context owns all device workspaces; they grow on demand and are

@@ -32,6 +32,9 @@ struct DevBuf {
 };
 
 bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
+// at most 256 blocks of at most 256 islands each per problem
+constexpr int kMaxIslands = 65536;
+constexpr int kMaxBlocks = 256;
 int ilog2(int64_t v) { int s = 0; while ((int64_t(1) << s) < v) ++s; return s; }
 bool all_finite(const double* p, int64_t n) {
   for (int64_t i = 0; i < n; ++i) if (!std::isfinite(p[i])) return false;
@@ -193,8 +196,8 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
                      const airpf_options* opt_in, double* log_z_out, int max_blocks, Prepared* P) {
   set_nan(log_z_out);
   if (!ctx || !model || !theta || !y || !log_z_out) return AIRPF_E_INVALID_ARG;
-  if (T < 1 || T > (int64_t(1) << 30) || !is_pow2(m) || m > (1 << 24) || N < 1 || N > 2048)
-    return AIRPF_E_INVALID_ARG;
+  if (T < 1 || T > (int64_t(1) << 30) || !is_pow2(m) || N < 1 || N > 2048) return AIRPF_E_INVALID_ARG;
+  if (m > kMaxIslands) return AIRPF_E_UNSUPPORTED;
   P->opt = opt_in ? *opt_in : default_options();
   const airpf_options& opt = P->opt;
   if (!(opt.tau == opt.tau)) return AIRPF_E_INVALID_ARG;
@@ -225,7 +228,11 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   airpf::FwdLaunch& L = P->L;
   L.kind = model->kind; L.dx = P->dx; L.fp64 = opt.precision == AIRPF_FP64;
   L.num_cus = ctx->num_cus; L.max_blocks = max_blocks; L.plan_only = 1; L.stream = s;
-  HIP_OK(airpf::launch_forward(L, a, &P->plan));
+  {
+    const hipError_t e = airpf::launch_forward(L, a, &P->plan);
+    if (e == hipErrorInvalidValue) return AIRPF_E_UNSUPPORTED;   // no tiling fits the LDS plan
+    if (e != hipSuccess) return AIRPF_E_DEVICE;
+  }
 
   const size_t store = L.fp64 ? 8 : 4;
   const size_t nstate = size_t(m) * N * P->dx * store;
@@ -316,7 +323,7 @@ extern "C" airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, cons
                                   const double* y, int64_t T, int32_t m, int32_t N, uint64_t seed,
                                   const airpf_options* opt_in, double* log_z_out, airpf_trace* trace) {
   Prepared P;
-  ST_OK(prepare(ctx, model, theta, d_theta, y, T, m, N, seed, opt_in, log_z_out, 1024, &P));
+  ST_OK(prepare(ctx, model, theta, d_theta, y, T, m, N, seed, opt_in, log_z_out, kMaxBlocks, &P));
   ST_OK(attach_trace(ctx, P, trace));
   P.L.plan_only = 0;
   HIP_OK(hipEventRecord(ctx->ev[0], ctx->stream));
@@ -358,7 +365,7 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
     }
   }
   Prepared P;
-  ST_OK(prepare(ctx, model, theta, d_theta, y, T, m, N, seed, opt_in, log_z_out, bwd_max < 1024 ? bwd_max : 1024, &P));
+  ST_OK(prepare(ctx, model, theta, d_theta, y, T, m, N, seed, opt_in, log_z_out, bwd_max < kMaxBlocks ? bwd_max : kMaxBlocks, &P));
   ST_OK(attach_trace(ctx, P, trace));
   airpf::FwdArgs& a = P.a;
   hipStream_t s = ctx->stream;
@@ -600,9 +607,10 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
     if (want_score) for (int q = 0; q < Pn; ++q) grad_out[size_t(i) * Pn + q] = std::nan("");
     Item it;
     airpf_status st = AIRPF_OK;
-    if (!pr.theta || !pr.y || pr.T < 1 || pr.T > (int64_t(1) << 30) || !is_pow2(pr.m) || pr.m > (1 << 24) || pr.N < 1 ||
-        pr.N > 2048)
+    if (!pr.theta || !pr.y || pr.T < 1 || pr.T > (int64_t(1) << 30) || !is_pow2(pr.m) || pr.N < 1 || pr.N > 2048)
       st = AIRPF_E_INVALID_ARG;
+    else if (pr.m > kMaxIslands)
+      st = AIRPF_E_UNSUPPORTED;
     if (st == AIRPF_OK) st = prepare_model(model, pr.theta, pr.d_theta, pr.N, &it.mp, &it.cst_q, &dx, &dy);
     if (st == AIRPF_OK && pr.d_theta != Pn) st = AIRPF_E_INVALID_ARG;
     if (st == AIRPF_OK && !y_dev && !all_finite(pr.y, pr.T * dy)) st = AIRPF_E_INVALID_ARG;

@@ -238,6 +238,30 @@ __device__ EnfRec block_pair_enf(double* M, double* A, double* B, double* wM, do
   return r;
 }
 
+// One wave reduces n <= 256 ENF records (n a power of two) by the
+// adjacent-pair tree: lane l first joins its aligned run of n/64 records,
+// then lanes join in a butterfly over xor 1, 2, ..., 32.  The join is
+// commutative bit for bit, so lane l ^ d holds exactly the other half of
+// every pair: the result is that of the adjacent-pair tree, in every lane.
+// `rec(i)` yields record i.
+template <class F>
+__device__ __forceinline__ EnfRec wave_reduce_enf(int n, F rec) {
+  const int lane = threadIdx.x & 63;
+  EnfRec r{ninf(), 0.0, 0.0};
+  if (n <= 64) {
+    if (lane < n) r = rec(lane);
+  } else if (n == 128) {
+    r = enf_join(rec(2 * lane), rec(2 * lane + 1));
+  } else {
+    r = enf_join(enf_join(rec(4 * lane), rec(4 * lane + 1)), enf_join(rec(4 * lane + 2), rec(4 * lane + 3)));
+  }
+  for (int d = 1; d < 64; d <<= 1) {
+    const EnfRec o{__shfl_xor(r.M, d, 64), __shfl_xor(r.a, d, 64), __shfl_xor(r.b, d, 64)};
+    r = enf_join(r, o);
+  }
+  return r;
+}
+
 // block-wide reductions with a fixed pattern (identical result in every block)
 __device__ double block_max(double v, double* red) {
   for (int d = 1; d < 64; d <<= 1) v = fmax(v, __shfl_xor(v, d, 64));

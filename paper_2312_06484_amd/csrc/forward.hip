@@ -57,10 +57,12 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   __shared__ uint64_t bc_u[kBlock];
   __shared__ int bc_i[kBlock];
   __shared__ int s_sstar;
+  __shared__ double s_enf[kWaves], s_encmax[kWaves];
 
   const int tid = threadIdx.x;
   const int TP = a.TP, tpb = kBlock / TP;
   const int team = tid / TP, lane = tid & (TP - 1);
+  const int wave = tid >> 6, lane64 = tid & 63;
   const int m = a.m, N = a.N, S = a.S, c = a.c, lc = a.lc, G = a.G;
   const int kbase = bid * c;
   const Key key = make_key(a.seed);
@@ -71,23 +73,26 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   int* sA = reinterpret_cast<int*>(sC + kBlock * PPT);                             // [kBlock*PPT]
   double* lv = reinterpret_cast<double*>(sA + kBlock * PPT);                       // [2c]
   double* up = lv + 2 * c;                                                        // [2G]
-  double* scr = up + 2 * G;                                                       // [max(12c, 6G)]
 
   unsigned epoch = 0;
 
-  // levels lc+1 .. S+1 of the island tree in `up` from the G published block
-  // roots (identical in every block); returns the root, log of the mean
-  // island weight
-  auto upper_tree = [&](int par) -> double {
-    for (int b = tid; b < G; b += kBlock) up[b] = get(a.tree[par] + tree_off(m, lc + 1) + b);
-    __syncthreads();
-    for (int u = 1; lc + 1 + u <= S + 1; ++u) {
+  // levels lc+1 .. `level` of the island tree in `up`, built on demand from
+  // the G published block roots (identical in every block); up_top is the
+  // highest level built for the current cascade
+  int up_top = 0;
+  auto build_upper_to = [&](int par, int level) {
+    if (up_top < lc + 1) {
+      for (int b = tid; b < G; b += kBlock) up[b] = get(a.tree[par] + tree_off(m, lc + 1) + b);
+      __syncthreads();
+      up_top = lc + 1;
+    }
+    for (; up_top < level; ++up_top) {
+      const int u = up_top + 1 - (lc + 1);
       const int cnt = G >> u;
       const int o_prev = 2 * G - ((2 * G) >> (u - 1)), o = 2 * G - ((2 * G) >> u);
       for (int i = tid; i < cnt; i += kBlock) up[o + i] = pair_mean(up[o_prev + 2 * i], up[o_prev + 2 * i + 1]);
       __syncthreads();
     }
-    return up[2 * G - 2];
   };
 
   auto lt_value = [&](int par, int level, int idx) -> double {   // tree value, level >= 1
@@ -104,48 +109,56 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     }
     if (n > a.n0 && !replay) {
       // ---- cascade of step n-1 (every block, identical) ----
-      const double lroot = upper_tree(ppar);                         // log mean_k W_k
-      if (lroot == ninf()) {                                         // every island dead
-        if (bid == 0 && tid == 0) *a.out_logz = ninf();
-        return;
-      }
+      up_top = 0;
       int sstar = 0;
       if (a.shortcut_all) {
+        // tau > 1: every stage interacts (ENF <= 1 always)
+        build_upper_to(ppar, S + 1);
+        if (up[2 * G - 2] == ninf()) {                               // every island dead
+          if (bid == 0 && tid == 0) *a.out_logz = ninf();
+          return;
+        }
         sstar = S;
       } else {
-        // stages interact while ENF < tau; a stage that does not interact leaves
-        // every weight unchanged, so every later stage sees the same ENF and
-        // does not interact either (traced as that same value)
-        for (int s = 1; s <= S; ++s) {
-          // ENF of the weights after s-1 interacting stages: every island holds
-          // its 2^{s-1}-block mean, so sum_k W_k = 2^{s-1} sum_b w_b and
-          // sum_k W_k^2 = 2^{s-1} sum_b w_b^2 over the level-s tree values
-          EnfRec r;
-          double* rm = scr;
-          double* ra = scr + G;
-          double* rb = scr + 2 * G;
-          double* w0 = scr + 3 * G;
-          if (s <= lc + 1) {
-            const double* ps = a.part[ppar] + static_cast<int64_t>(s - 1) * 3 * G;
-            for (int b = tid; b < G; b += kBlock) { rm[b] = get(ps + b); ra[b] = get(ps + G + b); rb[b] = get(ps + 2 * G + b); }
-            __syncthreads();
-            r = block_pair_enf(rm, ra, rb, w0, w0 + G / 2, w0 + G, G);
-          } else {
-            const int cnt = G >> (s - lc - 1);
-            const double* lvl = up + 2 * G - ((2 * G) >> (s - lc - 1));
-            for (int i = tid; i < cnt; i += kBlock) { const EnfRec e = enf_leaf(lvl[i]); rm[i] = e.M; ra[i] = e.a; rb[i] = e.b; }
-            __syncthreads();
-            r = block_pair_enf(rm, ra, rb, w0, w0 + G / 2, w0 + G, cnt);
+        // ENF of stages s0 .. s0+3 at once, one per wave; a stage that does not
+        // interact leaves every weight unchanged, so every later stage sees the
+        // same ENF and does not interact either (traced as that same value)
+        bool stop = false;
+        for (int s0 = 1; s0 <= S && !stop; s0 += kWaves) {
+          const int s_hi = s0 + kWaves - 1 < S ? s0 + kWaves - 1 : S;
+          if (s_hi > lc + 1) build_upper_to(ppar, s_hi);
+          const int sw = s0 + wave;
+          if (sw <= s_hi) {
+            EnfRec r;
+            if (sw <= lc + 1) {
+              const double* ps = a.part[ppar] + static_cast<int64_t>(sw - 1) * 3 * G;
+              r = wave_reduce_enf(G, [&](int i) { return EnfRec{get(ps + i), get(ps + G + i), get(ps + 2 * G + i)}; });
+            } else {
+              const double* lvl = up + 2 * G - ((2 * G) >> (sw - lc - 1));
+              r = wave_reduce_enf(G >> (sw - lc - 1), [&](int i) { return enf_leaf(lvl[i]); });
+            }
+            // after s-1 interacting stages every island holds its 2^{s-1}-block
+            // mean: sum_k W_k = 2^{s-1} sum_b w_b, sum_k W_k^2 = 2^{s-1} sum_b w_b^2
+            const double blk = static_cast<double>(1 << (sw - 1));
+            const double am = (blk * r.a) / static_cast<double>(m), bm = (blk * r.b) / static_cast<double>(m);
+            if ((tid & 63) == 0) { s_enf[wave] = (am * am) / bm; s_encmax[wave] = r.M; }
           }
-          const double blk = static_cast<double>(1 << (s - 1));
-          const double am = (blk * r.a) / static_cast<double>(m), bm = (blk * r.b) / static_cast<double>(m);
-          const double enf = (am * am) / bm;
-          const bool go = enf < a.tau;
-          if (a.tr_enf && bid == 0 && tid == 0)
-            for (int t = s; t <= (go ? s : S); ++t) a.tr_enf[(n - 1) * (S + 1) + t] = enf;
-          if (!go) break;
-          sstar = s;
+          __syncthreads();
+          if (s0 == 1 && s_encmax[0] == ninf()) {                    // every island dead
+            if (bid == 0 && tid == 0) *a.out_logz = ninf();
+            return;
+          }
+          for (int t = s0; t <= s_hi; ++t) {
+            const double enf = s_enf[t - s0];
+            const bool go = enf < a.tau;
+            if (a.tr_enf && bid == 0 && tid == 0)
+              for (int q = t; q <= (go ? t : S); ++q) a.tr_enf[(n - 1) * (S + 1) + q] = enf;
+            if (!go) { stop = true; break; }
+            sstar = t;
+          }
+          __syncthreads();
         }
+        if (sstar + 1 > lc + 1) build_upper_to(ppar, sstar + 1);
       }
       if (bid == 0 && tid == 0) {
         if (a.tr_sstar) a.tr_sstar[n - 1] = sstar;
@@ -285,7 +298,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         Store* xo = static_cast<Store*>(a.x1[par]) + (static_cast<int64_t>(k) * N) * DX;
         int* sAt = sA + team * TP * PPT;
         unsigned long long dig = 0;
-        // ancestors of this lane's slots: min{i : N C_i > U + j Q}
+        // ancestors of this lane's slots: min{i : N C_i > U + j Q}; the
+        // lane's slots are consecutive and their ancestors non-decreasing, so
+        // one binary search finds the first and the rest advance from it
+        int prev = 0;
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           const int j = j0 + r;
@@ -293,12 +309,18 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
             int anc = j;
             if (Qk > 0) {
               const uint64_t t = U + static_cast<uint64_t>(j) * Qk;
-              int lo = 0, hi = N - 1;
-              while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (static_cast<uint64_t>(N) * sCt[mid] > t) hi = mid; else lo = mid + 1;
+              int lo = prev;
+              if (r == 0) {
+                int hi = N - 1;
+                while (lo < hi) {
+                  const int mid = (lo + hi) >> 1;
+                  if (static_cast<uint64_t>(N) * sCt[mid] > t) hi = mid; else lo = mid + 1;
+                }
+              } else {
+                while (static_cast<uint64_t>(N) * sCt[lo] <= t) ++lo;
               }
               anc = lo;
+              prev = lo;
             }
             sAt[j] = anc;
             if (a.tr_anc) a.tr_anc[(n * m + k) * static_cast<int64_t>(N) + j] = anc;
@@ -327,68 +349,46 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     __syncthreads();
     if (replay) continue;
 
-    // ---- this block's part of the island tree and the ENF partial sums ----
-    for (int l = 2; l <= lc + 1; ++l) {
-      const int cnt = c >> (l - 1);
-      const int o_prev = 2 * c - ((2 * c) >> (l - 2)), o = 2 * c - ((2 * c) >> (l - 1));
-      for (int i = tid; i < cnt; i += kBlock) lv[o + i] = pair_mean(lv[o_prev + 2 * i], lv[o_prev + 2 * i + 1]);
-      __syncthreads();
+    // ---- this block's part of the island tree and the ENF partial records ----
+    if (c <= 64) {
+      // one wave: lane i holds value i of the level below
+      if (wave == 0) {
+        double v = (lane64 < c) ? lv[lane64] : ninf();
+        for (int l = 2; l <= lc + 1; ++l) {
+          const int cnt = c >> (l - 1);
+          const int o = 2 * c - ((2 * c) >> (l - 1));
+          const double v0 = __shfl(v, (2 * lane64) & 63, 64), v1 = __shfl(v, (2 * lane64 + 1) & 63, 64);
+          const double nv = lane64 < cnt ? pair_mean(v0, v1) : ninf();
+          if (lane64 < cnt) lv[o + lane64] = nv;
+          v = nv;
+        }
+      }
+    } else {
+      for (int l = 2; l <= lc + 1; ++l) {
+        const int cnt = c >> (l - 1);
+        const int o_prev = 2 * c - ((2 * c) >> (l - 2)), o = 2 * c - ((2 * c) >> (l - 1));
+        for (int i = tid; i < cnt; i += kBlock) lv[o + i] = pair_mean(lv[o_prev + 2 * i], lv[o_prev + 2 * i + 1]);
+        __syncthreads();
+      }
     }
+    __syncthreads();
     for (int l = 1; l <= lc + 1; ++l) {
       const int cnt = c >> (l - 1);
       const int o = 2 * c - ((2 * c) >> (l - 1));
       double* dst = a.tree[par] + tree_off(m, l) + (kbase >> (l - 1));
       for (int i = tid; i < cnt; i += kBlock) put(dst + i, lv[o + i]);
     }
-    // per level l: the ENF record of this block's level-l tree values, by
-    // adjacent pairs; all levels reduce together, one level per item, in lc
-    // rounds alternating between two copies of the level layout
-    {
-      double* M0 = scr;
-      double* A0 = scr + 2 * c;
-      double* B0 = scr + 4 * c;
-      double* M1 = scr + 6 * c;
-      double* A1 = scr + 8 * c;
-      double* B1 = scr + 10 * c;
-      for (int i = tid; i < 2 * c - 1; i += kBlock) {
-        const EnfRec e = enf_leaf(lv[i]);
-        M0[i] = e.M; A0[i] = e.a; B0[i] = e.b;
-      }
-      __syncthreads();
-      for (int t = 1; t <= lc; ++t) {
-        double* sm = (t & 1) ? M0 : M1;
-        double* sa = (t & 1) ? A0 : A1;
-        double* sb = (t & 1) ? B0 : B1;
-        double* dm = (t & 1) ? M1 : M0;
-        double* da = (t & 1) ? A1 : A0;
-        double* db = (t & 1) ? B1 : B0;
-        for (int it = tid; it < c; it += kBlock) {
-          int i = it;
-          for (int l = 1; l <= lc + 1; ++l) {
-            const int cnt = (c >> (l - 1)) >> t;
-            if (i < cnt) {
-              const int o = 2 * c - ((2 * c) >> (l - 1));
-              const EnfRec r = enf_join(EnfRec{sm[o + 2 * i], sa[o + 2 * i], sb[o + 2 * i]},
-                                        EnfRec{sm[o + 2 * i + 1], sa[o + 2 * i + 1], sb[o + 2 * i + 1]});
-              dm[o + i] = r.M; da[o + i] = r.a; db[o + i] = r.b;
-              break;
-            }
-            i -= cnt;
-          }
-        }
-        __syncthreads();
-      }
-      if (tid <= lc) {
-        const int l = tid + 1;
-        const int rounds = lc + 1 - l;                 // log2 of the level's count
-        const int o = 2 * c - ((2 * c) >> (l - 1));
-        const bool odd = rounds & 1;
+    // ENF record of each level's values in this block, one wave per level
+    for (int l = 1 + wave; l <= lc + 1; l += kWaves) {
+      const int cnt = c >> (l - 1);
+      const int o = 2 * c - ((2 * c) >> (l - 1));
+      const EnfRec r = wave_reduce_enf(cnt, [&](int i) { return enf_leaf(lv[o + i]); });
+      if (lane64 == 0) {
         double* pl = a.part[par] + static_cast<int64_t>(l - 1) * 3 * G;
-        put(pl + bid, odd ? M1[o] : M0[o]);
-        put(pl + G + bid, odd ? A1[o] : A0[o]);
-        put(pl + 2 * G + bid, odd ? B1[o] : B0[o]);
+        put(pl + bid, r.M);
+        put(pl + G + bid, r.a);
+        put(pl + 2 * G + bid, r.b);
       }
-      __syncthreads();
     }
   }
 
@@ -397,7 +397,9 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   if (replay || a.n1 < a.T) return;
   if (!grid_barrier(a.bar, G, bid, epoch, a.status)) return;
   if (bid == 0) {
-    const double lroot = upper_tree(static_cast<int>((a.T - 1) & 1));
+    up_top = 0;
+    build_upper_to(static_cast<int>((a.T - 1) & 1), S + 1);
+    const double lroot = up[2 * G - 2];
     if (tid == 0) {
       *a.out_logz = lroot;
       if (a.tr_sstar) a.tr_sstar[a.T - 1] = 0;
@@ -429,8 +431,7 @@ static int ilog2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
 
 static size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) {
   const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
-  const size_t scr = 12 * size_t(c) > 6 * size_t(G) ? 12 * size_t(c) : 6 * size_t(G);
-  return sx + 8 * size_t(kBlock) * ppt + 4 * size_t(kBlock) * ppt + 8 * 2 * size_t(c) + 8 * 2 * size_t(G) + 8 * scr;
+  return sx + 8 * size_t(kBlock) * ppt + 4 * size_t(kBlock) * ppt + 8 * 2 * size_t(c) + 8 * 2 * size_t(G);
 }
 
 template <class Model, typename Store, int PPT>
@@ -453,6 +454,7 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
     if (static_cast<long>(per_cu) * L.num_cus >= G) break;
   }
   if (G < 1) return hipErrorCooperativeLaunchTooLarge;
+  if (a.m / G > 256) return hipErrorInvalidValue;     // islands per block are bounded by the LDS plan
   a.TP = TP;
   a.G = G;
   a.c = a.m / G;

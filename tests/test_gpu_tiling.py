@@ -45,7 +45,8 @@ def test_forward_tiling_invariant(ctx, kind, m, N, T, tau):
     y = W.lg1_data(T) if kind == 0 else W.sv_data(T)
     th = W.LG1_THETA if kind == 0 else W.SV_THETA
     outs = []
-    for cap in (None, 1, 2, 8):
+    lo = max(1, m // 256)                  # a block holds at most 256 islands
+    for cap in (None, lo, 2 * lo, 8 * lo):
         tr = airpf.Trace(T, m, N, enf=False, digest=False)
         _, lz = _with_cap(cap, lambda: ctx.run(kind, th, y, m, N, 3, tau=tau, trace=tr))
         outs.append((lz, tr))
@@ -54,6 +55,12 @@ def test_forward_tiling_invariant(ctx, kind, m, N, T, tau):
         assert lz == lz0
         for f in ("lpost", "anc", "pi", "sstar"):
             assert np.array_equal(getattr(tr, f), getattr(t0, f)), f
+
+
+def test_too_few_blocks_is_unsupported(ctx):
+    from paper_2312_06484_amd import airpf
+    st, v = _with_cap(1, lambda: ctx.run(0, W.LG1_THETA, W.lg1_data(5), 1024, 8, 1, raise_on_error=False))
+    assert st == airpf.E_UNSUPPORTED
 
 
 def test_score_tiling_invariant(ctx):
