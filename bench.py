@@ -23,10 +23,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s, fwd and fwd+score, batched vs plain AIRPF, at stated logZ err"
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per particle-step of the forward filter: the state of
-# the selected island block is read once (mutation input) and the resampled
-# block written once, each d_x values of the storage type
-FWD_BYTES_PER_PARTICLE_STEP = {(1, "f32"): 8, (1, "f64"): 16, (8, "f32"): 64, (8, "f64"): 128}
 
 
 def measured_traffic(workload):
@@ -84,55 +80,113 @@ def cpu_baseline(wl, y, gpu_ctx, budget_steps):
         abs(lg - lo)
 
 
-def measure_extras(ctx, torch):
-    """Forward+score on the stochastic-volatility workload, and the 64-chain
-    proposal batch (forward+score) run in one batched call versus one theta
-    at a time.  Each is timed once after one warm-up call."""
-    from paper_2312_06484_amd import workloads as W
-    out = {}
-    # forward + path-space score, SV, T = 2000, 4096 x 128, checkpoints every 100 steps
-    T, m, N = 2000, 4096, 128
-    y = W.sv_data(T)
-    yd = torch.tensor(y, dtype=torch.float64, device="cuda")
-    run = lambda seed: ctx.score(1, W.SV_THETA, None, m, N, seed, tau=0.3, ckpt_every=100,
-                                 y_device_ptr=yd.data_ptr(), T=T)
-    run(99)
+def fwd_bytes(dx, store_bytes):
+    """Algorithmic HBM bytes per particle-step of the forward filter: the
+    selected island block read once, the resampled block written once."""
+    return 2 * store_bytes * dx
+
+
+def fwd_score_bytes(dx, store_bytes):
+    """Algorithmic HBM bytes per particle-step of forward + score: the
+    forward with checkpoints (read + write the state), the segment recompute
+    (read + write the state, record the state entering the weighting and the
+    16-bit ancestors) and the reverse pass (read the recorded state and
+    ancestors, read the children's (lam, D) and write the parents')."""
+    fwd = 2 * store_bytes * dx
+    rec = 2 * store_bytes * dx + store_bytes * dx + 2
+    rev = store_bytes * dx + 2 + 2 * store_bytes * (dx + 1)
+    return fwd + rec + rev
+
+
+def mode_record(particle_steps, seconds, bpp, **extra):
+    gbs = bpp * particle_steps / seconds / 1e9
+    rec = {"value": particle_steps / seconds, "unit": "particle-steps/s", "ms": seconds * 1e3,
+           "bytes_per_particle_step": bpp, "algorithmic_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    rec.update(extra)
+    return rec
+
+
+def timed(torch, fn):
+    fn(True)                                          # warm-up (also sizes the workspaces)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, lz, g = run(1)
+    r = fn(False)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["fwd_score_sv_t2000_m4096_n128_k100"] = {
-        "value": m * N * T / dt, "unit": "particle-steps/s", "ms": dt * 1e3, "device_ms": ctx.last_kernel_ms(),
-        "log_z": lz, "grad": list(g)}
-    # 64 chains' proposals, uneven T, m, N: forward + score
+    return time.perf_counter() - t0, r
+
+
+def measure_modes(ctx, torch):
+    """Every configuration of the benchmark table besides the headline one,
+    each timed once (wall clock, inputs resident in HBM) after one warm-up
+    call: the 1-D LG workload with interactions off, the SV workload forward
+    and forward + score, the 64-chain SV proposal batch (forward + score) in
+    one batched call versus one theta at a time, and the 8-D LG workload
+    forward and forward + score."""
+    from paper_2312_06484_amd import workloads as W
+    out = {}
+    dev = "cuda"
+
+    # interactions off (tau = 0: independent bootstrap filters), 1-D LG, T=1000, 1024 x 256
+    T, m, N = 1000, 1024, 256
+    yd = torch.tensor(W.lg1_data(T), dtype=torch.float64, device=dev)
+    dt, lz = timed(torch, lambda w: ctx.run(0, W.LG1_THETA, None, m, N, 77 if w else 1, tau=0.0,
+                                            y_device_ptr=yd.data_ptr(), T=T)[1])
+    out["fwd_lg1_t1000_m1024_n256_f32_tau0"] = mode_record(m * N * T, dt, fwd_bytes(1, 4), log_z=lz,
+                                                          device_ms=ctx.last_kernel_ms())
+
+    # SV, T = 2000, 4096 x 128: forward, and forward + path-space score with checkpoints every 100 steps
+    T, m, N = 2000, 4096, 128
+    yd = torch.tensor(W.sv_data(T), dtype=torch.float64, device=dev)
+    dt, lz = timed(torch, lambda w: ctx.run(1, W.SV_THETA, None, m, N, 99 if w else 1, tau=0.3,
+                                            y_device_ptr=yd.data_ptr(), T=T)[1])
+    out["fwd_sv_t2000_m4096_n128_f32"] = mode_record(m * N * T, dt, fwd_bytes(1, 4), log_z=lz,
+                                                     device_ms=ctx.last_kernel_ms())
+    dt, (_, lz, g) = timed(torch, lambda w: ctx.score(1, W.SV_THETA, None, m, N, 99 if w else 1, tau=0.3,
+                                                      ckpt_every=100, y_device_ptr=yd.data_ptr(), T=T))
+    out["fwd_score_sv_t2000_m4096_n128_f32_k100"] = mode_record(m * N * T, dt, fwd_score_bytes(1, 4), log_z=lz,
+                                                                grad=list(g))
+
+    # 64 chains' proposals, uneven T, m, N: forward + score, batched and one at a time
     items = W.batch_c4(64)
     ydev = {}
     probs = []
     for it in items:
         if it["T"] not in ydev:
-            ydev[it["T"]] = torch.tensor(W.sv_data(it["T"]), dtype=torch.float64, device="cuda")
+            ydev[it["T"]] = torch.tensor(W.sv_data(it["T"]), dtype=torch.float64, device=dev)
         probs.append(dict(theta=it["theta"], y=ydev[it["T"]].data_ptr(), T=it["T"], m=it["m"], N=it["N"],
                           seed=it["seed"]))
     total = sum(it["m"] * it["N"] * it["T"] for it in items)
-    ctx.run_batch(1, probs[:4], tau=0.3, want_score=True, ckpt_every=100, y_on_device=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, lzb, grb, ist = ctx.run_batch(1, probs, tau=0.3, want_score=True, ckpt_every=100, y_on_device=True)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    out["batched_sv_64_chains_fwd_score"] = {"value": total / tb, "unit": "particle-steps/s", "ms": tb * 1e3,
-                                             "particle_steps": total, "items_ok": int((ist == 0).sum())}
+    bpp = fwd_score_bytes(1, 4)
+    tb, (st, lzb, grb, ist) = timed(torch, lambda w: ctx.run_batch(1, probs[:4] if w else probs, tau=0.3,
+                                                                   want_score=True, ckpt_every=100,
+                                                                   y_on_device=True))
+    out["batched_fwd_score_sv_64_chains"] = mode_record(total, tb, bpp, total_particle_steps=total,
+                                                        items_ok=int((ist == 0).sum()))
     t0 = time.perf_counter()
     same = True
     for p, lzv, gv in zip(probs, lzb, grb):
         _, l1, g1 = ctx.score(1, p["theta"], None, p["m"], p["N"], p["seed"], tau=0.3, ckpt_every=100,
                               y_device_ptr=p["y"], T=p["T"])
-        same = same and (l1 == lzv) and bool((g1 == gv).all())
+        same = same and bool(l1 == lzv) and bool((g1 == gv).all())
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
-    out["plain_sv_64_chains_fwd_score"] = {"value": total / tp, "unit": "particle-steps/s", "ms": tp * 1e3,
-                                           "batched_speedup": tp / tb, "batched_items_bit_identical": same}
+    out["plain_fwd_score_sv_64_chains"] = mode_record(total, tp, bpp, batched_speedup=tp / tb,
+                                                      batched_items_bit_identical=same)
+
+    # 8-D LG, T = 500, 16384 x 64: forward, and forward + score wrt the 64 entries of A (K = 50)
+    A, H = W.lgd_model()
+    T, m, N = 500, 16384, 64
+    yd = torch.tensor(W.lgd_data(A, H, T).reshape(-1), dtype=torch.float64, device=dev)
+    cst = W.lgd_consts(H)
+    th = A.reshape(-1).tolist()
+    dt, lz = timed(torch, lambda w: ctx.run(2, th, None, m, N, 99 if w else 1, tau=0.3, dx=8, dy=4, consts=cst,
+                                            y_device_ptr=yd.data_ptr(), T=T)[1])
+    out["fwd_lgd8_t500_m16384_n64_f32"] = mode_record(m * N * T, dt, fwd_bytes(8, 4), log_z=lz,
+                                                      device_ms=ctx.last_kernel_ms())
+    dt, (_, lz, g) = timed(torch, lambda w: ctx.score(2, th, None, m, N, 99 if w else 1, tau=0.3, dx=8, dy=4,
+                                                      consts=cst, ckpt_every=50, y_device_ptr=yd.data_ptr(),
+                                                      T=T))
+    out["fwd_score_lgd8_t500_m16384_n64_f32_k50"] = mode_record(m * N * T, dt, fwd_score_bytes(8, 4), log_z=lz)
     return out
 
 
@@ -197,7 +251,7 @@ def main():
     ps_per_step = m * N * T
     value = ps_per_step * args.steps / elapsed
     avg_k = sum(kernel_ms) / len(kernel_ms)
-    bpp = FWD_BYTES_PER_PARTICLE_STEP[(wl["dx"], "f32" if wl["f32"] else "f64")]
+    bpp = fwd_bytes(wl["dx"], 4 if wl["f32"] else 8)
     achieved = bpp * ps_per_step / (avg_k * 1e-3) / 1e9
 
     err = {}
@@ -213,7 +267,7 @@ def main():
         cpu, d = cpu_baseline(wl, y, ctx, args.cpu_sample_steps)
         err["max_abs_vs_oracle_on_sample"] = d
 
-    extras = None if args.no_extras else measure_extras(ctx, torch)
+    extras = None if args.no_extras else measure_modes(ctx, torch)
 
     out = {
         "metric": METRIC,

@@ -30,12 +30,24 @@ def flags():
 
 
 def build(verbose: bool = False, out: str = OUT) -> str:
+    """Compile each source to an object (in parallel), then link."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *flags(), "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    compile_flags = [f for f in flags() if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="airpf_build_") as d:
+        objs = [os.path.join(d, os.path.basename(s) + ".o") for s in srcs]
+        cmds = [[hipcc(), *compile_flags, "-c", "-o", o, s] for s, o in zip(srcs, objs)]
+        cmds.append([hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp, *objs])
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+            for r in ex.map(lambda c: subprocess.run(c), cmds[:-1]):
+                if r.returncode != 0:
+                    raise subprocess.CalledProcessError(r.returncode, r.args)
+        subprocess.run(cmds[-1], check=True)
     os.replace(tmp, out)
     return out
 

@@ -218,6 +218,7 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   a.T = T; a.m = m; a.N = N; a.S = P->S; a.dy = P->dy; a.seed = seed; a.tau = opt.tau;
   a.n0 = 0; a.n1 = T;
   a.shortcut_all = opt.tau > 1.0 + 1e-9;
+  a.no_interaction = opt.tau <= 0.5 / m;
 
   // AIRPF_MAX_BLOCKS caps the blocks of a launch (tiling tests); results do
   // not depend on it
@@ -736,6 +737,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
         a.T = it.T; a.m = it.m; a.N = it.N; a.S = it.S; a.TP = it.TP; a.G = it.G; a.c = it.m / it.G;
         a.lc = ilog2(a.c); a.dy = dy; a.seed = it.seed; a.tau = opt.tau; a.cst_q = it.cst_q;
         a.shortcut_all = opt.tau > 1.0 + 1e-9;
+        a.no_interaction = opt.tau <= 0.5 / it.m;
         for (int p = 0; p < 2; ++p) {
           a.x1[p] = at(it.o_x1[p]);
           a.tree[p] = static_cast<double*>(at(it.o_tree[p]));

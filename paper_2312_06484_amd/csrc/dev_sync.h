@@ -94,6 +94,20 @@ __device__ bool grid_barrier(unsigned* flags, int G, int bid, unsigned& epoch, i
 // one wave (shuffles only), TP > 64 spans TP/64 whole waves (LDS combine).
 // Every helper is called by the whole block (TP is block-uniform).
 
+// Orders the LDS accesses of a team.  A team of TP <= 64 lanes lies inside
+// one wave, whose LDS instructions execute in program order, so only the
+// compiler has to be kept from moving accesses across this point; a wider
+// team needs the block barrier.
+__device__ __forceinline__ void team_sync(int TP) {
+  if (TP <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T team_bcast(T v, int TP, T* lds_slot_per_team) {
   const int tid = threadIdx.x;
@@ -208,12 +222,17 @@ __device__ __forceinline__ EnfRec enf_leaf(double L) {
   return L == ninf() ? EnfRec{L, 0.0, 0.0} : EnfRec{L, 1.0, 1.0};
 }
 
+// (the side at the larger maximum keeps its sums unscaled: its factor is
+// exp(0) = 1 exactly, so one exponential per join suffices)
 __device__ __forceinline__ EnfRec enf_join(const EnfRec& x, const EnfRec& y) {
   if (x.M == ninf()) return y;
   if (y.M == ninf()) return x;
-  const double M = x.M > y.M ? x.M : y.M;
-  const double fx = dexp(x.M - M), fy = dexp(y.M - M);
-  return EnfRec{M, x.a * fx + y.a * fy, x.b * (fx * fx) + y.b * (fy * fy)};
+  if (x.M >= y.M) {
+    const double f = dexp(y.M - x.M);
+    return EnfRec{x.M, x.a + y.a * f, x.b + y.b * (f * f)};
+  }
+  const double f = dexp(x.M - y.M);
+  return EnfRec{y.M, x.a * f + y.a, x.b * (f * f) + y.b};
 }
 
 // reduce n = 2^q records in LDS (arrays M, A, B) by adjacent pairs, whole
@@ -240,10 +259,10 @@ __device__ EnfRec block_pair_enf(double* M, double* A, double* B, double* wM, do
 
 // One wave reduces n <= 256 ENF records (n a power of two) by the
 // adjacent-pair tree: lane l first joins its aligned run of n/64 records,
-// then lanes join in a butterfly over xor 1, 2, ..., 32.  The join is
-// commutative bit for bit, so lane l ^ d holds exactly the other half of
-// every pair: the result is that of the adjacent-pair tree, in every lane.
-// `rec(i)` yields record i.
+// then lanes join in a butterfly over xor 1, 2, ..., min(n, 64)/2.  The join
+// is commutative bit for bit, so lane l ^ d holds exactly the other half of
+// every pair: the result is that of the adjacent-pair tree, in every lane
+// l < n.  `rec(i)` yields record i.
 template <class F>
 __device__ __forceinline__ EnfRec wave_reduce_enf(int n, F rec) {
   const int lane = threadIdx.x & 63;
@@ -255,7 +274,8 @@ __device__ __forceinline__ EnfRec wave_reduce_enf(int n, F rec) {
   } else {
     r = enf_join(enf_join(rec(4 * lane), rec(4 * lane + 1)), enf_join(rec(4 * lane + 2), rec(4 * lane + 3)));
   }
-  for (int d = 1; d < 64; d <<= 1) {
+  const int width = n < 64 ? n : 64;
+  for (int d = 1; d < width; d <<= 1) {
     const EnfRec o{__shfl_xor(r.M, d, 64), __shfl_xor(r.a, d, 64), __shfl_xor(r.b, d, 64)};
     r = enf_join(r, o);
   }

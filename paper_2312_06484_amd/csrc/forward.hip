@@ -71,10 +71,18 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   Store* sx = reinterpret_cast<Store*>(smem);                                    // [kBlock*NZ]
   uint64_t* sC = reinterpret_cast<uint64_t*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));
   int* sA = reinterpret_cast<int*>(sC + kBlock * PPT);                             // [kBlock*PPT]
-  double* lv = reinterpret_cast<double*>(sA + kBlock * PPT);                       // [2c]
-  double* up = lv + 2 * c;                                                        // [2G]
+  double* lvb = reinterpret_cast<double*>(sA + kBlock * PPT);                      // [2][2c]
+  double* up = lvb + 4 * c;                                                       // [2G]
+  // this block's part of the island tree (levels 1 .. lc+1, level l at
+  // offset 2c - 2c/2^(l-1)), one copy per step parity: the walk of step n
+  // reads step n-1's copy while the weighting writes step n's
+  auto lvp = [&](int par) { return lvb + 2 * c * par; };
 
   unsigned epoch = 0;
+  // tau so small that no stage can ever interact, and nothing traced or
+  // recorded: the blocks are independent until the final log Zhat
+  const bool never = a.no_interaction && !a.tr_enf && !a.tr_sstar && !a.tr_pi && !a.tr_lpost && !a.tr_anc &&
+                     !a.tr_digest && !a.tr_lpre && !a.rec_x && !a.rec_anc && !a.ck_x && !a.ck_in;
 
   // levels lc+1 .. `level` of the island tree in `up`, built on demand from
   // the G published block roots (identical in every block); up_top is the
@@ -95,8 +103,16 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     }
   };
 
-  auto lt_value = [&](int par, int level, int idx) -> double {   // tree value, level >= 1
-    if (level <= lc + 1) return get(a.tree[par] + tree_off(m, level) + idx);
+  // tree value, level >= 1: this block's own nodes from LDS, the block roots
+  // (level lc+1) from `up` (loaded whenever a walk reaches that level), lower
+  // nodes of other blocks from their published copy
+  auto lt_value = [&](int par, int level, int idx) -> double {
+    if (level <= lc + 1) {
+      const int lo = kbase >> (level - 1);
+      if (idx >= lo && idx < lo + (c >> (level - 1))) return lvp(par)[2 * c - ((2 * c) >> (level - 1)) + (idx - lo)];
+      if (level == lc + 1) return up[idx];
+      return get(a.tree[par] + tree_off(m, level) + idx);
+    }
     const int u = level - (lc + 1);
     return up[2 * G - ((2 * G) >> u) + idx];
   };
@@ -104,10 +120,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   const bool replay = a.replay_pi != 0;
   for (int64_t n = a.n0; n < a.n1; ++n) {
     const int par = static_cast<int>(n & 1), ppar = par ^ 1;
-    if (n > a.n0) {
+    if (n > a.n0 && !never) {
       if (!grid_barrier(a.bar, G, bid, epoch, a.status)) return;
     }
-    if (n > a.n0 && !replay) {
+    if (n > a.n0 && !replay && !never) {
       // ---- cascade of step n-1 (every block, identical) ----
       up_top = 0;
       int sstar = 0;
@@ -120,12 +136,16 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         }
         sstar = S;
       } else {
-        // ENF of stages s0 .. s0+3 at once, one per wave; a stage that does not
+        // ENF of up to four stages at once, one per wave; a stage that does not
         // interact leaves every weight unchanged, so every later stage sees the
-        // same ENF and does not interact either (traced as that same value)
+        // same ENF and does not interact either (traced as that same value).
+        // The first batch stops at the stages the published block records
+        // cover, so a step whose first stage does not interact never needs
+        // the upper tree.
         bool stop = false;
-        for (int s0 = 1; s0 <= S && !stop; s0 += kWaves) {
-          const int s_hi = s0 + kWaves - 1 < S ? s0 + kWaves - 1 : S;
+        int s_hi = lc + 1 < kWaves ? lc + 1 : kWaves;
+        if (s_hi > S) s_hi = S;
+        for (int s0 = 1; s0 <= S && !stop; s0 = s_hi + 1, s_hi = s0 + kWaves - 1 < S ? s0 + kWaves - 1 : S) {
           if (s_hi > lc + 1) build_upper_to(ppar, s_hi);
           const int sw = s0 + wave;
           if (sw <= s_hi) {
@@ -167,7 +187,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       s_sstar = sstar;
       __syncthreads();
     }
-    const int sstar = (n > a.n0 && !replay) ? s_sstar : 0;
+    const int sstar = (n > a.n0 && !replay && !never) ? s_sstar : 0;
 
     for (int p = 0; p < passes; ++p) {
       const int li = p * tpb + team;
@@ -176,13 +196,15 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       const int j0 = lane * PPT;
 
       // ---- mutation (or initial draw) ----
-      double z[NZ];
-      for (int g = 0; g < NZ / 4; ++g) {
-        double t[4];
-        normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
+      // normals of (step n, island k), this lane's particles
+      auto draw_normals = [&](double* z) {
+        for (int g = 0; g < NZ / 4; ++g) {
+          double t[4];
+          normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
-      }
+          for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
+        }
+      };
       double x[PPT][DX];
       double Lpre = 0.0;
       if (n == a.n0 && a.ck_in) {
@@ -195,6 +217,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           for (int d = 0; d < DX; ++d) x[r][d] = (j0 + r < N) ? static_cast<double>(xc[(j0 + r) * DX + d]) : 0.0;
         if (lane == 0) Lpre = a.ck_L[(n / a.ck_every) * m + k];
       } else if (n == 0) {
+        double z[NZ];
+        draw_normals(z);
 #pragma unroll
         for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * DX, x[r]);
       } else {
@@ -217,13 +241,20 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           if (a.tr_digest) atomicAdd(&a.tr_digest[2 * (n - 1) + 1], digest_term(n - 1, k, 4095, src));
         }
         src = team_bcast(src, TP, bc_i);
+        // the source block's loads go out first; the normals do not need them
         const Store* xin = static_cast<const Store*>(a.x1[ppar]) + (static_cast<int64_t>(src) * N) * DX;
+        Store xr[PPT][DX];
+#pragma unroll
+        for (int r = 0; r < PPT; ++r)
+#pragma unroll
+          for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? get(xin + (j0 + r) * DX + d) : Store(0);
+        double z[NZ];
+        draw_normals(z);
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
-          const int j = j0 + r;
           double xp[DX];
 #pragma unroll
-          for (int d = 0; d < DX; ++d) xp[d] = (j < N) ? static_cast<double>(get(xin + j * DX + d)) : 0.0;
+          for (int d = 0; d < DX; ++d) xp[d] = static_cast<double>(xr[r][d]);
           Model::template prop<Store>(a.mp, xp, z + r * DX, x[r]);
         }
       }
@@ -275,7 +306,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       const uint64_t Qk = team_sum_u64(tsum, TP, red_u);       // Q = sum_i q_i of the island
       if (lane == 0 && active && !replay) {
         const double L = (Qk == 0) ? ninf() : Lpre + ((mx + dlog(static_cast<double>(Qk))) + a.cst_q);
-        lv[li] = L;
+        lvp(par)[li] = L;
         if (a.tr_lpost) a.tr_lpost[n * m + k] = L;
       }
 
@@ -294,7 +325,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         uint64_t U = 0;
         if (lane == 0 && active && Qk > 0) U = bounded_u64(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, Qk);
         U = team_bcast(U, TP, bc_u);
-        __syncthreads();
+        team_sync(TP);
         Store* xo = static_cast<Store*>(a.x1[par]) + (static_cast<int64_t>(k) * N) * DX;
         int* sAt = sA + team * TP * PPT;
         unsigned long long dig = 0;
@@ -332,7 +363,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           dig = team_sum_u64(dig, TP, red_u);
           if (lane == 0 && active) atomicAdd(&a.tr_digest[2 * n], dig);
         }
-        __syncthreads();
+        team_sync(TP);
         // the resampled block, written word by word with consecutive lanes on
         // consecutive words so every store instruction covers whole lines
         if (active) {
@@ -343,13 +374,14 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
             if (j < N) put(xo + w, sxt[sAt[j] * DX + d]);
           }
         }
-        __syncthreads();
+        team_sync(TP);
       }
     }
     __syncthreads();
-    if (replay) continue;
+    if (replay || (never && n < a.T - 1)) continue;
 
     // ---- this block's part of the island tree and the ENF partial records ----
+    double* lv = lvp(par);
     if (c <= 64) {
       // one wave: lane i holds value i of the level below
       if (wave == 0) {
@@ -431,7 +463,7 @@ static int ilog2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
 
 static size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) {
   const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
-  return sx + 8 * size_t(kBlock) * ppt + 4 * size_t(kBlock) * ppt + 8 * 2 * size_t(c) + 8 * 2 * size_t(G);
+  return sx + 8 * size_t(kBlock) * ppt + 4 * size_t(kBlock) * ppt + 8 * 4 * size_t(c) + 8 * 2 * size_t(G);
 }
 
 template <class Model, typename Store, int PPT>

@@ -15,7 +15,8 @@ struct FwdArgs {
   int m, N, S, TP, c, lc, G, dy;
   uint64_t seed;
   double tau, cst_q;
-  int shortcut_all;
+  int shortcut_all;           // tau > 1: every stage interacts
+  int no_interaction;         // tau <= 1/(2m): no stage can interact (ENF >= 1/m)
   void* x1[2];                // Store*, resampled blocks, [m*N*DX] particle-major
   double* tree[2];            // [2m] pair-mean tree of island log-weights
   double* part[2];            // [(lc+1)*3*G] per level: the blocks' ENF records (max, sum w, sum w^2)

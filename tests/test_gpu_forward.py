@@ -189,3 +189,26 @@ def test_enf_threshold_at_a_stage_bound(ctx, orc, tau):
     # such a bound must be decided as the definition decides it (not < tau)
     lz, gt, lo, ot, P = run_both(ctx, orc, "lgd", 16, 64, 25, tau, False, dx=8)
     assert_parity(lz, gt, lo, ot, P)
+
+
+@pytest.mark.parametrize("model,m,N,T,tau,f64,dx", [
+    ("lg1", 1024, 256, 120, 0.0, False, None),     # the benchmark width, interactions off
+    ("sv", 64, 37, 50, 0.005, False, None),        # tau <= 1/(2m), ragged N
+    ("lgd", 32, 20, 30, 0.0, True, 4),
+])
+def test_untraced_run_without_interactions(ctx, orc, model, m, N, T, tau, f64, dx):
+    """With tau <= 1/(2m) no stage can interact (ENF >= 1/m), and an untraced
+    run skips the per-step synchronisation entirely; its log Zhat must be the
+    traced run's bit for bit, and the oracle's."""
+    g, P = make_case(orc, model, m, N, T, 3, dx)
+    print("case", model, dx, m, N, T, tau, flush=True)
+    from paper_2312_06484_amd import airpf
+    gt = airpf.Trace(T, m, N, enf=False, anc=False, digest=False)
+    _, lz_traced = ctx.run(g["kind"], g["theta"], g["y"], m, N, 3, tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"],
+                           consts=g["consts"], trace=gt)
+    _, lz = ctx.run(g["kind"], g["theta"], g["y"], m, N, 3, tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"],
+                    consts=g["consts"])
+    assert lz == lz_traced
+    assert (gt.sstar == 0).all()
+    lo = orc.run(P, tau=tau, store_f32=not f64)
+    assert abs(lz - lo) <= 1e-12 * max(1.0, abs(lo)), (lz, lo)
