@@ -33,7 +33,7 @@ def measured_traffic(workload):
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
-    for f in ["forward.hip", "dev_math.h", "dev_models.h", "dev_sync.h", "internal.h"]:
+    for f in ["forward_impl.h", "dev_math.h", "dev_models.h", "dev_sync.h", "internal.h"]:
         h.update(open(os.path.join(ROOT, "paper_2312_06484_amd", "csrc", f), "rb").read())
     for key, rec in json.load(open(path)).items():
         if key.endswith(" " + workload) and rec.get("kernel_sources_sha256") == h.hexdigest():

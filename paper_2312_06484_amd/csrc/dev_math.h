@@ -57,23 +57,36 @@ __device__ __forceinline__ double uniform53(uint32_t hi, uint32_t lo) {
 
 // Uniform integer in [0, Q), Q >= 1: Lemire's multiply-and-reject on 64-bit
 // candidates taken as (w0:w1), (w2:w3) of sub-blocks 0, 1, ..., at most 64
-// sub-blocks (then the last candidate is used as is).
-__device__ inline uint64_t bounded_u64(Key key, uint32_t c0, uint32_t island, uint32_t step,
-                                       uint32_t tag, uint64_t Q) {
-  const uint64_t reject_below = (~Q + 1) % Q;          // 2^64 mod Q
+// sub-blocks (then the last candidate is used as is).  A candidate c is
+// accepted iff the low word of c*Q is at least 2^64 mod Q; as that bound is
+// below Q, the 64-bit remainder is only evaluated when the low word is below
+// Q (probability Q/2^64).  `w0` is sub-block 0, drawn by the caller (it does
+// not depend on Q).
+__device__ inline uint64_t bounded_u64_from(const uint32_t w0[4], Key key, uint32_t c0, uint32_t island,
+                                            uint32_t step, uint32_t tag, uint64_t Q) {
+  uint64_t reject_below = 0;
+  bool have_bound = false;
   uint64_t hi = 0;
+  uint32_t w[4] = {w0[0], w0[1], w0[2], w0[3]};
   for (uint32_t sub = 0; sub < 64; ++sub) {
-    uint32_t w[4];
-    draw4(key, c0, island, step, tag, sub, w);
+    if (sub > 0) draw4(key, c0, island, step, tag, sub, w);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const uint64_t cand = (static_cast<uint64_t>(w[2 * h]) << 32) | w[2 * h + 1];
       hi = __umul64hi(cand, Q);
       const uint64_t lo = cand * Q;
+      if (lo >= Q) return hi;
+      if (!have_bound) { reject_below = (~Q + 1) % Q; have_bound = true; }   // 2^64 mod Q
       if (lo >= reject_below) return hi;
     }
   }
   return hi;
+}
+
+__device__ inline uint64_t bounded_u64(Key key, uint32_t c0, uint32_t island, uint32_t step, uint32_t tag, uint64_t Q) {
+  uint32_t w[4];
+  draw4(key, c0, island, step, tag, 0, w);
+  return bounded_u64_from(w, key, c0, island, step, tag, Q);
 }
 
 // ---------------------------------------------------------------- exp / log

@@ -11,6 +11,7 @@ namespace airpf {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kMaxIslandsPerBlock = 256;   // the LDS plan of the forward kernel
 
 
 __device__ __forceinline__ int64_t tree_off(int m, int level) {  // level >= 1
@@ -89,6 +90,29 @@ __device__ bool grid_barrier(unsigned* flags, int G, int bid, unsigned& epoch, i
   return ok != 0;
 }
 
+// ------------------------------------------------------------ DPP lane moves
+// Cross-lane moves inside a row of 16 lanes (and the two row broadcasts of
+// the scan) through the VALU's data-parallel primitives, without the LDS
+// crossbar.  Lanes a move does not write (masked rows, sources outside the
+// row) read 0.  Controls: quad_perm(1,0,3,2) = 0xB1 and (2,3,0,1) = 0x4E
+// (xor 1, xor 2), row_shr:k = 0x110 + k, row_mirror = 0x140 (lane i <- 15-i),
+// row_half_mirror = 0x141 (i <- 7-i in each half row), row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROWMASK, 0xf, true));
+}
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const uint32_t lo = dpp32<CTRL, ROWMASK>(static_cast<uint32_t>(v));
+  const uint32_t hi = dpp32<CTRL, ROWMASK>(static_cast<uint32_t>(v >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+  return __longlong_as_double(static_cast<long long>(dpp64<CTRL>(static_cast<uint64_t>(__double_as_longlong(v)))));
+}
+
 // ------------------------------------------------------------ team / block reductions
 // A team is TP consecutive lanes (TP a power of two); TP <= 64 stays inside
 // one wave (shuffles only), TP > 64 spans TP/64 whole waves (LDS combine).
@@ -121,8 +145,14 @@ __device__ __forceinline__ T team_bcast(T v, int TP, T* lds_slot_per_team) {
 }
 
 __device__ __forceinline__ double team_max(double v, int TP, double* red) {
-  const int w = TP < 64 ? TP : 64;
-  for (int d = 1; d < w; d <<= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  // partners xor 1, xor 2, then the mirrors of 8 and 16 lanes (each pairs a
+  // lane with one holding the other half of its group), then xor 16, 32
+  if (TP >= 2) v = fmax(v, dppd<0xB1>(v));
+  if (TP >= 4) v = fmax(v, dppd<0x4E>(v));
+  if (TP >= 8) v = fmax(v, dppd<0x141>(v));
+  if (TP >= 16) v = fmax(v, dppd<0x140>(v));
+  if (TP >= 32) v = fmax(v, __shfl_xor(v, 16, 64));
+  if (TP >= 64) v = fmax(v, __shfl_xor(v, 32, 64));
   if (TP > 64) {
     const int tid = threadIdx.x;
     if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -152,15 +182,19 @@ __device__ __forceinline__ uint64_t team_sum_u64(uint64_t v, int TP, uint64_t* r
   return v;
 }
 
-// inclusive scan of v over the team's lanes (lane order)
+// inclusive scan of v over the team's lanes (lane order): shifts by 1, 2, 4,
+// 8 inside each row of 16 lanes, then the row totals carried forward by the
+// two row broadcasts (lane 15 into the next row, lane 31 into rows 2 and 3)
 __device__ __forceinline__ uint64_t team_scan_u64(uint64_t v, int TP, uint64_t* red) {
   const int tid = threadIdx.x;
-  const int w = TP < 64 ? TP : 64;
-  const int sl = tid & (w - 1);
-  for (int d = 1; d < w; d <<= 1) {
-    const uint64_t t = __shfl_up(v, d, w);
-    if (sl >= d) v += t;
-  }
+  const int sl = tid & ((TP < 64 ? TP : 64) - 1);
+  uint64_t t;
+  if (TP > 1) { t = dpp64<0x111>(v); if (sl >= 1) v += t; }
+  if (TP > 2) { t = dpp64<0x112>(v); if (sl >= 2) v += t; }
+  if (TP > 4) { t = dpp64<0x114>(v); if (sl >= 4) v += t; }
+  if (TP > 8) { t = dpp64<0x118>(v); if (sl >= 8) v += t; }
+  if (TP > 16) v += dpp64<0x142, 0xa>(v);
+  if (TP > 32) v += dpp64<0x143, 0xc>(v);
   if (TP > 64) {
     if ((tid & 63) == 63) red[tid >> 6] = v;
     __syncthreads();
@@ -211,58 +245,40 @@ __device__ __forceinline__ double team_scan_f64(double v, int TP, double* red) {
   return v;
 }
 
-// ENF sums of a set of island log-weights L: the record (M, a, b) holds
-// M = max L, a = sum exp(L - M), b = sum exp(L - M)^2.  Records of two
-// halves combine by rescaling to the larger maximum; a member at the maximum
-// contributes exactly 1, as in the definition ENF = (m^-1 sum W)^2 / (m^-1 sum W^2)
-// evaluated with W = exp(L - max L).
-struct EnfRec { double M, a, b; };
+// ENF sums of a set of island log-weights L.  The record (E, a, b) holds
+// a = sum exp(L) 2^-E and b = sum exp(2L) 2^-2E for an integer E kept as a
+// double (E = -inf for an empty or all-dead set).  A leaf takes E as the
+// integer nearest L / log 2, so its share exp(L - E log 2) lies in
+// [0.7, 1.42]; two records join at the larger E with exact power-of-two
+// rescaling (two ldexp and one addition per sum, no exponential).  The ENF
+// (m^-1 sum W)^2 / (m^-1 sum W^2) is a^2 / b up to the block factors: 2^E
+// cancels.  When one member's weight swamps the others' below rounding, a
+// and b reduce to that member's w and fl(w^2) and the ENF lands exactly on
+// its rational value, as the definition does.
+struct EnfRec { double E, a, b; };
 
 __device__ __forceinline__ EnfRec enf_leaf(double L) {
-  return L == ninf() ? EnfRec{L, 0.0, 0.0} : EnfRec{L, 1.0, 1.0};
+  if (L == ninf()) return EnfRec{L, 0.0, 0.0};
+  const double E = rint(L * kInvLn2);
+  const double w = dexp(fma(-E, kLn2Tail, fma(-E, kLn2Head, L)));
+  return EnfRec{E, w, w * w};
 }
 
-// (the side at the larger maximum keeps its sums unscaled: its factor is
-// exp(0) = 1 exactly, so one exponential per join suffices)
 __device__ __forceinline__ EnfRec enf_join(const EnfRec& x, const EnfRec& y) {
-  if (x.M == ninf()) return y;
-  if (y.M == ninf()) return x;
-  if (x.M >= y.M) {
-    const double f = dexp(y.M - x.M);
-    return EnfRec{x.M, x.a + y.a * f, x.b + y.b * (f * f)};
-  }
-  const double f = dexp(x.M - y.M);
-  return EnfRec{y.M, x.a * f + y.a, x.b * (f * f) + y.b};
-}
-
-// reduce n = 2^q records in LDS (arrays M, A, B) by adjacent pairs, whole
-// block; w* are scratch arrays of n/2.  The pairing depends only on the
-// indices, so records of aligned index ranges combine to the same value
-// however the range is split across blocks.
-__device__ EnfRec block_pair_enf(double* M, double* A, double* B, double* wM, double* wA, double* wB, int n) {
-  double *sm = M, *sa = A, *sb = B, *dm = wM, *da = wA, *db = wB;
-  for (int h = n >> 1; h >= 1; h >>= 1) {
-    for (int i = threadIdx.x; i < h; i += kBlock) {
-      const EnfRec r = enf_join(EnfRec{sm[2 * i], sa[2 * i], sb[2 * i]}, EnfRec{sm[2 * i + 1], sa[2 * i + 1], sb[2 * i + 1]});
-      dm[i] = r.M; da[i] = r.a; db[i] = r.b;
-    }
-    __syncthreads();
-    double* t;
-    t = sm; sm = dm; dm = t;
-    t = sa; sa = da; da = t;
-    t = sb; sb = db; db = t;
-  }
-  const EnfRec r{sm[0], sa[0], sb[0]};
-  __syncthreads();
-  return r;
+  if (x.E == ninf()) return y;
+  if (y.E == ninf()) return x;
+  const double E = x.E > y.E ? x.E : y.E;
+  const int dx = static_cast<int>(x.E - E), dy = static_cast<int>(y.E - E);   // <= 0
+  return EnfRec{E, __builtin_ldexp(x.a, dx) + __builtin_ldexp(y.a, dy),
+                __builtin_ldexp(x.b, 2 * dx) + __builtin_ldexp(y.b, 2 * dy)};
 }
 
 // One wave reduces n <= 256 ENF records (n a power of two) by the
 // adjacent-pair tree: lane l first joins its aligned run of n/64 records,
-// then lanes join in a butterfly over xor 1, 2, ..., min(n, 64)/2.  The join
-// is commutative bit for bit, so lane l ^ d holds exactly the other half of
-// every pair: the result is that of the adjacent-pair tree, in every lane
-// l < n.  `rec(i)` yields record i.
+// then lanes join in a butterfly over groups of 2, 4, ..., min(n, 64).  The
+// join is commutative bit for bit and a lane's partner holds exactly the
+// other half of its group, so the result is that of the adjacent-pair tree,
+// in every lane l < n.  `rec(i)` yields record i.
 template <class F>
 __device__ __forceinline__ EnfRec wave_reduce_enf(int n, F rec) {
   const int lane = threadIdx.x & 63;
@@ -274,11 +290,15 @@ __device__ __forceinline__ EnfRec wave_reduce_enf(int n, F rec) {
   } else {
     r = enf_join(enf_join(rec(4 * lane), rec(4 * lane + 1)), enf_join(rec(4 * lane + 2), rec(4 * lane + 3)));
   }
-  const int width = n < 64 ? n : 64;
-  for (int d = 1; d < width; d <<= 1) {
-    const EnfRec o{__shfl_xor(r.M, d, 64), __shfl_xor(r.a, d, 64), __shfl_xor(r.b, d, 64)};
-    r = enf_join(r, o);
-  }
+  // the butterfly: xor 1, xor 2, then the 8- and 16-lane mirrors (a lane's
+  // partner holds exactly the other half of its group, as with xor 4, xor 8),
+  // then xor 16, xor 32
+  if (n >= 2) r = enf_join(r, EnfRec{dppd<0xB1>(r.E), dppd<0xB1>(r.a), dppd<0xB1>(r.b)});
+  if (n >= 4) r = enf_join(r, EnfRec{dppd<0x4E>(r.E), dppd<0x4E>(r.a), dppd<0x4E>(r.b)});
+  if (n >= 8) r = enf_join(r, EnfRec{dppd<0x141>(r.E), dppd<0x141>(r.a), dppd<0x141>(r.b)});
+  if (n >= 16) r = enf_join(r, EnfRec{dppd<0x140>(r.E), dppd<0x140>(r.a), dppd<0x140>(r.b)});
+  if (n >= 32) r = enf_join(r, EnfRec{__shfl_xor(r.E, 16, 64), __shfl_xor(r.a, 16, 64), __shfl_xor(r.b, 16, 64)});
+  if (n >= 64) r = enf_join(r, EnfRec{__shfl_xor(r.E, 32, 64), __shfl_xor(r.a, 32, 64), __shfl_xor(r.b, 32, 64)});
   return r;
 }
 

@@ -1,0 +1,591 @@
+// AIRPF forward pass on gfx950: one persistent cooperative launch runs all T
+// filter steps of Algorithm 1 (Heine, arXiv:2312.06484, Section 2).
+//
+// Work decomposition
+//   * A team of TP lanes (power of two, <= 256) owns one island; lane l holds
+//     particles [l*PPT, (l+1)*PPT) of it in registers, PPT >= 4 normals' worth
+//     so that one Philox call feeds whole Box-Muller pairs.
+//   * Block b (256 lanes) owns the c = m/G consecutive islands
+//     [b*c, (b+1)*c) and processes them tpb = 256/TP at a time.
+//   * Per step the only grid-wide dependency is the island-weight cascade
+//     (the ENF test and the pair selections): one grid barrier per step.
+//
+// Step n, per island k (Algorithm 1 in order):
+//   mutation     x_n = K(block pi_{n-1}(k) of step n-1's resampled state)
+//                (or x_0 ~ pi_0), normals at (step n, island k);
+//   weighting    lw = log g_n(x) per particle, q = floor(2^40 exp(lw - max)),
+//                Q = sum q (exact), L_k = Lpre_k + ((max + log Q) + cst);
+//   resampling   systematic on the integer cumulative weights: slot j takes
+//                min{i : N C_i > U + j Q}, U uniform on [0, Q);
+//   island tree  pair means log((W_a + W_b)/2) of aligned blocks, level by
+//                level (the normaliser line of Algorithm 1 applied to a
+//                block's two halves); published with per-level partial sums
+//                of W^2 for the ENF.
+// After the barrier every block evaluates the ENF of each stage from the
+// published partials, s* = the number of leading stages with ENF < tau, and
+// walks each of its islands down the stages s*, ..., 1: at stage s island
+// cur takes its partner cur ^ 2^(s-1) with probability
+// W_p / (W_cur + W_p) (draw at (step, island cur, stage s)).  The island's
+// next weight is its 2^{s*}-block mean.
+//
+// ENF at stage s (W the weights after s-1 interacting stages, B_b the sums of
+// the aligned 2^{s-1}-blocks): ENF_s = 2^{s-1} (sum W)^2 / (m sum_b B_b^2),
+// in logs 2 log sum W - log m - log sum_b exp(2 LT_b) - (s-1) log 2 with
+// LT_b = log(B_b / 2^{s-1}) the pair-mean tree value.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
+#include <stdint.h>
+
+#include "dev_models.h"
+#include "dev_sync.h"
+#include "internal.h"
+
+namespace airpf {
+
+// ------------------------------------------------------------ the kernel
+
+// One problem's filter, run by the G blocks of its sub-grid; `bid` is this
+// block's index within them.
+template <class Model, typename Store, int PPT>
+__device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
+  constexpr int DX = Model::DX;
+  constexpr int NZ = PPT * DX;                 // normals per lane per step
+  static_assert(NZ % 4 == 0, "a lane consumes whole Philox blocks");
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red_d[kWaves];
+  __shared__ uint64_t red_u[kWaves];
+  __shared__ uint64_t bc_u[kBlock];
+  __shared__ int s_sstar;
+  __shared__ double s_enf[kWaves], s_encmax[kWaves];
+  __shared__ int s_src[kMaxIslandsPerBlock];          // this step's source island of each island
+  __shared__ double s_lpre[kMaxIslandsPerBlock];      // and its entering log-weight
+
+  const int tid = threadIdx.x;
+  const int TP = a.TP, tpb = kBlock / TP;
+  const int team = tid / TP, lane = tid & (TP - 1);
+  const int wave = tid >> 6, lane64 = tid & 63;
+  const int m = a.m, N = a.N, S = a.S, c = a.c, lc = a.lc, G = a.G;
+  const int kbase = bid * c;
+  const Key key = make_key(a.seed);
+  const int passes = (c + tpb - 1) / tpb;
+
+  Store* sx = reinterpret_cast<Store*>(smem);                                    // [kBlock*NZ]
+  uint64_t* sC = reinterpret_cast<uint64_t*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));
+  int* sA = reinterpret_cast<int*>(sC + kBlock * PPT);                             // [kBlock*PPT]
+  double* lvb = reinterpret_cast<double*>(sA + kBlock * PPT);                      // [2][2c]
+  double* up = lvb + 4 * c;                                                       // [2G]
+  // this block's part of the island tree (levels 1 .. lc+1, level l at
+  // offset 2c - 2c/2^(l-1)), one copy per step parity: the walk of step n
+  // reads step n-1's copy while the weighting writes step n's
+  auto lvp = [&](int par) { return lvb + 2 * c * par; };
+
+  unsigned epoch = 0;
+  // tau so small that no stage can ever interact, and nothing traced or
+  // recorded: the blocks are independent until the final log Zhat
+  const bool never = a.no_interaction && !a.tr_enf && !a.tr_sstar && !a.tr_pi && !a.tr_lpost && !a.tr_anc &&
+                     !a.tr_digest && !a.tr_lpre && !a.rec_x && !a.rec_anc && !a.ck_x && !a.ck_in;
+
+  // levels lc+1 .. `level` of the island tree in `up`, built on demand from
+  // the G published block roots (identical in every block); up_top is the
+  // highest level built for the current cascade
+  int up_top = 0;
+  auto build_upper_to = [&](int par, int level) {
+    if (up_top < lc + 1) {
+      for (int b = tid; b < G; b += kBlock) up[b] = get(a.tree[par] + tree_off(m, lc + 1) + b);
+      __syncthreads();
+      up_top = lc + 1;
+    }
+    for (; up_top < level; ++up_top) {
+      const int u = up_top + 1 - (lc + 1);
+      const int cnt = G >> u;
+      const int o_prev = 2 * G - ((2 * G) >> (u - 1)), o = 2 * G - ((2 * G) >> u);
+      for (int i = tid; i < cnt; i += kBlock) up[o + i] = pair_mean(up[o_prev + 2 * i], up[o_prev + 2 * i + 1]);
+      __syncthreads();
+    }
+  };
+
+  // tree value, level >= 1: this block's own nodes from LDS, the block roots
+  // (level lc+1) from `up` (loaded whenever a walk reaches that level), lower
+  // nodes of other blocks from their published copy
+  auto lt_value = [&](int par, int level, int idx) -> double {
+    if (level <= lc + 1) {
+      const int lo = kbase >> (level - 1);
+      if (idx >= lo && idx < lo + (c >> (level - 1))) return lvp(par)[2 * c - ((2 * c) >> (level - 1)) + (idx - lo)];
+      if (level == lc + 1) return up[idx];
+      return get(a.tree[par] + tree_off(m, level) + idx);
+    }
+    const int u = level - (lc + 1);
+    return up[2 * G - ((2 * G) >> u) + idx];
+  };
+
+  const bool replay = a.replay_pi != 0;
+  for (int64_t n = a.n0; n < a.n1; ++n) {
+    const int par = static_cast<int>(n & 1), ppar = par ^ 1;
+    if (n > a.n0 && !never) {
+      if (!grid_barrier(a.bar, G, bid, epoch, a.status)) return;
+    }
+    if (n > a.n0 && !replay && !never) {
+      // ---- cascade of step n-1 (every block, identical) ----
+      up_top = 0;
+      int sstar = 0;
+      if (a.shortcut_all) {
+        // tau > 1: every stage interacts (ENF <= 1 always)
+        build_upper_to(ppar, S + 1);
+        if (up[2 * G - 2] == ninf()) {                               // every island dead
+          if (bid == 0 && tid == 0) *a.out_logz = ninf();
+          return;
+        }
+        sstar = S;
+      } else {
+        // ENF of up to four stages at once, one per wave; a stage that does not
+        // interact leaves every weight unchanged, so every later stage sees the
+        // same ENF and does not interact either (traced as that same value).
+        // The first batch stops at the stages the published block records
+        // cover, so a step whose first stage does not interact never needs
+        // the upper tree.
+        bool stop = false;
+        int s_hi = lc + 1 < kWaves ? lc + 1 : kWaves;
+        if (s_hi > S) s_hi = S;
+        for (int s0 = 1; s0 <= S && !stop; s0 = s_hi + 1, s_hi = s0 + kWaves - 1 < S ? s0 + kWaves - 1 : S) {
+          if (s_hi > lc + 1) build_upper_to(ppar, s_hi);
+          const int sw = s0 + wave;
+          if (sw <= s_hi) {
+            EnfRec r;
+            if (sw <= lc + 1) {
+              const double* ps = a.part[ppar] + static_cast<int64_t>(sw - 1) * 3 * G;
+              r = wave_reduce_enf(G, [&](int i) { return EnfRec{get(ps + i), get(ps + G + i), get(ps + 2 * G + i)}; });
+            } else {
+              const double* lvl = up + 2 * G - ((2 * G) >> (sw - lc - 1));
+              r = wave_reduce_enf(G >> (sw - lc - 1), [&](int i) { return enf_leaf(lvl[i]); });
+            }
+            // after s-1 interacting stages every island holds its 2^{s-1}-block
+            // mean: sum_k W_k = 2^{s-1} sum_b w_b, sum_k W_k^2 = 2^{s-1} sum_b w_b^2
+            const double blk = static_cast<double>(1 << (sw - 1));
+            const double am = (blk * r.a) / static_cast<double>(m), bm = (blk * r.b) / static_cast<double>(m);
+            if ((tid & 63) == 0) { s_enf[wave] = (am * am) / bm; s_encmax[wave] = r.E; }
+          }
+          __syncthreads();
+          if (s0 == 1 && s_encmax[0] == ninf()) {                    // every island dead
+            if (bid == 0 && tid == 0) *a.out_logz = ninf();
+            return;
+          }
+          for (int t = s0; t <= s_hi; ++t) {
+            const double enf = s_enf[t - s0];
+            const bool go = enf < a.tau;
+            if (a.tr_enf && bid == 0 && tid == 0)
+              for (int q = t; q <= (go ? t : S); ++q) a.tr_enf[(n - 1) * (S + 1) + q] = enf;
+            if (!go) { stop = true; break; }
+            sstar = t;
+          }
+          __syncthreads();
+        }
+        if (sstar + 1 > lc + 1) build_upper_to(ppar, sstar + 1);
+      }
+      if (bid == 0 && tid == 0) {
+        if (a.tr_sstar) a.tr_sstar[n - 1] = sstar;
+        if (a.tr_digest) atomicAdd(&a.tr_digest[2 * (n - 1) + 1], (unsigned long long)sstar * 0x9E3779B97F4A7C15ULL);
+      }
+      s_sstar = sstar;
+      __syncthreads();
+    }
+    const int sstar = (n > a.n0 && !replay && !never) ? s_sstar : 0;
+
+    // ---- the source block and entering weight of every island of the block,
+    // all islands at once: island k walks the interacting stages s*, ..., 1;
+    // at stage s the island `cur` it has reached takes its partner
+    // cur ^ 2^(s-1) with probability W_p / (W_cur + W_p) (its own draw at
+    // (step, cur, stage s)), which composes the per-stage selections that
+    // Algorithm 1 applies to every island.  Its entering weight is its
+    // 2^{s*}-block mean.
+    const bool mutate = n != 0 && !(n == a.n0 && a.ck_in);
+    if (mutate) {
+      for (int li = tid; li < c; li += kBlock) {
+        const int k = kbase + li;
+        int cur = k;
+        double lpre = 0.0;
+        if (replay) {
+          cur = a.tr_pi[(n - 1) * m + k];
+        } else {
+          for (int s = sstar; s >= 1; --s) {
+            const int pr = cur ^ (1 << (s - 1));
+            const double lc_ = lt_value(ppar, s, cur >> (s - 1));
+            const double lp_ = lt_value(ppar, s, pr >> (s - 1));
+            uint32_t w[4];
+            draw4(key, static_cast<uint32_t>(s), static_cast<uint32_t>(cur), static_cast<uint32_t>(n - 1), kTagIsl, 0, w);
+            if (uniform53(w[0], w[1]) < take_partner_prob(lc_, lp_)) cur = pr;
+          }
+          lpre = lt_value(ppar, sstar + 1, k >> sstar);
+          if (a.tr_pi) a.tr_pi[(n - 1) * m + k] = cur;
+          if (a.tr_digest) atomicAdd(&a.tr_digest[2 * (n - 1) + 1], digest_term(n - 1, k, 4095, cur));
+        }
+        s_src[li] = cur;
+        s_lpre[li] = lpre;
+      }
+      __syncthreads();
+    }
+
+    for (int p = 0; p < passes; ++p) {
+      const int li = p * tpb + team;
+      const bool active = li < c;
+      const int k = kbase + (active ? li : 0);
+      const int j0 = lane * PPT;
+
+      // ---- mutation (or initial draw) ----
+      // normals of (step n, island k), this lane's particles
+      auto draw_normals = [&](double* z) {
+        for (int g = 0; g < NZ / 4; ++g) {
+          double t[4];
+          normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
+        }
+      };
+      // sub-block 0 of the systematic offset's draw (it does not depend on Q)
+      uint32_t wsys[4] = {0u, 0u, 0u, 0u};
+      if (n < a.T - 1 && lane == 0) draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
+      double x[PPT][DX];
+      double Lpre = 0.0;
+      if (n == a.n0 && a.ck_in) {
+        // restart from the checkpoint taken entering this step
+        const Store* xc = static_cast<const Store*>(a.ck_x) + (n / a.ck_every) * (static_cast<int64_t>(m) * N * DX) +
+                          static_cast<int64_t>(k) * N * DX;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r)
+#pragma unroll
+          for (int d = 0; d < DX; ++d) x[r][d] = (j0 + r < N) ? static_cast<double>(xc[(j0 + r) * DX + d]) : 0.0;
+        if (lane == 0) Lpre = a.ck_L[(n / a.ck_every) * m + k];
+      } else if (n == 0) {
+        double z[NZ];
+        draw_normals(z);
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * DX, x[r]);
+      } else {
+        const int src = s_src[active ? li : 0];
+        if (lane == 0 && active) Lpre = s_lpre[li];
+        // the source block's loads go out first; the normals do not need them
+        const Store* xin = static_cast<const Store*>(a.x1[ppar]) + (static_cast<int64_t>(src) * N) * DX;
+        Store xr[PPT][DX];
+#pragma unroll
+        for (int r = 0; r < PPT; ++r)
+#pragma unroll
+          for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? get(xin + (j0 + r) * DX + d) : Store(0);
+        double z[NZ];
+        draw_normals(z);
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          double xp[DX];
+#pragma unroll
+          for (int d = 0; d < DX; ++d) xp[d] = static_cast<double>(xr[r][d]);
+          Model::template prop<Store>(a.mp, xp, z + r * DX, x[r]);
+        }
+      }
+
+      // ---- what the score records: the state entering this weighting ----
+      if (active) {
+        if (a.rec_x) {
+          Store* rx = static_cast<Store*>(a.rec_x) + ((n - a.n0) * m + k) * static_cast<int64_t>(N) * DX;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r)
+#pragma unroll
+            for (int d = 0; d < DX; ++d)
+              if (j0 + r < N) rx[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
+        }
+        if (a.ck_every > 0 && n % a.ck_every == 0 && !replay && a.ck_x) {
+          Store* xc = static_cast<Store*>(a.ck_x) + (n / a.ck_every) * (static_cast<int64_t>(m) * N * DX) +
+                      static_cast<int64_t>(k) * N * DX;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r)
+#pragma unroll
+            for (int d = 0; d < DX; ++d)
+              if (j0 + r < N) xc[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
+          if (lane == 0) a.ck_L[(n / a.ck_every) * m + k] = Lpre;
+        }
+        if (lane == 0 && a.tr_lpre && !replay) a.tr_lpre[n * m + k] = Lpre;
+      }
+
+      // ---- weighting ----
+      const double* yn = a.y + n * a.dy;
+      double lw[PPT];
+      double mx = ninf();
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        const bool valid = active && (j0 + r < N);
+        double v = valid ? Model::logpot(a.mp, x[r], yn) : ninf();
+        if (!(v == v)) v = ninf();
+        lw[r] = v;
+        mx = fmax(mx, v);
+      }
+      mx = team_max(mx, TP, red_d);
+      uint64_t q[PPT];
+      uint64_t tsum = 0;
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        q[r] = (mx == ninf()) ? 0 : static_cast<uint64_t>(dexp(lw[r] - mx) * 0x1p40);
+        tsum += q[r];
+      }
+      const uint64_t incl = team_scan_u64(tsum, TP, red_u);
+      // Q = sum_i q_i of the island: the scan's value in the team's last lane
+      const uint64_t Qk = TP <= 64 ? __shfl(incl, (tid & 63) | (TP - 1), 64) : team_sum_u64(tsum, TP, red_u);
+      if (lane == 0 && active && !replay) {
+        const double L = (Qk == 0) ? ninf() : Lpre + ((mx + dlog(static_cast<double>(Qk))) + a.cst_q);
+        lvp(par)[li] = L;
+        if (a.tr_lpost) a.tr_lpost[n * m + k] = L;
+      }
+
+      // ---- internal resampling ----
+      if (n < a.T - 1) {
+        Store* sxt = sx + team * TP * NZ;
+        uint64_t* sCt = sC + team * TP * PPT;
+        uint64_t run = incl - tsum;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          run += q[r];
+          sCt[j0 + r] = run;
+#pragma unroll
+          for (int d = 0; d < DX; ++d) sxt[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
+        }
+        uint64_t U = 0;
+        if (lane == 0 && active && Qk > 0)
+          U = bounded_u64_from(wsys, key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, Qk);
+        U = team_bcast(U, TP, bc_u);
+        team_sync(TP);
+        Store* xo = static_cast<Store*>(a.x1[par]) + (static_cast<int64_t>(k) * N) * DX;
+        int* sAt = sA + team * TP * PPT;
+        unsigned long long dig = 0;
+        // ancestors of this lane's slots: min{i : N C_i > U + j Q}; the
+        // lane's slots are consecutive and their ancestors non-decreasing, so
+        // one binary search finds the first and the rest advance from it
+        int prev = 0;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const int j = j0 + r;
+          if (active && j < N) {
+            int anc = j;
+            if (Qk > 0) {
+              const uint64_t t = U + static_cast<uint64_t>(j) * Qk;
+              int lo = prev;
+              if (r == 0) {
+                int hi = N - 1;
+                while (lo < hi) {
+                  const int mid = (lo + hi) >> 1;
+                  if (static_cast<uint64_t>(N) * sCt[mid] > t) hi = mid; else lo = mid + 1;
+                }
+              } else {
+                while (static_cast<uint64_t>(N) * sCt[lo] <= t) ++lo;
+              }
+              anc = lo;
+              prev = lo;
+            }
+            sAt[j] = anc;
+            if (a.tr_anc) a.tr_anc[(n * m + k) * static_cast<int64_t>(N) + j] = anc;
+            if (a.rec_anc) a.rec_anc[((n - a.n0) * m + k) * static_cast<int64_t>(N) + j] = static_cast<uint16_t>(anc);
+            if (a.tr_digest) dig += digest_term(n, k, j, anc);
+          }
+        }
+        if (a.tr_digest) {
+          dig = team_sum_u64(dig, TP, red_u);
+          if (lane == 0 && active) atomicAdd(&a.tr_digest[2 * n], dig);
+        }
+        team_sync(TP);
+        // the resampled block, written word by word with consecutive lanes on
+        // consecutive words so every store instruction covers whole lines
+        if (active) {
+#pragma unroll
+          for (int r = 0; r < NZ; ++r) {
+            const int w = r * TP + lane;
+            const int j = w / DX, d = w - j * DX;
+            if (j < N) put(xo + w, sxt[sAt[j] * DX + d]);
+          }
+        }
+        team_sync(TP);
+      }
+    }
+    __syncthreads();
+    if (replay || (never && n < a.T - 1)) continue;
+
+    // ---- this block's part of the island tree and the ENF partial records ----
+    double* lv = lvp(par);
+    if (c <= 64) {
+      // one wave: lane i holds value i of the level below
+      if (wave == 0) {
+        double v = (lane64 < c) ? lv[lane64] : ninf();
+        for (int l = 2; l <= lc + 1; ++l) {
+          const int cnt = c >> (l - 1);
+          const int o = 2 * c - ((2 * c) >> (l - 1));
+          const double v0 = __shfl(v, (2 * lane64) & 63, 64), v1 = __shfl(v, (2 * lane64 + 1) & 63, 64);
+          const double nv = lane64 < cnt ? pair_mean(v0, v1) : ninf();
+          if (lane64 < cnt) lv[o + lane64] = nv;
+          v = nv;
+        }
+      }
+    } else {
+      for (int l = 2; l <= lc + 1; ++l) {
+        const int cnt = c >> (l - 1);
+        const int o_prev = 2 * c - ((2 * c) >> (l - 2)), o = 2 * c - ((2 * c) >> (l - 1));
+        for (int i = tid; i < cnt; i += kBlock) lv[o + i] = pair_mean(lv[o_prev + 2 * i], lv[o_prev + 2 * i + 1]);
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    for (int l = 1; l <= lc + 1; ++l) {
+      const int cnt = c >> (l - 1);
+      const int o = 2 * c - ((2 * c) >> (l - 1));
+      double* dst = a.tree[par] + tree_off(m, l) + (kbase >> (l - 1));
+      for (int i = tid; i < cnt; i += kBlock) put(dst + i, lv[o + i]);
+    }
+    // ENF record of each level's values in this block, one wave per level
+    for (int l = 1 + wave; l <= lc + 1; l += kWaves) {
+      const int cnt = c >> (l - 1);
+      const int o = 2 * c - ((2 * c) >> (l - 1));
+      const EnfRec r = wave_reduce_enf(cnt, [&](int i) { return enf_leaf(lv[o + i]); });
+      if (lane64 == 0) {
+        double* pl = a.part[par] + static_cast<int64_t>(l - 1) * 3 * G;
+        put(pl + bid, r.E);
+        put(pl + G + bid, r.a);
+        put(pl + 2 * G + bid, r.b);
+      }
+    }
+  }
+
+  // ---- log Zhat after the last weighting: log of the mean island weight,
+  // the root of the island tree ----
+  if (replay || a.n1 < a.T) return;
+  if (!grid_barrier(a.bar, G, bid, epoch, a.status)) return;
+  if (bid == 0) {
+    up_top = 0;
+    build_upper_to(static_cast<int>((a.T - 1) & 1), S + 1);
+    const double lroot = up[2 * G - 2];
+    if (tid == 0) {
+      *a.out_logz = lroot;
+      if (a.tr_sstar) a.tr_sstar[a.T - 1] = 0;
+    }
+  }
+}
+
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
+  forward_body<Model, Store, PPT>(a, static_cast<int>(blockIdx.x));
+}
+
+// Several problems in one cooperative launch: block b runs block bmap[b].y of
+// problem bmap[b].x; each problem synchronises only its own blocks.
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void forward_batch_kernel(const FwdArgs* probs, const int2* bmap) {
+  const int2 pb = bmap[blockIdx.x];
+  forward_body<Model, Store, PPT>(probs[pb.x], pb.y);
+}
+
+}  // namespace airpf
+
+// ============================================================ host launcher
+
+namespace airpf {
+
+inline int pow2_ceil(int v) { int p = 1; while (p < v) p <<= 1; return p; }
+inline int ilog2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
+
+inline size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) {
+  const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
+  return sx + 8 * size_t(kBlock) * ppt + 4 * size_t(kBlock) * ppt + 8 * 4 * size_t(c) + 8 * 2 * size_t(G);
+}
+
+template <class Model, typename Store, int PPT>
+static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
+  auto kern = forward_kernel<Model, Store, PPT>;
+  const int TP = pow2_ceil((a.N + PPT - 1) / PPT);
+  const int tpb = kBlock / TP;
+  int G = a.m / tpb;
+  if (G < 1) G = 1;
+  if (G > L.max_blocks) G = L.max_blocks;
+  G = 1 << ilog2i(G + 1) >> 1;                  // power of two <= G
+  if (G < 1) G = 1;
+  size_t smem = 0;
+  for (; G >= 1; G >>= 1) {
+    const int c = a.m / G;
+    smem = fwd_smem_bytes(sizeof(Store), PPT, Model::DX, c, G);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, smem);
+    if (e != hipSuccess) return e;
+    if (static_cast<long>(per_cu) * L.num_cus >= G) break;
+  }
+  if (G < 1) return hipErrorCooperativeLaunchTooLarge;
+  if (a.m / G > kMaxIslandsPerBlock) return hipErrorInvalidValue;     // islands per block are bounded by the LDS plan
+  a.TP = TP;
+  a.G = G;
+  a.c = a.m / G;
+  a.lc = ilog2i(a.c);
+  plan->ppt = PPT; plan->tp = TP; plan->G = G; plan->c = a.c; plan->smem = smem;
+  if (L.plan_only) return hipSuccess;
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(G), dim3(kBlock), args,
+                                    static_cast<unsigned>(smem), L.stream);
+}
+
+// particles per lane: the smallest PPT with PPT*DX a multiple of four (a lane
+// consumes whole Philox blocks) and at most 256 lanes per island
+template <class Model, typename Store>
+static hipError_t dispatch_ppt(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan) {
+  constexpr int DX = Model::DX;
+  if constexpr (DX % 4 == 0) {
+    if (a.N <= 256) return launch_t<Model, Store, 1>(L, a, plan);
+    if (a.N <= 512) return launch_t<Model, Store, 2>(L, a, plan);
+  } else if constexpr (DX % 2 == 0) {
+    if (a.N <= 512) return launch_t<Model, Store, 2>(L, a, plan);
+  }
+  if (a.N <= 1024) return launch_t<Model, Store, 4>(L, a, plan);
+  return launch_t<Model, Store, 8>(L, a, plan);
+}
+
+template <class Model, typename Store, int PPT>
+static hipError_t batch_fwd_t(const BatchLaunch& L, int* cap) {
+  auto kern = forward_batch_kernel<Model, Store, PPT>;
+  if (cap) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, L.smem);
+    *cap = per_cu * L.num_cus;
+    return e;
+  }
+  const void* probs = L.probs;
+  const int2* bmap = L.bmap;
+  void* args[] = {&probs, &bmap};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(L.blocks), dim3(kBlock), args,
+                                    static_cast<unsigned>(L.smem), L.stream);
+}
+
+template <class Model, typename Store>
+static hipError_t batch_fwd_ppt(const BatchLaunch& L, int* cap) {
+  switch (forward_ppt(L.kind, L.dx, L.n_max)) {
+    case 1: if constexpr (Model::DX % 4 == 0) return batch_fwd_t<Model, Store, 1>(L, cap); break;
+    case 2: if constexpr (Model::DX % 2 == 0) return batch_fwd_t<Model, Store, 2>(L, cap); break;
+    case 4: return batch_fwd_t<Model, Store, 4>(L, cap);
+    case 8: return batch_fwd_t<Model, Store, 8>(L, cap);
+  }
+  return hipErrorInvalidValue;
+}
+
+// one model's launches in both storage precisions (each model's kernels are
+// compiled in a translation unit of their own)
+template <class Model>
+hipError_t fwd_launch_model(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan) {
+  return L.fp64 ? dispatch_ppt<Model, double>(L, a, plan) : dispatch_ppt<Model, float>(L, a, plan);
+}
+template <class Model>
+hipError_t fwd_batch_model(const BatchLaunch& L, int* cap) {
+  return L.fp64 ? batch_fwd_ppt<Model, double>(L, cap) : batch_fwd_ppt<Model, float>(L, cap);
+}
+
+hipError_t fwd_launch_lg1(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
+hipError_t fwd_batch_lg1(const BatchLaunch& L, int* cap);
+hipError_t fwd_launch_sv(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
+hipError_t fwd_batch_sv(const BatchLaunch& L, int* cap);
+hipError_t fwd_launch_lgd2(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
+hipError_t fwd_batch_lgd2(const BatchLaunch& L, int* cap);
+hipError_t fwd_launch_lgd3(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
+hipError_t fwd_batch_lgd3(const BatchLaunch& L, int* cap);
+hipError_t fwd_launch_lgd4(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
+hipError_t fwd_batch_lgd4(const BatchLaunch& L, int* cap);
+hipError_t fwd_launch_lgd8(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
+hipError_t fwd_batch_lgd8(const BatchLaunch& L, int* cap);
+
+}  // namespace airpf

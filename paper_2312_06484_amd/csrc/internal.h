@@ -19,7 +19,7 @@ struct FwdArgs {
   int no_interaction;         // tau <= 1/(2m): no stage can interact (ENF >= 1/m)
   void* x1[2];                // Store*, resampled blocks, [m*N*DX] particle-major
   double* tree[2];            // [2m] pair-mean tree of island log-weights
-  double* part[2];            // [(lc+1)*3*G] per level: the blocks' ENF records (max, sum w, sum w^2)
+  double* part[2];            // [(lc+1)*3*G] per level: the blocks' ENF records (E, a, b)
   unsigned* bar;              // [G] grid-barrier flags, zero before the launch
   int* status;                // [1] 0 ok, 1 barrier timed out
   double* out_logz;           // [1]
