@@ -637,7 +637,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   airpf::BatchLaunch BL;
   BL.kind = model->kind; BL.dx = dx; BL.fp64 = fp64; BL.n_max = n_max; BL.num_cus = ctx->num_cus;
   BL.stream = s; BL.blocks = 0; BL.probs = nullptr; BL.bmap = nullptr;
-  BL.smem = airpf::forward_smem(fp64, ppt_f, dx, 256, 256);     // bound of any tiling below
+  BL.smem = airpf::forward_smem(fp64, ppt_f, dx, 256, 256, airpf::kResidentBudget);   // bound of any tiling below
   int cap_f = 0;
   HIP_OK(airpf::forward_batch_capacity(BL, &cap_f));
   int cap_b = 0;
@@ -724,6 +724,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
     fa.clear();
     ba.clear();
     int c_max = 1, G_max = 1;
+    size_t res_max = 0;
     for (size_t i = 0; i < act.size(); ++i) {
       Item& it = *act[i];
       for (int b = 0; b < it.G; ++b) bmap.push_back(make_int2(int(i), b));
@@ -738,6 +739,9 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
         a.lc = ilog2(a.c); a.dy = dy; a.seed = it.seed; a.tau = opt.tau; a.cst_q = it.cst_q;
         a.shortcut_all = opt.tau > 1.0 + 1e-9;
         a.no_interaction = opt.tau <= 0.5 / it.m;
+        const size_t res = airpf::forward_resident_bytes(fp64, dx, a.c, it.N);
+        a.res_lds = res > 0;
+        res_max = std::max(res_max, res);
         for (int p = 0; p < 2; ++p) {
           a.x1[p] = at(it.o_x1[p]);
           a.tree[p] = static_cast<double*>(at(it.o_tree[p]));
@@ -775,7 +779,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
     // the batched forward kernel's LDS plan must cover every problem's tiling
     airpf::BatchLaunch L = BL;
     L.blocks = int(bmap.size());
-    L.smem = mode == 0 ? airpf::forward_smem(fp64, ppt_f, dx, c_max, G_max) : airpf::backward_smem(fp64, ppt_b, dx);
+    L.smem = mode == 0 ? airpf::forward_smem(fp64, ppt_f, dx, c_max, G_max, res_max) : airpf::backward_smem(fp64, ppt_b, dx);
     void* d_args = at(o_args);
     if (mode == 0) HIP_OK(hipMemcpyAsync(d_args, fa.data(), sizeof(airpf::FwdArgs) * fa.size(), hipMemcpyHostToDevice, s));
     else HIP_OK(hipMemcpyAsync(d_args, ba.data(), sizeof(airpf::BwdArgs) * ba.size(), hipMemcpyHostToDevice, s));

@@ -69,11 +69,16 @@ __device__ __forceinline__ T get(const T* p) {
 // completed (s_waitcnt 0), so the block's device-scope stores are visible
 // to any device-scope load issued after the flag is seen.  Spinning is
 // bounded: after ~2^24 polls a block raises status and leaves.
-__device__ bool grid_barrier(unsigned* flags, int G, int bid, unsigned& epoch, int* status) {
+// Split into its two halves so that a block can do work that does not
+// depend on the other blocks between publishing its flag and waiting.
+__device__ __forceinline__ void grid_arrive(unsigned* flags, int bid, unsigned& epoch) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   ++epoch;
   if (threadIdx.x == 0) put(&flags[bid], epoch);
+}
+
+__device__ bool grid_wait(const unsigned* flags, int G, unsigned epoch, int* status) {
   int ok = 1;
   for (int i = threadIdx.x; i < G && ok; i += kBlock) {
     unsigned spins = 0;
@@ -88,6 +93,11 @@ __device__ bool grid_barrier(unsigned* flags, int G, int bid, unsigned& epoch, i
   }
   ok = __syncthreads_and(ok);
   return ok != 0;
+}
+
+__device__ __forceinline__ bool grid_barrier(unsigned* flags, int G, int bid, unsigned& epoch, int* status) {
+  grid_arrive(flags, bid, epoch);
+  return grid_wait(flags, G, epoch, status);
 }
 
 // ------------------------------------------------------------ DPP lane moves

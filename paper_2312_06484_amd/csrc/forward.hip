@@ -33,9 +33,11 @@ int forward_ppt(int kind, int dx, int n) {
   return n <= 1024 ? 4 : 8;
 }
 
-size_t forward_smem(int fp64, int ppt, int dx, int c, int G) {
-  return fwd_smem_bytes(fp64 ? 8 : 4, ppt, dx, c, G);
+size_t forward_smem(int fp64, int ppt, int dx, int c, int G, size_t resident) {
+  return fwd_smem_bytes(fp64 ? 8 : 4, ppt, dx, c, G) + resident;
 }
+
+size_t forward_resident_bytes(int fp64, int dx, int c, int N) { return fwd_res_bytes(fp64 ? 8 : 4, dx, c, N); }
 
 static hipError_t batch_fwd(const BatchLaunch& L, int* cap) {
   switch (L.kind) {

@@ -75,6 +75,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   int* sA = reinterpret_cast<int*>(sC + kBlock * PPT);                             // [kBlock*PPT]
   double* lvb = reinterpret_cast<double*>(sA + kBlock * PPT);                      // [2][2c]
   double* up = lvb + 4 * c;                                                       // [2G]
+  // with res_lds: this block's resampled states of the last two steps, by
+  // step parity, island-major as in HBM ([2][c*N*DX])
+  Store* res = reinterpret_cast<Store*>(up + 2 * G);
+  const int64_t res_words = static_cast<int64_t>(c) * N * DX;
   // this block's part of the island tree (levels 1 .. lc+1, level l at
   // offset 2c - 2c/2^(l-1)), one copy per step parity: the walk of step n
   // reads step n-1's copy while the weighting writes step n's
@@ -120,12 +124,50 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   };
 
   const bool replay = a.replay_pi != 0;
-  for (int64_t n = a.n0; n < a.n1; ++n) {
-    const int par = static_cast<int>(n & 1), ppar = par ^ 1;
-    if (n > a.n0 && !never) {
-      if (!grid_barrier(a.bar, G, bid, epoch, a.status)) return;
+  // normals of (step, island, particle) for this lane's particles
+  auto draw_normals = [&](int64_t n, int k, int j0, double* z) {
+    for (int g = 0; g < NZ / 4; ++g) {
+      double t[4];
+      normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
     }
-    if (n > a.n0 && !replay && !never) {
+  };
+  // Speculation: the stages of most steps do not interact (s* = 0), and then
+  // every island continues from its own resampled block with its own weight,
+  // all of which this block holds.  With the resampled states resident in
+  // LDS, a block runs step n's passes under that assumption right after
+  // publishing step n-1, while the other blocks arrive; the cascade then
+  // confirms s* = 0 (the speculative results are kept and the resampled
+  // blocks written out) or the step is run again as usual.  The results are
+  // the same either way.
+  const bool spec_on = a.res_lds && !never && !replay && !a.shortcut_all && !a.tr_enf && !a.tr_sstar && !a.tr_pi &&
+                       !a.tr_lpost && !a.tr_anc && !a.tr_digest && !a.tr_lpre && !a.rec_x && !a.rec_anc && !a.ck_x &&
+                       !a.ck_in;
+  bool pending = false;     // step n-1 is published and its cascade not yet taken
+  bool spec_done = false;   // step n's passes have run speculatively
+  int64_t n = a.n0;
+  while (n < a.n1) {
+    const int par = static_cast<int>(n & 1), ppar = par ^ 1;
+    const bool spec = spec_on && pending && !spec_done;
+    // the first pass's draws (its normals and the systematic offset's first
+    // block) do not depend on the other blocks: they are taken between
+    // publishing this block's flag and waiting for the others
+    double z_first[NZ];
+    uint32_t wsys_first[4] = {0u, 0u, 0u, 0u};
+    bool first_drawn = false;
+    bool skip_passes = false;
+    if (pending && !spec) {
+      if (!spec_done) {
+        const int k0 = kbase + (team < c ? team : 0);
+        draw_normals(n, k0, lane * PPT, z_first);
+        if (n < a.T - 1 && lane == 0) draw4(key, 0, static_cast<uint32_t>(k0), static_cast<uint32_t>(n), kTagSys, 0, wsys_first);
+        first_drawn = true;
+      }
+      if (!grid_wait(a.bar, G, epoch, a.status)) return;
+      pending = false;
+    }
+    if (n > a.n0 && !replay && !never && !spec) {
       // ---- cascade of step n-1 (every block, identical) ----
       up_top = 0;
       int sstar = 0;
@@ -188,8 +230,19 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       }
       s_sstar = sstar;
       __syncthreads();
+      if (spec_done) {
+        spec_done = false;
+        if (sstar == 0) {
+          // speculation confirmed: write the resampled blocks out
+          if (n < a.T - 1) {
+            Store* xo_blk = static_cast<Store*>(a.x1[par]) + static_cast<int64_t>(kbase) * N * DX;
+            for (int64_t w = tid; w < res_words; w += kBlock) put(xo_blk + w, res[par * res_words + w]);
+          }
+          skip_passes = true;
+        }
+      }
     }
-    const int sstar = (n > a.n0 && !replay && !never) ? s_sstar : 0;
+    const int sstar = (n > a.n0 && !replay && !never && !spec) ? s_sstar : 0;
 
     // ---- the source block and entering weight of every island of the block,
     // all islands at once: island k walks the interacting stages s*, ..., 1;
@@ -199,7 +252,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     // Algorithm 1 applies to every island.  Its entering weight is its
     // 2^{s*}-block mean.
     const bool mutate = n != 0 && !(n == a.n0 && a.ck_in);
-    if (mutate) {
+    if (!skip_passes) {
+    if (mutate && !spec) {
       for (int li = tid; li < c; li += kBlock) {
         const int k = kbase + li;
         int cur = k;
@@ -232,18 +286,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       const int j0 = lane * PPT;
 
       // ---- mutation (or initial draw) ----
-      // normals of (step n, island k), this lane's particles
-      auto draw_normals = [&](double* z) {
-        for (int g = 0; g < NZ / 4; ++g) {
-          double t[4];
-          normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
-        }
-      };
+      const bool pre = first_drawn && p == 0;
       // sub-block 0 of the systematic offset's draw (it does not depend on Q)
-      uint32_t wsys[4] = {0u, 0u, 0u, 0u};
-      if (n < a.T - 1 && lane == 0) draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
+      uint32_t wsys[4] = {wsys_first[0], wsys_first[1], wsys_first[2], wsys_first[3]};
+      if (!pre && n < a.T - 1 && lane == 0) draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
       double x[PPT][DX];
       double Lpre = 0.0;
       if (n == a.n0 && a.ck_in) {
@@ -257,21 +303,35 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         if (lane == 0) Lpre = a.ck_L[(n / a.ck_every) * m + k];
       } else if (n == 0) {
         double z[NZ];
-        draw_normals(z);
+        draw_normals(n, k, j0, z);
 #pragma unroll
         for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * DX, x[r]);
       } else {
-        const int src = s_src[active ? li : 0];
-        if (lane == 0 && active) Lpre = s_lpre[li];
-        // the source block's loads go out first; the normals do not need them
-        const Store* xin = static_cast<const Store*>(a.x1[ppar]) + (static_cast<int64_t>(src) * N) * DX;
+        const int src = spec ? k : s_src[active ? li : 0];
+        if (lane == 0 && active) Lpre = spec ? lvp(ppar)[li] : s_lpre[li];
+        // the source block's loads go out first; the normals do not need them.
+        // A source island of this block is read from its LDS copy.
         Store xr[PPT][DX];
+        if (a.res_lds && src >= kbase && src < kbase + c) {
+          const Store* xin = res + ppar * res_words + static_cast<int64_t>(src - kbase) * N * DX;
 #pragma unroll
-        for (int r = 0; r < PPT; ++r)
+          for (int r = 0; r < PPT; ++r)
 #pragma unroll
-          for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? get(xin + (j0 + r) * DX + d) : Store(0);
+            for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? xin[(j0 + r) * DX + d] : Store(0);
+        } else {
+          const Store* xin = static_cast<const Store*>(a.x1[ppar]) + (static_cast<int64_t>(src) * N) * DX;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r)
+#pragma unroll
+            for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? get(xin + (j0 + r) * DX + d) : Store(0);
+        }
         double z[NZ];
-        draw_normals(z);
+        if (pre) {
+#pragma unroll
+          for (int i = 0; i < NZ; ++i) z[i] = z_first[i];
+        } else {
+          draw_normals(n, k, j0, z);
+        }
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           double xp[DX];
@@ -395,14 +455,20 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           for (int r = 0; r < NZ; ++r) {
             const int w = r * TP + lane;
             const int j = w / DX, d = w - j * DX;
-            if (j < N) put(xo + w, sxt[sAt[j] * DX + d]);
+            if (j < N) {
+              const Store v = sxt[sAt[j] * DX + d];
+              if (!spec) put(xo + w, v);
+              if (a.res_lds) res[par * res_words + static_cast<int64_t>(li) * N * DX + w] = v;
+            }
           }
         }
         team_sync(TP);
       }
     }
     __syncthreads();
-    if (replay || (never && n < a.T - 1)) continue;
+    if (spec) { spec_done = true; continue; }
+    }  // !skip_passes
+    if (!(replay || (never && n < a.T - 1))) {
 
     // ---- this block's part of the island tree and the ENF partial records ----
     double* lv = lvp(par);
@@ -446,6 +512,12 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         put(pl + 2 * G + bid, r.b);
       }
     }
+    }  // tree
+    ++n;
+    if (n < a.n1 && !never) {
+      grid_arrive(a.bar, bid, epoch);
+      pending = true;
+    }
   }
 
   // ---- log Zhat after the last weighting: log of the mean island weight,
@@ -485,6 +557,11 @@ namespace airpf {
 inline int pow2_ceil(int v) { int p = 1; while (p < v) p <<= 1; return p; }
 inline int ilog2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
 
+inline size_t fwd_res_bytes(size_t store_bytes, int dx, int c, int N) {
+  const size_t b = 2 * store_bytes * size_t(dx) * size_t(c) * size_t(N);
+  return b <= kResidentBudget ? b : 0;
+}
+
 inline size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) {
   const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
   return sx + 8 * size_t(kBlock) * ppt + 4 * size_t(kBlock) * ppt + 8 * 4 * size_t(c) + 8 * 2 * size_t(G);
@@ -503,7 +580,7 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
   size_t smem = 0;
   for (; G >= 1; G >>= 1) {
     const int c = a.m / G;
-    smem = fwd_smem_bytes(sizeof(Store), PPT, Model::DX, c, G);
+    smem = fwd_smem_bytes(sizeof(Store), PPT, Model::DX, c, G) + fwd_res_bytes(sizeof(Store), Model::DX, c, a.N);
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, smem);
     if (e != hipSuccess) return e;
@@ -515,6 +592,7 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
   a.G = G;
   a.c = a.m / G;
   a.lc = ilog2i(a.c);
+  a.res_lds = fwd_res_bytes(sizeof(Store), Model::DX, a.c, a.N) > 0;
   plan->ppt = PPT; plan->tp = TP; plan->G = G; plan->c = a.c; plan->smem = smem;
   if (L.plan_only) return hipSuccess;
   void* args[] = {&a};

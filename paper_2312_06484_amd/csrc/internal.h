@@ -17,6 +17,7 @@ struct FwdArgs {
   double tau, cst_q;
   int shortcut_all;           // tau > 1: every stage interacts
   int no_interaction;         // tau <= 1/(2m): no stage can interact (ENF >= 1/m)
+  int res_lds;                // 1: a block also keeps its resampled states in LDS (one copy per step parity)
   void* x1[2];                // Store*, resampled blocks, [m*N*DX] particle-major
   double* tree[2];            // [2m] pair-mean tree of island log-weights
   double* part[2];            // [(lc+1)*3*G] per level: the blocks' ENF records (E, a, b)
@@ -96,7 +97,13 @@ struct BatchLaunch {
   hipStream_t stream;
 };
 int forward_ppt(int kind, int dx, int n_max);
-size_t forward_smem(int fp64, int ppt, int dx, int c, int G);
+// dynamic LDS of a forward block with c islands of a G-block problem, plus
+// `resident` bytes of LDS-resident resampled states (forward_resident_bytes)
+size_t forward_smem(int fp64, int ppt, int dx, int c, int G, size_t resident);
+// LDS for both parity copies of a block's resampled states, or 0 when they
+// exceed the budget kResidentBudget (the states then come from HBM only)
+size_t forward_resident_bytes(int fp64, int dx, int c, int N);
+constexpr size_t kResidentBudget = 32768;
 hipError_t forward_batch_capacity(const BatchLaunch& L, int* blocks);   // co-resident blocks at L.smem
 hipError_t launch_forward_batch(const BatchLaunch& L);
 int backward_ppt(int kind, int dx, int n_max);                          // 0: unsupported

@@ -212,3 +212,29 @@ def test_untraced_run_without_interactions(ctx, orc, model, m, N, T, tau, f64, d
     assert (gt.sstar == 0).all()
     lo = orc.run(P, tau=tau, store_f32=not f64)
     assert abs(lz - lo) <= 1e-12 * max(1.0, abs(lo)), (lz, lo)
+
+
+@pytest.mark.parametrize("model,m,N,T,tau,f64,dx", [
+    ("lg1", 1024, 256, 300, 0.3, False, None),     # the benchmark width: s* = 0 on most steps
+    ("sv", 4096, 128, 150, 0.3, False, None),      # 16 islands per block
+    ("lg1", 64, 64, 200, 0.9, True, None),         # frequent interactions
+    ("lgd", 256, 32, 60, 0.5, False, 4),
+    ("sv", 512, 37, 80, 0.6, False, None),         # ragged N
+])
+def test_untraced_run_matches_traced(ctx, orc, model, m, N, T, tau, f64, dx):
+    """An untraced run may take each step's passes before the step's
+    interaction count is known (assuming no stage interacts) and redo them
+    when some stage does; its log Zhat must equal the traced run's bit for
+    bit, and the oracle's."""
+    g, P = make_case(orc, model, m, N, T, 5, dx)
+    print("case", model, dx, m, N, T, tau, flush=True)
+    from paper_2312_06484_amd import airpf
+    gt = airpf.Trace(T, m, N, enf=False, anc=False, digest=False, lpost=False)
+    _, lz_traced = ctx.run(g["kind"], g["theta"], g["y"], m, N, 5, tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"],
+                           consts=g["consts"], trace=gt)
+    _, lz = ctx.run(g["kind"], g["theta"], g["y"], m, N, 5, tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"],
+                    consts=g["consts"])
+    print("steps with interactions:", int((gt.sstar[:-1] > 0).sum()), "of", T - 1, flush=True)
+    assert lz == lz_traced
+    lo = orc.run(P, tau=tau, store_f32=not f64)
+    assert abs(lz - lo) <= 1e-12 * max(1.0, abs(lo)), (lz, lo)
