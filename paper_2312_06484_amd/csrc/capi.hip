@@ -636,6 +636,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   }
   airpf::BatchLaunch BL;
   BL.kind = model->kind; BL.dx = dx; BL.fp64 = fp64; BL.n_max = n_max; BL.num_cus = ctx->num_cus;
+  BL.plain = want_score ? 0 : 1;          // the score's forward launches record and replay
   BL.stream = s; BL.blocks = 0; BL.probs = nullptr; BL.bmap = nullptr;
   BL.smem = airpf::forward_smem(fp64, ppt_f, dx, 256, 256, airpf::kResidentBudget);   // bound of any tiling below
   int cap_f = 0;

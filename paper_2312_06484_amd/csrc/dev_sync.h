@@ -12,6 +12,7 @@ namespace airpf {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxIslandsPerBlock = 256;   // the LDS plan of the forward kernel
+constexpr int kPiCache = 4096;             // island maps the reverse kernel caches in LDS per step
 
 
 __device__ __forceinline__ int64_t tree_off(int m, int level) {  // level >= 1
@@ -217,10 +218,16 @@ __device__ __forceinline__ uint64_t team_scan_u64(uint64_t v, int TP, uint64_t* 
   return v;
 }
 
-// sum of a double over the team's lanes (fixed pattern; every lane gets it)
+// sum of a double over the team's lanes (fixed pattern; every lane gets it):
+// partners xor 1, xor 2, the 8- and 16-lane mirrors, xor 16, xor 32 (each
+// adds the other half of its group, so every lane holds the same bits)
 __device__ __forceinline__ double team_sum_f64(double v, int TP, double* red) {
-  const int w = TP < 64 ? TP : 64;
-  for (int d = 1; d < w; d <<= 1) v += __shfl_xor(v, d, 64);
+  if (TP >= 2) v += dppd<0xB1>(v);
+  if (TP >= 4) v += dppd<0x4E>(v);
+  if (TP >= 8) v += dppd<0x141>(v);
+  if (TP >= 16) v += dppd<0x140>(v);
+  if (TP >= 32) v += __shfl_xor(v, 16, 64);
+  if (TP >= 64) v += __shfl_xor(v, 32, 64);
   if (TP > 64) {
     const int tid = threadIdx.x;
     if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -234,15 +241,18 @@ __device__ __forceinline__ double team_sum_f64(double v, int TP, double* red) {
   return v;
 }
 
-// inclusive scan of a double over the team's lanes (lane order)
+// inclusive scan of a double over the team's lanes (lane order), in the
+// pattern of team_scan_u64
 __device__ __forceinline__ double team_scan_f64(double v, int TP, double* red) {
   const int tid = threadIdx.x;
-  const int w = TP < 64 ? TP : 64;
-  const int sl = tid & (w - 1);
-  for (int d = 1; d < w; d <<= 1) {
-    const double t = __shfl_up(v, d, w);
-    if (sl >= d) v += t;
-  }
+  const int sl = tid & ((TP < 64 ? TP : 64) - 1);
+  double t;
+  if (TP > 1) { t = dppd<0x111>(v); if (sl >= 1) v += t; }
+  if (TP > 2) { t = dppd<0x112>(v); if (sl >= 2) v += t; }
+  if (TP > 4) { t = dppd<0x114>(v); if (sl >= 4) v += t; }
+  if (TP > 8) { t = dppd<0x118>(v); if (sl >= 8) v += t; }
+  if (TP > 16) v += __longlong_as_double(static_cast<long long>(dpp64<0x142, 0xa>(static_cast<uint64_t>(__double_as_longlong(v)))));
+  if (TP > 32) v += __longlong_as_double(static_cast<long long>(dpp64<0x143, 0xc>(static_cast<uint64_t>(__double_as_longlong(v)))));
   if (TP > 64) {
     if ((tid & 63) == 63) red[tid >> 6] = v;
     __syncthreads();

@@ -19,19 +19,20 @@
 //                min{i : N C_i > U + j Q}, U uniform on [0, Q);
 //   island tree  pair means log((W_a + W_b)/2) of aligned blocks, level by
 //                level (the normaliser line of Algorithm 1 applied to a
-//                block's two halves); published with per-level partial sums
-//                of W^2 for the ENF.
+//                block's two halves); published with one ENF record
+//                (E, a, b) per level (a = sum W 2^-E, b = sum W^2 2^-2E).
 // After the barrier every block evaluates the ENF of each stage from the
-// published partials, s* = the number of leading stages with ENF < tau, and
+// published records, s* = the number of leading stages with ENF < tau, and
 // walks each of its islands down the stages s*, ..., 1: at stage s island
 // cur takes its partner cur ^ 2^(s-1) with probability
 // W_p / (W_cur + W_p) (draw at (step, island cur, stage s)).  The island's
 // next weight is its 2^{s*}-block mean.
 //
 // ENF at stage s (W the weights after s-1 interacting stages, B_b the sums of
-// the aligned 2^{s-1}-blocks): ENF_s = 2^{s-1} (sum W)^2 / (m sum_b B_b^2),
-// in logs 2 log sum W - log m - log sum_b exp(2 LT_b) - (s-1) log 2 with
-// LT_b = log(B_b / 2^{s-1}) the pair-mean tree value.
+// the aligned 2^{s-1}-blocks): every island holds its block mean, so
+// sum_k W_k = sum_b B_b and sum_k W_k^2 = 2^{s-1} sum_b (B_b / 2^{s-1})^2, and
+// ENF_s = (m^-1 sum W)^2 / (m^-1 sum W^2) follows from the record of the
+// level-s tree values (the block means B_b / 2^{s-1}).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_cooperative_groups.h>
@@ -47,7 +48,10 @@ namespace airpf {
 
 // One problem's filter, run by the G blocks of its sub-grid; `bid` is this
 // block's index within them.
-template <class Model, typename Store, int PPT>
+// Plain: a run with no traces, no score records, no replay and no
+// checkpoints, compiled on its own so that none of those paths (nor the
+// registers they hold) exist in it.
+template <class Model, typename Store, int PPT, bool Plain>
 __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;                 // normals per lane per step
@@ -69,6 +73,20 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   const int kbase = bid * c;
   const Key key = make_key(a.seed);
   const int passes = (c + tpb - 1) / tpb;
+  int32_t* const tr_sstar = Plain ? nullptr : a.tr_sstar;
+  double* const tr_enf = Plain ? nullptr : a.tr_enf;
+  double* const tr_lpost = Plain ? nullptr : a.tr_lpost;
+  int32_t* const tr_anc = Plain ? nullptr : a.tr_anc;
+  int32_t* const tr_pi = Plain ? nullptr : a.tr_pi;
+  unsigned long long* const tr_digest = Plain ? nullptr : a.tr_digest;
+  double* const tr_lpre = Plain ? nullptr : a.tr_lpre;
+  void* const rec_x = Plain ? nullptr : a.rec_x;
+  uint16_t* const rec_anc = Plain ? nullptr : a.rec_anc;
+  void* const ck_x = Plain ? nullptr : a.ck_x;
+  double* const ck_L = Plain ? nullptr : a.ck_L;
+  const int64_t ck_every = Plain ? 0 : a.ck_every;
+  const int ck_in = Plain ? 0 : a.ck_in;
+  const int64_t n0 = Plain ? 0 : a.n0, n1 = Plain ? a.T : a.n1;
 
   Store* sx = reinterpret_cast<Store*>(smem);                                    // [kBlock*NZ]
   uint64_t* sC = reinterpret_cast<uint64_t*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));
@@ -87,8 +105,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   unsigned epoch = 0;
   // tau so small that no stage can ever interact, and nothing traced or
   // recorded: the blocks are independent until the final log Zhat
-  const bool never = a.no_interaction && !a.tr_enf && !a.tr_sstar && !a.tr_pi && !a.tr_lpost && !a.tr_anc &&
-                     !a.tr_digest && !a.tr_lpre && !a.rec_x && !a.rec_anc && !a.ck_x && !a.ck_in;
+  const bool never = a.no_interaction && !tr_enf && !tr_sstar && !tr_pi && !tr_lpost && !tr_anc &&
+                     !tr_digest && !tr_lpre && !rec_x && !rec_anc && !ck_x && !ck_in;
 
   // levels lc+1 .. `level` of the island tree in `up`, built on demand from
   // the G published block roots (identical in every block); up_top is the
@@ -123,7 +141,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     return up[2 * G - ((2 * G) >> u) + idx];
   };
 
-  const bool replay = a.replay_pi != 0;
+  const bool replay = !Plain && a.replay_pi != 0;
   // normals of (step, island, particle) for this lane's particles
   auto draw_normals = [&](int64_t n, int k, int j0, double* z) {
     for (int g = 0; g < NZ / 4; ++g) {
@@ -141,13 +159,13 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   // confirms s* = 0 (the speculative results are kept and the resampled
   // blocks written out) or the step is run again as usual.  The results are
   // the same either way.
-  const bool spec_on = a.res_lds && !never && !replay && !a.shortcut_all && !a.tr_enf && !a.tr_sstar && !a.tr_pi &&
-                       !a.tr_lpost && !a.tr_anc && !a.tr_digest && !a.tr_lpre && !a.rec_x && !a.rec_anc && !a.ck_x &&
-                       !a.ck_in;
+  const bool spec_on = a.res_lds && !never && !replay && !a.shortcut_all && !tr_enf && !tr_sstar && !tr_pi &&
+                       !tr_lpost && !tr_anc && !tr_digest && !tr_lpre && !rec_x && !rec_anc && !ck_x &&
+                       !ck_in;
   bool pending = false;     // step n-1 is published and its cascade not yet taken
   bool spec_done = false;   // step n's passes have run speculatively
-  int64_t n = a.n0;
-  while (n < a.n1) {
+  int64_t n = n0;
+  while (n < n1) {
     const int par = static_cast<int>(n & 1), ppar = par ^ 1;
     const bool spec = spec_on && pending && !spec_done;
     // the first pass's draws (its normals and the systematic offset's first
@@ -167,7 +185,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       if (!grid_wait(a.bar, G, epoch, a.status)) return;
       pending = false;
     }
-    if (n > a.n0 && !replay && !never && !spec) {
+    if (n > n0 && !replay && !never && !spec) {
       // ---- cascade of step n-1 (every block, identical) ----
       up_top = 0;
       int sstar = 0;
@@ -215,8 +233,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           for (int t = s0; t <= s_hi; ++t) {
             const double enf = s_enf[t - s0];
             const bool go = enf < a.tau;
-            if (a.tr_enf && bid == 0 && tid == 0)
-              for (int q = t; q <= (go ? t : S); ++q) a.tr_enf[(n - 1) * (S + 1) + q] = enf;
+            if (tr_enf && bid == 0 && tid == 0)
+              for (int q = t; q <= (go ? t : S); ++q) tr_enf[(n - 1) * (S + 1) + q] = enf;
             if (!go) { stop = true; break; }
             sstar = t;
           }
@@ -225,8 +243,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         if (sstar + 1 > lc + 1) build_upper_to(ppar, sstar + 1);
       }
       if (bid == 0 && tid == 0) {
-        if (a.tr_sstar) a.tr_sstar[n - 1] = sstar;
-        if (a.tr_digest) atomicAdd(&a.tr_digest[2 * (n - 1) + 1], (unsigned long long)sstar * 0x9E3779B97F4A7C15ULL);
+        if (tr_sstar) tr_sstar[n - 1] = sstar;
+        if (tr_digest) atomicAdd(&tr_digest[2 * (n - 1) + 1], (unsigned long long)sstar * 0x9E3779B97F4A7C15ULL);
       }
       s_sstar = sstar;
       __syncthreads();
@@ -242,7 +260,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         }
       }
     }
-    const int sstar = (n > a.n0 && !replay && !never && !spec) ? s_sstar : 0;
+    const int sstar = (n > n0 && !replay && !never && !spec) ? s_sstar : 0;
 
     // ---- the source block and entering weight of every island of the block,
     // all islands at once: island k walks the interacting stages s*, ..., 1;
@@ -251,7 +269,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     // (step, cur, stage s)), which composes the per-stage selections that
     // Algorithm 1 applies to every island.  Its entering weight is its
     // 2^{s*}-block mean.
-    const bool mutate = n != 0 && !(n == a.n0 && a.ck_in);
+    const bool mutate = n != 0 && !(n == n0 && ck_in);
     if (!skip_passes) {
     if (mutate && !spec) {
       for (int li = tid; li < c; li += kBlock) {
@@ -259,7 +277,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         int cur = k;
         double lpre = 0.0;
         if (replay) {
-          cur = a.tr_pi[(n - 1) * m + k];
+          cur = tr_pi[(n - 1) * m + k];
         } else {
           for (int s = sstar; s >= 1; --s) {
             const int pr = cur ^ (1 << (s - 1));
@@ -270,8 +288,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
             if (uniform53(w[0], w[1]) < take_partner_prob(lc_, lp_)) cur = pr;
           }
           lpre = lt_value(ppar, sstar + 1, k >> sstar);
-          if (a.tr_pi) a.tr_pi[(n - 1) * m + k] = cur;
-          if (a.tr_digest) atomicAdd(&a.tr_digest[2 * (n - 1) + 1], digest_term(n - 1, k, 4095, cur));
+          if (tr_pi) tr_pi[(n - 1) * m + k] = cur;
+          if (tr_digest) atomicAdd(&tr_digest[2 * (n - 1) + 1], digest_term(n - 1, k, 4095, cur));
         }
         s_src[li] = cur;
         s_lpre[li] = lpre;
@@ -292,15 +310,15 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       if (!pre && n < a.T - 1 && lane == 0) draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
       double x[PPT][DX];
       double Lpre = 0.0;
-      if (n == a.n0 && a.ck_in) {
+      if (n == n0 && ck_in) {
         // restart from the checkpoint taken entering this step
-        const Store* xc = static_cast<const Store*>(a.ck_x) + (n / a.ck_every) * (static_cast<int64_t>(m) * N * DX) +
+        const Store* xc = static_cast<const Store*>(ck_x) + (n / ck_every) * (static_cast<int64_t>(m) * N * DX) +
                           static_cast<int64_t>(k) * N * DX;
 #pragma unroll
         for (int r = 0; r < PPT; ++r)
 #pragma unroll
           for (int d = 0; d < DX; ++d) x[r][d] = (j0 + r < N) ? static_cast<double>(xc[(j0 + r) * DX + d]) : 0.0;
-        if (lane == 0) Lpre = a.ck_L[(n / a.ck_every) * m + k];
+        if (lane == 0) Lpre = ck_L[(n / ck_every) * m + k];
       } else if (n == 0) {
         double z[NZ];
         draw_normals(n, k, j0, z);
@@ -343,25 +361,25 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 
       // ---- what the score records: the state entering this weighting ----
       if (active) {
-        if (a.rec_x) {
-          Store* rx = static_cast<Store*>(a.rec_x) + ((n - a.n0) * m + k) * static_cast<int64_t>(N) * DX;
+        if (rec_x) {
+          Store* rx = static_cast<Store*>(rec_x) + ((n - n0) * m + k) * static_cast<int64_t>(N) * DX;
 #pragma unroll
           for (int r = 0; r < PPT; ++r)
 #pragma unroll
             for (int d = 0; d < DX; ++d)
               if (j0 + r < N) rx[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
         }
-        if (a.ck_every > 0 && n % a.ck_every == 0 && !replay && a.ck_x) {
-          Store* xc = static_cast<Store*>(a.ck_x) + (n / a.ck_every) * (static_cast<int64_t>(m) * N * DX) +
+        if (ck_every > 0 && n % ck_every == 0 && !replay && ck_x) {
+          Store* xc = static_cast<Store*>(ck_x) + (n / ck_every) * (static_cast<int64_t>(m) * N * DX) +
                       static_cast<int64_t>(k) * N * DX;
 #pragma unroll
           for (int r = 0; r < PPT; ++r)
 #pragma unroll
             for (int d = 0; d < DX; ++d)
               if (j0 + r < N) xc[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
-          if (lane == 0) a.ck_L[(n / a.ck_every) * m + k] = Lpre;
+          if (lane == 0) ck_L[(n / ck_every) * m + k] = Lpre;
         }
-        if (lane == 0 && a.tr_lpre && !replay) a.tr_lpre[n * m + k] = Lpre;
+        if (lane == 0 && tr_lpre && !replay) tr_lpre[n * m + k] = Lpre;
       }
 
       // ---- weighting ----
@@ -390,7 +408,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       if (lane == 0 && active && !replay) {
         const double L = (Qk == 0) ? ninf() : Lpre + ((mx + dlog(static_cast<double>(Qk))) + a.cst_q);
         lvp(par)[li] = L;
-        if (a.tr_lpost) a.tr_lpost[n * m + k] = L;
+        if (tr_lpost) tr_lpost[n * m + k] = L;
       }
 
       // ---- internal resampling ----
@@ -438,14 +456,14 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
               prev = lo;
             }
             sAt[j] = anc;
-            if (a.tr_anc) a.tr_anc[(n * m + k) * static_cast<int64_t>(N) + j] = anc;
-            if (a.rec_anc) a.rec_anc[((n - a.n0) * m + k) * static_cast<int64_t>(N) + j] = static_cast<uint16_t>(anc);
-            if (a.tr_digest) dig += digest_term(n, k, j, anc);
+            if (tr_anc) tr_anc[(n * m + k) * static_cast<int64_t>(N) + j] = anc;
+            if (rec_anc) rec_anc[((n - n0) * m + k) * static_cast<int64_t>(N) + j] = static_cast<uint16_t>(anc);
+            if (tr_digest) dig += digest_term(n, k, j, anc);
           }
         }
-        if (a.tr_digest) {
+        if (tr_digest) {
           dig = team_sum_u64(dig, TP, red_u);
-          if (lane == 0 && active) atomicAdd(&a.tr_digest[2 * n], dig);
+          if (lane == 0 && active) atomicAdd(&tr_digest[2 * n], dig);
         }
         team_sync(TP);
         // the resampled block, written word by word with consecutive lanes on
@@ -514,7 +532,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     }
     }  // tree
     ++n;
-    if (n < a.n1 && !never) {
+    if (n < n1 && !never) {
       grid_arrive(a.bar, bid, epoch);
       pending = true;
     }
@@ -522,7 +540,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 
   // ---- log Zhat after the last weighting: log of the mean island weight,
   // the root of the island tree ----
-  if (replay || a.n1 < a.T) return;
+  if (replay || n1 < a.T) return;
   if (!grid_barrier(a.bar, G, bid, epoch, a.status)) return;
   if (bid == 0) {
     up_top = 0;
@@ -530,22 +548,22 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     const double lroot = up[2 * G - 2];
     if (tid == 0) {
       *a.out_logz = lroot;
-      if (a.tr_sstar) a.tr_sstar[a.T - 1] = 0;
+      if (tr_sstar) tr_sstar[a.T - 1] = 0;
     }
   }
 }
 
-template <class Model, typename Store, int PPT>
+template <class Model, typename Store, int PPT, bool Plain>
 __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
-  forward_body<Model, Store, PPT>(a, static_cast<int>(blockIdx.x));
+  forward_body<Model, Store, PPT, Plain>(a, static_cast<int>(blockIdx.x));
 }
 
 // Several problems in one cooperative launch: block b runs block bmap[b].y of
 // problem bmap[b].x; each problem synchronises only its own blocks.
-template <class Model, typename Store, int PPT>
+template <class Model, typename Store, int PPT, bool Plain>
 __global__ __launch_bounds__(kBlock) void forward_batch_kernel(const FwdArgs* probs, const int2* bmap) {
   const int2 pb = bmap[blockIdx.x];
-  forward_body<Model, Store, PPT>(probs[pb.x], pb.y);
+  forward_body<Model, Store, PPT, Plain>(probs[pb.x], pb.y);
 }
 
 }  // namespace airpf
@@ -556,6 +574,12 @@ namespace airpf {
 
 inline int pow2_ceil(int v) { int p = 1; while (p < v) p <<= 1; return p; }
 inline int ilog2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
+
+// nothing traced, recorded, replayed or checkpointed: the Plain kernel runs it
+inline bool fwd_is_plain(const FwdArgs& a) {
+  return !a.tr_sstar && !a.tr_enf && !a.tr_lpost && !a.tr_anc && !a.tr_pi && !a.tr_digest && !a.tr_lpre && !a.rec_x &&
+         !a.rec_anc && !a.ck_x && !a.ck_L && !a.ck_in && a.ck_every == 0 && !a.replay_pi && a.n0 == 0 && a.n1 == a.T;
+}
 
 inline size_t fwd_res_bytes(size_t store_bytes, int dx, int c, int N) {
   const size_t b = 2 * store_bytes * size_t(dx) * size_t(c) * size_t(N);
@@ -569,7 +593,7 @@ inline size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) 
 
 template <class Model, typename Store, int PPT>
 static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
-  auto kern = forward_kernel<Model, Store, PPT>;
+  auto kern = fwd_is_plain(a) ? forward_kernel<Model, Store, PPT, true> : forward_kernel<Model, Store, PPT, false>;
   const int TP = pow2_ceil((a.N + PPT - 1) / PPT);
   const int tpb = kBlock / TP;
   int G = a.m / tpb;
@@ -617,7 +641,7 @@ static hipError_t dispatch_ppt(const FwdLaunch& L, const FwdArgs& a, FwdPlan* pl
 
 template <class Model, typename Store, int PPT>
 static hipError_t batch_fwd_t(const BatchLaunch& L, int* cap) {
-  auto kern = forward_batch_kernel<Model, Store, PPT>;
+  auto kern = L.plain ? forward_batch_kernel<Model, Store, PPT, true> : forward_batch_kernel<Model, Store, PPT, false>;
   if (cap) {
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, L.smem);

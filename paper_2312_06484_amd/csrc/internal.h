@@ -95,6 +95,7 @@ struct BatchLaunch {
   const void* probs;          // device array of FwdArgs or BwdArgs
   const int2* bmap;           // device [blocks]
   hipStream_t stream;
+  int plain = 0;              // forward: every item plain (no traces, records, replay or checkpoints)
 };
 int forward_ppt(int kind, int dx, int n_max);
 // dynamic LDS of a forward block with c islands of a G-block problem, plus

@@ -25,6 +25,50 @@
 
 namespace airpf {
 
+// Sums acc[0..63] over the 64 lanes of a wave, lane l returning the total of
+// acc[l]: at each level a lane keeps the half of its values indexed by its
+// own lane bit and adds the partner's copy of that half (xor 32, 16, 8, 4,
+// 2, 1), 63 exchanges instead of 64 full reductions.  The pattern is fixed.
+__device__ __forceinline__ double wave_reduce_scatter64(double (&acc)[64]) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const bool h = (l & 32) != 0;
+    const double send = h ? acc[i] : acc[i + 32], keep = h ? acc[i + 32] : acc[i];
+    acc[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const bool h = (l & 16) != 0;
+    const double send = h ? acc[i] : acc[i + 16], keep = h ? acc[i + 16] : acc[i];
+    acc[i] = keep + __shfl_xor(send, 16, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const bool h = (l & 8) != 0;
+    const double send = h ? acc[i] : acc[i + 8], keep = h ? acc[i + 8] : acc[i];
+    acc[i] = keep + dppd<0x128>(send);              // row_ror:8 = xor 8 inside a row
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const bool h = (l & 4) != 0;
+    const double send = h ? acc[i] : acc[i + 4], keep = h ? acc[i + 4] : acc[i];
+    acc[i] = keep + __shfl_xor(send, 4, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const bool h = (l & 2) != 0;
+    const double send = h ? acc[i] : acc[i + 2], keep = h ? acc[i + 2] : acc[i];
+    acc[i] = keep + dppd<0x4E>(send);
+  }
+  {
+    const bool h = (l & 1) != 0;
+    const double send = h ? acc[0] : acc[1], keep = h ? acc[1] : acc[0];
+    acc[0] = keep + dppd<0xB1>(send);
+  }
+  return acc[0];
+}
+
 template <class Model, typename Store, int PPT>
 __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
@@ -48,6 +92,7 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
   int* sA = reinterpret_cast<int*>(sP + kBlock * PPT * NV);                          // [kBlock*PPT]
   int* sS = sA + kBlock * PPT;                                                       // [kBlock*PPT] run start
   int* sE = sS + kBlock * PPT;                                                       // [kBlock*PPT] run end
+  int* s_pi = sE + kBlock * PPT;                                                     // [kPiCache] island maps
 
   unsigned epoch = 0;
   const double logz = *a.logz;
@@ -58,6 +103,15 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
     const int B = last ? 1 : (1 << a.sstar_all[n]);
     const int par = static_cast<int>(n & 1), npar = par ^ 1;
     const double* yn = a.y + n * a.dy;
+    // the island maps of step n over the candidates of this block's islands
+    // (the aligned 2^{s*}-block of each), cached in LDS when they fit
+    const int R_len = B > c ? B : c;
+    const int R_lo = kbase & ~(B - 1);
+    const bool pi_cached = !last && R_len <= kPiCache;
+    if (pi_cached) {
+      for (int i = tid; i < R_len; i += kBlock) s_pi[i] = a.pi_all[n * m + R_lo + i];
+      __syncthreads();
+    }
 
     for (int p = 0; p < passes; ++p) {
       const int li = p * tpb + team;
@@ -109,7 +163,7 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
         const uint16_t* an = a.rec_anc + ((n - a.n_lo) * m + k) * static_cast<int64_t>(N);
 #pragma unroll
         for (int r = 0; r < PPT; ++r) sAt[j0 + r] = (active && j0 + r < N) ? static_cast<int>(an[j0 + r]) : 0x7fffffff;
-        __syncthreads();
+        team_sync(TP);
 
         double sl[PPT][NV];                      // per slot: sum over children of (lam, D)
 #pragma unroll
@@ -132,7 +186,8 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
         const Store* del_in = static_cast<const Store*>(a.del[npar]);
         for (int it = 0; it < B; it += W) {
           const int cand = blo + it + sl_lane;
-          const bool match = active && (it + sl_lane < B) && a.pi_all[n * m + cand] == k;
+          const bool match = active && (it + sl_lane < B) &&
+                             (pi_cached ? s_pi[cand - R_lo] : a.pi_all[n * m + cand]) == k;
           const unsigned long long ball = __ballot(match);
           unsigned long long seg = (W == 64) ? ball : ((ball >> seg0) & ((1ull << W) - 1));
           while (seg) {
@@ -184,7 +239,7 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
             sPt[(j0 + r) * NV + v] = base[v];          // inclusive prefix over slots
           }
         }
-        __syncthreads();
+        team_sync(TP);
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           const int j = j0 + r;
@@ -194,7 +249,7 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
             if (j == N - 1 || sAt[j + 1] != aj) sEt[aj] = j;
           }
         }
-        __syncthreads();
+        team_sync(TP);
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           const int i = j0 + r;
@@ -246,12 +301,22 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
       }
       // the island's gradient contribution, summed over its lanes in a fixed
       // pattern and added to the island's own accumulator (in step order)
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        const double v = team_sum_f64(acc[q], TP, red_d);
-        if (lane == 0 && active) a.gisl[static_cast<int64_t>(k) * P + q] += v;
+      bool summed = false;
+      if constexpr (P == 64) {
+        if (TP == 64) {
+          const double v = wave_reduce_scatter64(acc);
+          if (active) a.gisl[static_cast<int64_t>(k) * P + (tid & 63)] += v;
+          summed = true;
+        }
       }
-      __syncthreads();
+      if (!summed) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const double v = team_sum_f64(acc[q], TP, red_d);
+          if (lane == 0 && active) a.gisl[static_cast<int64_t>(k) * P + q] += v;
+        }
+      }
+      team_sync(TP);
     }
   }
 }
@@ -297,7 +362,7 @@ static int pow2_ceil_b(int v) { int p = 1; while (p < v) p <<= 1; return p; }
 
 static size_t bwd_smem_bytes(size_t store_bytes, int ppt, int dx) {
   const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
-  return sx + 8 * size_t(kBlock) * ppt * (dx + 1) + 3 * 4 * size_t(kBlock) * ppt;
+  return sx + 8 * size_t(kBlock) * ppt * (dx + 1) + 3 * 4 * size_t(kBlock) * ppt + 4 * size_t(kPiCache);
 }
 
 template <class Model, typename Store, int PPT>
