@@ -73,6 +73,8 @@ typedef enum { AIRPF_FP32 = 0, AIRPF_FP64 = 1 } airpf_precision;
 typedef enum { AIRPF_PATHSPACE = 0, AIRPF_PATHWISE = 1 } airpf_score_mode;
 
 #define AIRPF_FLAG_Y_ON_DEVICE 1u /* y is a device pointer (already resident in HBM) */
+#define AIRPF_FLAG_AUTOTUNE 2u    /* airpf_run_batch: measure the tiler's cost ratio for this
+                                     batch shape (see airpf_run_batch) */
 
 typedef struct {
   double tau;         /* ENF threshold of the adaptation line of Algorithm 1:
@@ -149,7 +151,14 @@ typedef struct {
  * want_score; item_status[B] per problem (an invalid problem is reported
  * there and skipped, the others still run).  Each item's results are
  * bit-identical to the same problem run alone with airpf_run / airpf_score.
- * The call's return value is AIRPF_OK unless the batch as a whole failed. */
+ * The call's return value is AIRPF_OK unless the batch as a whole failed.
+ * Tiling: a problem's time is modelled as steps * (1 + r * passes) (a pass
+ * is one round of island work of a block); with AIRPF_FLAG_AUTOTUNE in
+ * opt->flags the library times the tilings of several r on the first (up to)
+ * 32 steps of every problem, keeps the fastest and caches it in the context
+ * for batches of the same shape (model, precision, score, and every
+ * problem's T, m, N), so only the first such call pays for the probes.
+ * Tiling never changes results. */
 airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model, int32_t B,
                              const airpf_problem* probs, const airpf_options* opt,
                              int32_t want_score, double* log_z_out, double* grad_out,

@@ -20,6 +20,7 @@ SYSTEMATIC, MULTINOMIAL = 0, 1
 FP32, FP64 = 0, 1
 PATHSPACE, PATHWISE = 0, 1
 FLAG_Y_ON_DEVICE = 1
+FLAG_AUTOTUNE = 2
 
 OK, E_INVALID_ARG, E_DOMAIN, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(6)
 
@@ -207,9 +208,11 @@ class Context:
         return st, out.value, grad
 
     def run_batch(self, kind, problems, tau=0.3, fp64=False, dx=1, dy=1, consts=None, want_score=False,
-                  ckpt_every=0, y_on_device=False, raise_on_error=True):
+                  ckpt_every=0, y_on_device=False, autotune=False, raise_on_error=True):
         """airpf_run_batch.  ``problems``: dicts with theta, y (host array, or a
-        device pointer int with ``y_on_device`` and then T), m, N, seed.
+        device pointer int with ``y_on_device`` and then T), m, N, seed;
+        ``autotune`` sets AIRPF_FLAG_AUTOTUNE (measured tiling, cached per
+        batch shape in the context).
         Returns (status, log_z[B], grad[B, d_theta] or None, item_status[B])."""
         B = len(problems)
         model = _Model()
@@ -220,7 +223,7 @@ class Context:
         opt = _Options()
         opt.tau, opt.resampling, opt.precision = float(tau), SYSTEMATIC, FP64 if fp64 else FP32
         opt.score_mode, opt.ckpt_every = PATHSPACE, int(ckpt_every)
-        opt.flags = FLAG_Y_ON_DEVICE if y_on_device else 0
+        opt.flags = (FLAG_Y_ON_DEVICE if y_on_device else 0) | (FLAG_AUTOTUNE if autotune else 0)
         arr = (_Problem * max(B, 1))()
         keep = []
         for i, pr in enumerate(problems):

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <vector>
 
 #include "airpf.h"
@@ -54,6 +55,9 @@ struct airpf_ctx {
   DevBuf s_pi, s_sstar, s_lpre, s_ckx, s_ckL, s_recx, s_reca, s_lam[2], s_del[2], s_grad;
   DevBuf dbg_in, dbg_in32, dbg_out, dbg_out2, dbg_out32;
   DevBuf batch;
+  // tiler cost ratios (pass time / step overhead) measured by AIRPF_FLAG_AUTOTUNE,
+  // keyed by batch shape
+  std::map<uint64_t, double> tuned_ratio;
 };
 
 #define HIP_OK(expr) do { if ((expr) != hipSuccess) return AIRPF_E_DEVICE; } while (0)
@@ -533,21 +537,18 @@ struct Item {
 };
 
 // Tiler.  Modelled time of a problem over `steps` filter steps on G blocks:
-// steps * (alpha + beta * passes), passes = ceil(islands per block / islands
-// per pass).  alpha (the per-step grid synchronisation and island cascade)
-// and beta (one pass of island work) default to values measured on MI355X
-// and can be replaced through AIRPF_TILER="alpha,beta" (microseconds).
+// steps * (1 + ratio * passes), passes = ceil(islands per block / islands
+// per pass): a step's fixed part (the grid synchronisation and island
+// cascade) is the unit and `ratio` prices one pass of island work.  The
+// default ratio 1/3 was measured on MI355X (12 us per step, 4 us per pass);
+// AIRPF_TILER="alpha,beta" (microseconds) replaces it, and
+// AIRPF_FLAG_AUTOTUNE measures it per batch shape (see airpf_run_batch).
 // Start from the fewest blocks that keep a block's islands within the LDS
 // plan (<= 256) and double the block count of the slowest problem while the
 // device's co-residency allows.
-bool tile(std::vector<Item*>& its, const std::vector<int64_t>& steps, int capacity) {
-  double alpha = 12.0, beta = 4.0;
-  if (const char* env = std::getenv("AIRPF_TILER")) {
-    double a = 0, b = 0;
-    if (std::sscanf(env, "%lf,%lf", &a, &b) == 2 && a >= 0 && b > 0) { alpha = a; beta = b; }
-  }
+bool tile(std::vector<Item*>& its, const std::vector<int64_t>& steps, int capacity, double ratio) {
   auto passes = [](const Item* it, int G) { const int c = it->m / G; return (c + it->tpb - 1) / it->tpb; };
-  auto cost = [&](size_t i, int G) { return double(steps[i]) * (alpha + beta * passes(its[i], G)); };
+  auto cost = [&](size_t i, int G) { return double(steps[i]) * (1.0 + ratio * passes(its[i], G)); };
   int used = 0;
   for (Item* it : its) {
     int g = pow2_ceil_i((it->m + 255) / 256);
@@ -639,8 +640,13 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   BL.plain = want_score ? 0 : 1;          // the score's forward launches record and replay
   BL.stream = s; BL.blocks = 0; BL.probs = nullptr; BL.bmap = nullptr;
   BL.smem = airpf::forward_smem(fp64, ppt_f, dx, 256, 256, airpf::kResidentBudget);   // bound of any tiling below
-  int cap_f = 0;
+  int cap_f = 0, cap_fp = 0;
   HIP_OK(airpf::forward_batch_capacity(BL, &cap_f));
+  {
+    airpf::BatchLaunch BP = BL;
+    BP.plain = 1;
+    HIP_OK(airpf::forward_batch_capacity(BP, &cap_fp));
+  }
   int cap_b = 0;
   if (want_score) {
     airpf::BatchLaunch BB = BL;
@@ -716,11 +722,16 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   std::vector<int2> bmap;
   // launch helper: tile the given items, upload arguments and block map, zero
   // their barrier flags, launch forward (mode 0) or reverse (mode 1)
+  double ratio = 1.0 / 3.0;
+  if (const char* env = std::getenv("AIRPF_TILER")) {
+    double ea = 0, eb = 0;
+    if (std::sscanf(env, "%lf,%lf", &ea, &eb) == 2 && ea > 0 && eb > 0) ratio = eb / ea;
+  }
   auto launch = [&](std::vector<Item*>& act, const std::vector<int64_t>& steps, int mode,
                     const std::function<void(Item&, airpf::FwdArgs&)>& fwd_fill,
-                    const std::function<void(Item&, airpf::BwdArgs&)>& bwd_fill) -> airpf_status {
+                    const std::function<void(Item&, airpf::BwdArgs&)>& bwd_fill, bool probe = false) -> airpf_status {
     if (act.empty()) return AIRPF_OK;
-    if (!tile(act, steps, mode == 0 ? cap_f : cap_b)) return AIRPF_E_UNSUPPORTED;
+    if (!tile(act, steps, mode == 0 ? (probe ? cap_fp : cap_f) : cap_b, ratio)) return AIRPF_E_UNSUPPORTED;
     bmap.clear();
     fa.clear();
     ba.clear();
@@ -779,6 +790,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
     }
     // the batched forward kernel's LDS plan must cover every problem's tiling
     airpf::BatchLaunch L = BL;
+    if (probe) L.plain = 1;
     L.blocks = int(bmap.size());
     L.smem = mode == 0 ? airpf::forward_smem(fp64, ppt_f, dx, c_max, G_max, res_max) : airpf::backward_smem(fp64, ppt_b, dx);
     void* d_args = at(o_args);
@@ -796,6 +808,46 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   std::vector<Item*> all;
   std::vector<int64_t> steps;
   for (Item& it : items) { all.push_back(&it); steps.push_back(it.T); }
+
+  // ---- AIRPF_FLAG_AUTOTUNE: time the tilings of a few cost ratios on the
+  // first (up to) 32 steps of every problem (plain forward runs whose
+  // results are discarded) and keep the fastest, cached per batch shape ----
+  if ((opt.flags & AIRPF_FLAG_AUTOTUNE) && !std::getenv("AIRPF_TILER")) {
+    uint64_t key = 0x9E3779B97F4A7C15ULL;
+    auto mix = [&](uint64_t v) { key = (key ^ v) * 0xff51afd7ed558ccdULL; key ^= key >> 29; };
+    mix(uint64_t(model->kind)); mix(uint64_t(dx)); mix(uint64_t(fp64)); mix(uint64_t(want_score));
+    for (const Item& it : items) { mix(uint64_t(it.T)); mix(uint64_t(it.m)); mix(uint64_t(it.N)); }
+    auto hit = ctx->tuned_ratio.find(key);
+    if (hit != ctx->tuned_ratio.end()) {
+      ratio = hit->second;
+    } else {
+      const double cand[] = {1.0 / 32, 1.0 / 8, 1.0 / 3, 1.0, 4.0};
+      double best_ms = -1.0, best = ratio;
+      std::vector<std::vector<int>> seen;
+      for (double r : cand) {
+        ratio = r;
+        std::vector<Item*> tmp = all;
+        if (!tile(tmp, steps, cap_fp, ratio)) continue;
+        std::vector<int> gs;
+        for (const Item* it : tmp) gs.push_back(it->G);
+        if (std::find(seen.begin(), seen.end(), gs) != seen.end()) continue;   // same tiling as a ratio tried
+        seen.push_back(gs);
+        HIP_OK(hipEventRecord(ctx->ev[0], s));
+        const airpf_status pst = launch(all, steps, 0, [&](Item& it, airpf::FwdArgs& a) {
+          a.T = std::min<int64_t>(it.T, 32);
+          a.n1 = a.T;
+        }, [](Item&, airpf::BwdArgs&) {}, true);
+        HIP_OK(hipEventRecord(ctx->ev[1], s));
+        HIP_OK(hipEventSynchronize(ctx->ev[1]));
+        if (pst != AIRPF_OK) continue;
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+        if (best_ms < 0 || ms < best_ms) { best_ms = ms; best = r; }
+      }
+      ratio = best;
+      ctx->tuned_ratio[key] = ratio;
+    }
+  }
   HIP_OK(hipEventRecord(ctx->ev[0], s));
   auto no_bwd = [](Item&, airpf::BwdArgs&) {};
   airpf_status st = launch(all, steps, 0, [&](Item& it, airpf::FwdArgs& a) {

@@ -84,3 +84,18 @@ def test_batch_of_sixty_four_proposals_shape(ctx):
     for it, v in list(zip(items, lz))[::7]:
         _, ref = ctx.run(1, it["theta"], it["y"], it["m"], it["N"], it["seed"], tau=0.3)
         assert v == ref
+
+
+@pytest.mark.parametrize("want_score", [False, True])
+def test_batch_autotuned_tiling_changes_nothing(ctx, want_score):
+    """AIRPF_FLAG_AUTOTUNE times a few tilings on a prefix of the batch and
+    keeps the fastest (cached per shape: the second call reuses it); results
+    stay bit-identical to the default tiling's."""
+    items = sv_batch(10, seed=3)
+    _, lz0, gr0, ist0 = ctx.run_batch(1, items, tau=0.4, want_score=want_score, ckpt_every=9)
+    for rep in range(2):
+        _, lz1, gr1, ist1 = ctx.run_batch(1, items, tau=0.4, want_score=want_score, ckpt_every=9, autotune=True)
+        assert (ist1 == 0).all() and (ist0 == 0).all()
+        assert np.array_equal(lz0, lz1)
+        if want_score:
+            assert np.array_equal(gr0, gr1)
