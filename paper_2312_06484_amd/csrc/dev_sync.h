@@ -299,6 +299,20 @@ __device__ __forceinline__ EnfRec enf_join(const EnfRec& x, const EnfRec& y) {
 // join is commutative bit for bit and a lane's partner holds exactly the
 // other half of its group, so the result is that of the adjacent-pair tree,
 // in every lane l < n.  `rec(i)` yields record i.
+// The lanes' part of wave_reduce_enf: lane l holds the record of its
+// aligned run; groups of 2, 4, ..., min(n, 64) lanes join (xor 1, xor 2,
+// then the 8- and 16-lane mirrors, whose partner holds exactly the other
+// half of the group as with xor 4, xor 8, then xor 16, xor 32).
+__device__ __forceinline__ EnfRec wave_butterfly_enf(EnfRec r, int n) {
+  if (n >= 2) r = enf_join(r, EnfRec{dppd<0xB1>(r.E), dppd<0xB1>(r.a), dppd<0xB1>(r.b)});
+  if (n >= 4) r = enf_join(r, EnfRec{dppd<0x4E>(r.E), dppd<0x4E>(r.a), dppd<0x4E>(r.b)});
+  if (n >= 8) r = enf_join(r, EnfRec{dppd<0x141>(r.E), dppd<0x141>(r.a), dppd<0x141>(r.b)});
+  if (n >= 16) r = enf_join(r, EnfRec{dppd<0x140>(r.E), dppd<0x140>(r.a), dppd<0x140>(r.b)});
+  if (n >= 32) r = enf_join(r, EnfRec{__shfl_xor(r.E, 16, 64), __shfl_xor(r.a, 16, 64), __shfl_xor(r.b, 16, 64)});
+  if (n >= 64) r = enf_join(r, EnfRec{__shfl_xor(r.E, 32, 64), __shfl_xor(r.a, 32, 64), __shfl_xor(r.b, 32, 64)});
+  return r;
+}
+
 template <class F>
 __device__ __forceinline__ EnfRec wave_reduce_enf(int n, F rec) {
   const int lane = threadIdx.x & 63;
@@ -310,16 +324,7 @@ __device__ __forceinline__ EnfRec wave_reduce_enf(int n, F rec) {
   } else {
     r = enf_join(enf_join(rec(4 * lane), rec(4 * lane + 1)), enf_join(rec(4 * lane + 2), rec(4 * lane + 3)));
   }
-  // the butterfly: xor 1, xor 2, then the 8- and 16-lane mirrors (a lane's
-  // partner holds exactly the other half of its group, as with xor 4, xor 8),
-  // then xor 16, xor 32
-  if (n >= 2) r = enf_join(r, EnfRec{dppd<0xB1>(r.E), dppd<0xB1>(r.a), dppd<0xB1>(r.b)});
-  if (n >= 4) r = enf_join(r, EnfRec{dppd<0x4E>(r.E), dppd<0x4E>(r.a), dppd<0x4E>(r.b)});
-  if (n >= 8) r = enf_join(r, EnfRec{dppd<0x141>(r.E), dppd<0x141>(r.a), dppd<0x141>(r.b)});
-  if (n >= 16) r = enf_join(r, EnfRec{dppd<0x140>(r.E), dppd<0x140>(r.a), dppd<0x140>(r.b)});
-  if (n >= 32) r = enf_join(r, EnfRec{__shfl_xor(r.E, 16, 64), __shfl_xor(r.a, 16, 64), __shfl_xor(r.b, 16, 64)});
-  if (n >= 64) r = enf_join(r, EnfRec{__shfl_xor(r.E, 32, 64), __shfl_xor(r.a, 32, 64), __shfl_xor(r.b, 32, 64)});
-  return r;
+  return wave_butterfly_enf(r, n);
 }
 
 // block-wide reductions with a fixed pattern (identical result in every block)

@@ -326,8 +326,10 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(BwdArgs a) {
   backward_body<Model, Store, PPT>(a, static_cast<int>(blockIdx.x));
 }
 
+// three waves per SIMD for the batch (VGPRs capped at 168, a few spilled): the
+// reverse pass of many problems is limited by latency, not by registers
 template <class Model, typename Store, int PPT>
-__global__ __launch_bounds__(kBlock) void backward_batch_kernel(const BwdArgs* probs, const int2* bmap) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void backward_batch_kernel(const BwdArgs* probs, const int2* bmap) {
   const int2 pb = bmap[blockIdx.x];
   backward_body<Model, Store, PPT>(probs[pb.x], pb.y);
 }
