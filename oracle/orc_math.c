@@ -9,7 +9,7 @@
  * sequence of correctly rounded IEEE-754 operations (+, -, *, /, sqrt, fma,
  * rint) instead of each platform's libm.  The methods are textbook:
  *   exp : Cody-Waite reduction x = k ln2 + r (two-part ln2), degree-13
- *         Taylor polynomial of e^r by Horner's rule, scaling by 2^k.
+ *         Taylor polynomial of e^r by Estrin's scheme, scaling by 2^k.
  *   log : x = 2^e f, f in [sqrt(2)/2, sqrt(2)], log f = 2 atanh(s) with
  *         s = (f-1)/(f+1), odd series in s to s^23.
  *   cos/sin(2 pi v): quadrant q = rint(4v), w = v - q/4 in [-1/8, 1/8],
@@ -37,21 +37,19 @@ double orc_exp(double x) {
   const double kd = rint(x * 0x1.71547652b82fep+0);    /* x / ln 2           */
   double r = fma(-kd, 0x1.62e42fee00000p-1, x);        /* ln2 high part      */
   r = fma(-kd, 0x1.a39ef35793c76p-33, r);              /* ln2 low part       */
-  /* e^r = sum_{i=0}^{13} r^i / i!  (Horner) */
-  double p = 0x1.6124613a86d09p-33;                    /* 1/13!              */
-  p = fma(p, r, 0x1.1eed8eff8d898p-29);                /* 1/12!              */
-  p = fma(p, r, 0x1.ae64567f544e4p-26);                /* 1/11!              */
-  p = fma(p, r, 0x1.27e4fb7789f5cp-22);                /* 1/10!              */
-  p = fma(p, r, 0x1.71de3a556c734p-19);                /* 1/9!               */
-  p = fma(p, r, 0x1.a01a01a01a01ap-16);                /* 1/8!               */
-  p = fma(p, r, 0x1.a01a01a01a01ap-13);                /* 1/7!               */
-  p = fma(p, r, 0x1.6c16c16c16c17p-10);                /* 1/6!               */
-  p = fma(p, r, 0x1.1111111111111p-7);                 /* 1/5!               */
-  p = fma(p, r, 0x1.5555555555555p-5);                 /* 1/4!               */
-  p = fma(p, r, 0x1.5555555555555p-3);                 /* 1/3!               */
-  p = fma(p, r, 0x1.0000000000000p-1);                 /* 1/2!               */
-  p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
+  /* e^r = 1 + (r + r^2 Q(r)),  Q(r) = sum_{i=2}^{13} r^{i-2} / i!
+     (Estrin: adjacent pairs in r, then combined with r^2, r^4, r^8; the
+     leading 1 added last) */
+  const double r2 = r * r, r4 = r2 * r2, r8 = r4 * r4;
+  const double q0 = fma(0x1.5555555555555p-3, r, 0x1.0000000000000p-1);   /* 1/3!, 1/2!   */
+  const double q1 = fma(0x1.1111111111111p-7, r, 0x1.5555555555555p-5);   /* 1/5!, 1/4!   */
+  const double q2 = fma(0x1.a01a01a01a01ap-13, r, 0x1.6c16c16c16c17p-10); /* 1/7!, 1/6!   */
+  const double q3 = fma(0x1.71de3a556c734p-19, r, 0x1.a01a01a01a01ap-16); /* 1/9!, 1/8!   */
+  const double q4 = fma(0x1.ae64567f544e4p-26, r, 0x1.27e4fb7789f5cp-22); /* 1/11!, 1/10! */
+  const double q5 = fma(0x1.6124613a86d09p-33, r, 0x1.1eed8eff8d898p-29); /* 1/13!, 1/12! */
+  const double s0 = fma(q1, r2, q0), s1 = fma(q3, r2, q2), s2 = fma(q5, r2, q4);
+  const double Q = fma(s2, r8, fma(s1, r4, s0));
+  const double p = 1.0 + fma(r2, Q, r);
   const int k = (int)kd;
   if (k > 1023) return (p * 2.0) * pow2i(k - 1);
   if (k < -1022) return (p * pow2i(k + 200)) * pow2i(-200);
@@ -70,20 +68,18 @@ double orc_log(double x) {
   if (f > 0x1.6a09e667f3bcdp+0) { f = f * 0.5; e += 1; } /* f > sqrt(2)      */
   const double s = (f - 1.0) / (f + 1.0);
   const double z = s * s;
-  /* sum_{i=0}^{11} z^i / (2i+1)  (Horner) */
-  double p = 0x1.642c8590b2164p-5;                     /* 1/23 */
-  p = fma(p, z, 0x1.8618618618618p-5);                 /* 1/21 */
-  p = fma(p, z, 0x1.af286bca1af28p-5);                 /* 1/19 */
-  p = fma(p, z, 0x1.e1e1e1e1e1e1ep-5);                 /* 1/17 */
-  p = fma(p, z, 0x1.1111111111111p-4);                 /* 1/15 */
-  p = fma(p, z, 0x1.3b13b13b13b14p-4);                 /* 1/13 */
-  p = fma(p, z, 0x1.745d1745d1746p-4);                 /* 1/11 */
-  p = fma(p, z, 0x1.c71c71c71c71cp-4);                 /* 1/9  */
-  p = fma(p, z, 0x1.2492492492492p-3);                 /* 1/7  */
-  p = fma(p, z, 0x1.999999999999ap-3);                 /* 1/5  */
-  p = fma(p, z, 0x1.5555555555555p-2);                 /* 1/3  */
-  p = fma(p, z, 1.0);
-  double t = s * p;
+  /* 2 atanh(s) = 2 (s + s z P(z)),  P(z) = sum_{i=1}^{11} z^{i-1} / (2i+1)
+     (Estrin: adjacent pairs in z, then combined with z^2, z^4, z^8) */
+  const double z2 = z * z, z4 = z2 * z2, z8 = z4 * z4;
+  const double q0 = fma(0x1.999999999999ap-3, z, 0x1.5555555555555p-2);   /* 1/5, 1/3     */
+  const double q1 = fma(0x1.c71c71c71c71cp-4, z, 0x1.2492492492492p-3);   /* 1/9, 1/7     */
+  const double q2 = fma(0x1.3b13b13b13b14p-4, z, 0x1.745d1745d1746p-4);   /* 1/13, 1/11   */
+  const double q3 = fma(0x1.e1e1e1e1e1e1ep-5, z, 0x1.1111111111111p-4);   /* 1/17, 1/15   */
+  const double q4 = fma(0x1.8618618618618p-5, z, 0x1.af286bca1af28p-5);   /* 1/21, 1/19   */
+  const double s0 = fma(q1, z2, q0), s1 = fma(q3, z2, q2);
+  const double s2 = fma(0x1.642c8590b2164p-5, z2, q4);                    /* 1/23         */
+  const double P = fma(s2, z8, fma(s1, z4, s0));
+  double t = fma(s * z, P, s);
   t = t + t;                                           /* 2 atanh(s)         */
   const double ed = (double)e;
   const double hi = ed * 0x1.62e42fee00000p-1;         /* exact              */
@@ -96,30 +92,25 @@ void orc_cossin2pi(double v, double* c, double* s) {
   const double w = v - q * 0.25;                       /* |w| <= 1/8         */
   const double th = w * 0x1.921fb54442d18p+2;          /* 2 pi w             */
   const double z = th * th;
-  /* sin th = th * sum_{i=0}^{9} (-1)^i z^i / (2i+1)! */
-  double ps = -0x1.2f49b46814157p-57;
-  ps = fma(ps, z, 0x1.952c77030ad4ap-49);
-  ps = fma(ps, z, -0x1.ae7f3e733b81fp-41);
-  ps = fma(ps, z, 0x1.6124613a86d09p-33);
-  ps = fma(ps, z, -0x1.ae64567f544e4p-26);
-  ps = fma(ps, z, 0x1.71de3a556c734p-19);
-  ps = fma(ps, z, -0x1.a01a01a01a01ap-13);
-  ps = fma(ps, z, 0x1.1111111111111p-7);
-  ps = fma(ps, z, -0x1.5555555555555p-3);
-  ps = fma(ps, z, 1.0);
+  /* sin th = th * sum_{i=0}^{9} (-1)^i z^i / (2i+1)!  and
+     cos th = sum_{i=0}^{10} (-1)^i z^i / (2i)!, both by Estrin */
+  const double z2 = z * z, z4 = z2 * z2, z8 = z4 * z4;
+  const double a0 = fma(-0x1.5555555555555p-3, z, 1.0);                   /* -1/3!        */
+  const double a1 = fma(-0x1.a01a01a01a01ap-13, z, 0x1.1111111111111p-7); /* -1/7!, 1/5!  */
+  const double a2 = fma(-0x1.ae64567f544e4p-26, z, 0x1.71de3a556c734p-19); /* -1/11!, 1/9! */
+  const double a3 = fma(-0x1.ae7f3e733b81fp-41, z, 0x1.6124613a86d09p-33); /* -1/15!, 1/13! */
+  const double a4 = fma(-0x1.2f49b46814157p-57, z, 0x1.952c77030ad4ap-49); /* -1/19!, 1/17! */
+  const double b0 = fma(a1, z2, a0), b1 = fma(a3, z2, a2);
+  const double ps = fma(a4, z8, fma(b1, z4, b0));
   const double sn = th * ps;
-  /* cos th = sum_{i=0}^{10} (-1)^i z^i / (2i)! */
-  double pc = 0x1.e542ba4020225p-62;
-  pc = fma(pc, z, -0x1.6827863b97d97p-53);
-  pc = fma(pc, z, 0x1.ae7f3e733b81fp-45);
-  pc = fma(pc, z, -0x1.93974a8c07c9dp-37);
-  pc = fma(pc, z, 0x1.1eed8eff8d898p-29);
-  pc = fma(pc, z, -0x1.27e4fb7789f5cp-22);
-  pc = fma(pc, z, 0x1.a01a01a01a01ap-16);
-  pc = fma(pc, z, -0x1.6c16c16c16c17p-10);
-  pc = fma(pc, z, 0x1.5555555555555p-5);
-  pc = fma(pc, z, -0x1.0000000000000p-1);
-  pc = fma(pc, z, 1.0);
+  const double g0 = fma(-0x1.0000000000000p-1, z, 1.0);                   /* -1/2!        */
+  const double g1 = fma(-0x1.6c16c16c16c17p-10, z, 0x1.5555555555555p-5); /* -1/6!, 1/4!  */
+  const double g2 = fma(-0x1.27e4fb7789f5cp-22, z, 0x1.a01a01a01a01ap-16); /* -1/10!, 1/8! */
+  const double g3 = fma(-0x1.93974a8c07c9dp-37, z, 0x1.1eed8eff8d898p-29); /* -1/14!, 1/12! */
+  const double g4 = fma(-0x1.6827863b97d97p-53, z, 0x1.ae7f3e733b81fp-45); /* -1/18!, 1/16! */
+  const double h0 = fma(g1, z2, g0), h1 = fma(g3, z2, g2);
+  const double h2 = fma(0x1.e542ba4020225p-62, z2, g4);                   /* 1/20!        */
+  const double pc = fma(h2, z8, fma(h1, z4, h0));
   const double cs = pc;
   /* angle = th + q pi/2 */
   const int quad = ((int)q) & 3;

@@ -128,20 +128,19 @@ __device__ inline double dexp(double x) {
   if (x < -0x1.74910d52d3051p+9) return 0.0;
   const double kd = rint(x * kInvLn2);
   const double r = fma(-kd, kLn2Tail, fma(-kd, kLn2Head, x));
-  double p = InvFact<13>::value;
-  p = fma(p, r, InvFact<12>::value);
-  p = fma(p, r, InvFact<11>::value);
-  p = fma(p, r, InvFact<10>::value);
-  p = fma(p, r, InvFact<9>::value);
-  p = fma(p, r, InvFact<8>::value);
-  p = fma(p, r, InvFact<7>::value);
-  p = fma(p, r, InvFact<6>::value);
-  p = fma(p, r, InvFact<5>::value);
-  p = fma(p, r, InvFact<4>::value);
-  p = fma(p, r, InvFact<3>::value);
-  p = fma(p, r, InvFact<2>::value);
-  p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
+  // e^r = 1 + (r + r^2 Q(r)), Q(r) = sum_{i=2}^{13} r^{i-2} / i! by Estrin's
+  // scheme (adjacent pairs, then powers r^2, r^4, r^8); the leading 1 is
+  // added last
+  const double r2 = r * r, r4 = r2 * r2, r8 = r4 * r4;
+  const double q0 = fma(InvFact<3>::value, r, InvFact<2>::value);
+  const double q1 = fma(InvFact<5>::value, r, InvFact<4>::value);
+  const double q2 = fma(InvFact<7>::value, r, InvFact<6>::value);
+  const double q3 = fma(InvFact<9>::value, r, InvFact<8>::value);
+  const double q4 = fma(InvFact<11>::value, r, InvFact<10>::value);
+  const double q5 = fma(InvFact<13>::value, r, InvFact<12>::value);
+  const double s0 = fma(q1, r2, q0), s1 = fma(q3, r2, q2), s2 = fma(q5, r2, q4);
+  const double Q = fma(s2, r8, fma(s1, r4, s0));
+  const double p = 1.0 + fma(r2, Q, r);
   const int k = static_cast<int>(kd);
   if (k > 1023) return scale2(p * 2.0, k - 1);
   if (k < -1022) return scale2(scale2(p, k + 200), -200);
@@ -160,19 +159,17 @@ __device__ inline double dlog(double x) {
   if (f > 0x1.6a09e667f3bcdp+0) { f = f * 0.5; e += 1; }
   const double s = (f - 1.0) / (f + 1.0);
   const double z = s * s;
-  double p = InvOdd<11>::value;
-  p = fma(p, z, InvOdd<10>::value);
-  p = fma(p, z, InvOdd<9>::value);
-  p = fma(p, z, InvOdd<8>::value);
-  p = fma(p, z, InvOdd<7>::value);
-  p = fma(p, z, InvOdd<6>::value);
-  p = fma(p, z, InvOdd<5>::value);
-  p = fma(p, z, InvOdd<4>::value);
-  p = fma(p, z, InvOdd<3>::value);
-  p = fma(p, z, InvOdd<2>::value);
-  p = fma(p, z, InvOdd<1>::value);
-  p = fma(p, z, 1.0);
-  double t = s * p;
+  // 2 atanh(s) = 2 (s + s z P(z)), P(z) = sum_{i=1}^{11} z^{i-1} / (2i+1) by
+  // Estrin's scheme (adjacent pairs, then powers z^2, z^4, z^8)
+  const double z2 = z * z, z4 = z2 * z2, z8 = z4 * z4;
+  const double q0 = fma(InvOdd<2>::value, z, InvOdd<1>::value);
+  const double q1 = fma(InvOdd<4>::value, z, InvOdd<3>::value);
+  const double q2 = fma(InvOdd<6>::value, z, InvOdd<5>::value);
+  const double q3 = fma(InvOdd<8>::value, z, InvOdd<7>::value);
+  const double q4 = fma(InvOdd<10>::value, z, InvOdd<9>::value);
+  const double s0 = fma(q1, z2, q0), s1 = fma(q3, z2, q2), s2 = fma(InvOdd<11>::value, z2, q4);
+  const double P = fma(s2, z8, fma(s1, z4, s0));
+  double t = fma(s * z, P, s);
   t = t + t;
   const double ed = static_cast<double>(e);
   return ed * kLn2Head + (ed * kLn2Tail + t);
@@ -182,29 +179,24 @@ __device__ inline void cossin_2pi(double v, double& c, double& s) {
   const double q = rint(v * 4.0);
   const double th = (v - q * 0.25) * kTwoPi;
   const double z = th * th;
-  // sin th = th sum_i (-1)^i z^i / (2i+1)!,  cos th = sum_i (-1)^i z^i / (2i)!
-  double ps = -InvFact<19>::value;
-  ps = fma(ps, z, InvFact<17>::value);
-  ps = fma(ps, z, -InvFact<15>::value);
-  ps = fma(ps, z, InvFact<13>::value);
-  ps = fma(ps, z, -InvFact<11>::value);
-  ps = fma(ps, z, InvFact<9>::value);
-  ps = fma(ps, z, -InvFact<7>::value);
-  ps = fma(ps, z, InvFact<5>::value);
-  ps = fma(ps, z, -InvFact<3>::value);
-  ps = fma(ps, z, 1.0);
+  // sin th = th sum_{i=0}^{9} (-1)^i z^i / (2i+1)!,  cos th = sum_{i=0}^{10} (-1)^i z^i / (2i)!,
+  // both by Estrin's scheme
+  const double z2 = z * z, z4 = z2 * z2, z8 = z4 * z4;
+  const double a0 = fma(-InvFact<3>::value, z, 1.0);
+  const double a1 = fma(-InvFact<7>::value, z, InvFact<5>::value);
+  const double a2 = fma(-InvFact<11>::value, z, InvFact<9>::value);
+  const double a3 = fma(-InvFact<15>::value, z, InvFact<13>::value);
+  const double a4 = fma(-InvFact<19>::value, z, InvFact<17>::value);
+  const double b0 = fma(a1, z2, a0), b1 = fma(a3, z2, a2);
+  const double ps = fma(a4, z8, fma(b1, z4, b0));
   const double sn = th * ps;
-  double pc = InvFact<20>::value;
-  pc = fma(pc, z, -InvFact<18>::value);
-  pc = fma(pc, z, InvFact<16>::value);
-  pc = fma(pc, z, -InvFact<14>::value);
-  pc = fma(pc, z, InvFact<12>::value);
-  pc = fma(pc, z, -InvFact<10>::value);
-  pc = fma(pc, z, InvFact<8>::value);
-  pc = fma(pc, z, -InvFact<6>::value);
-  pc = fma(pc, z, InvFact<4>::value);
-  pc = fma(pc, z, -InvFact<2>::value);
-  pc = fma(pc, z, 1.0);
+  const double g0 = fma(-InvFact<2>::value, z, 1.0);
+  const double g1 = fma(-InvFact<6>::value, z, InvFact<4>::value);
+  const double g2 = fma(-InvFact<10>::value, z, InvFact<8>::value);
+  const double g3 = fma(-InvFact<14>::value, z, InvFact<12>::value);
+  const double g4 = fma(-InvFact<18>::value, z, InvFact<16>::value);
+  const double h0 = fma(g1, z2, g0), h1 = fma(g3, z2, g2), h2 = fma(InvFact<20>::value, z2, g4);
+  const double pc = fma(h2, z8, fma(h1, z4, h0));
   const int quad = static_cast<int>(q) & 3;
   const double a = (quad & 1) ? -sn : pc;   // cos(th + quad pi/2) for quad 0, 1
   const double b = (quad & 1) ? pc : sn;    // sin(th + quad pi/2) for quad 0, 1
