@@ -122,10 +122,12 @@ __device__ __forceinline__ double scale2(double p, int k) {  // p * 2^k, -1022 <
   return p * __longlong_as_double(static_cast<long long>(k + 1023) << 52);
 }
 
+// Branch-free: every lane runs the same instructions and the special cases
+// (NaN, overflow, underflow) are selected at the end.  p * 2^k is one
+// correctly rounded scaling (v_ldexp_f64), which equals the reference's
+// scaling by exact powers of two, including its two-step scaling into the
+// subnormal range (one rounding either way).
 __device__ inline double dexp(double x) {
-  if (!(x == x)) return x;
-  if (x > 0x1.62e42fefa39efp+9) return __longlong_as_double(0x7ff0000000000000LL);
-  if (x < -0x1.74910d52d3051p+9) return 0.0;
   const double kd = rint(x * kInvLn2);
   const double r = fma(-kd, kLn2Tail, fma(-kd, kLn2Head, x));
   // e^r = 1 + (r + r^2 Q(r)), Q(r) = sum_{i=2}^{13} r^{i-2} / i! by Estrin's
@@ -141,22 +143,24 @@ __device__ inline double dexp(double x) {
   const double s0 = fma(q1, r2, q0), s1 = fma(q3, r2, q2), s2 = fma(q5, r2, q4);
   const double Q = fma(s2, r8, fma(s1, r4, s0));
   const double p = 1.0 + fma(r2, Q, r);
-  const int k = static_cast<int>(kd);
-  if (k > 1023) return scale2(p * 2.0, k - 1);
-  if (k < -1022) return scale2(scale2(p, k + 200), -200);
-  return scale2(p, k);
+  const int k = static_cast<int>(fmin(fmax(kd, -2000.0), 2000.0));
+  double res = __builtin_ldexp(p, k);
+  res = x > 0x1.62e42fefa39efp+9 ? __longlong_as_double(0x7ff0000000000000LL) : res;
+  res = x < -0x1.74910d52d3051p+9 ? 0.0 : res;
+  return x == x ? res : x;
 }
 
-__device__ inline double dlog(double x) {
-  if (!(x == x) || x < 0.0) return __longlong_as_double(0x7ff8000000000000LL);
-  if (x == 0.0) return -__longlong_as_double(0x7ff0000000000000LL);
-  if (x == __longlong_as_double(0x7ff0000000000000LL)) return x;
-  int e = 0;
-  if (x < 0x1p-1022) { x = x * 0x1p+54; e = -54; }
+// Branch-free like dexp: special inputs (NaN, negative, 0, +inf) selected at
+// the end.
+__device__ inline double dlog(double x0) {
+  const bool sub = x0 < 0x1p-1022;
+  const double x = sub ? x0 * 0x1p+54 : x0;
   const long long bits = __double_as_longlong(x);
-  e += static_cast<int>((bits >> 52) & 0x7ff) - 1023;
+  int e = static_cast<int>((bits >> 52) & 0x7ff) - 1023 - (sub ? 54 : 0);
   double f = __longlong_as_double((bits & 0x000fffffffffffffLL) | 0x3ff0000000000000LL);
-  if (f > 0x1.6a09e667f3bcdp+0) { f = f * 0.5; e += 1; }
+  const bool big = f > 0x1.6a09e667f3bcdp+0;
+  f = big ? f * 0.5 : f;
+  e += big ? 1 : 0;
   const double s = (f - 1.0) / (f + 1.0);
   const double z = s * s;
   // 2 atanh(s) = 2 (s + s z P(z)), P(z) = sum_{i=1}^{11} z^{i-1} / (2i+1) by
@@ -172,7 +176,10 @@ __device__ inline double dlog(double x) {
   double t = fma(s * z, P, s);
   t = t + t;
   const double ed = static_cast<double>(e);
-  return ed * kLn2Head + (ed * kLn2Tail + t);
+  double res = ed * kLn2Head + (ed * kLn2Tail + t);
+  res = x0 == __longlong_as_double(0x7ff0000000000000LL) ? x0 : res;
+  res = x0 == 0.0 ? -__longlong_as_double(0x7ff0000000000000LL) : res;
+  return (x0 == x0 && x0 >= 0.0) ? res : __longlong_as_double(0x7ff8000000000000LL);
 }
 
 __device__ inline void cossin_2pi(double v, double& c, double& s) {

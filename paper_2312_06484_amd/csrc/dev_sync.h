@@ -24,28 +24,25 @@ __device__ __forceinline__ double ninf() { return -__longlong_as_double(0x7ff000
 // log((exp(a) + exp(b)) / 2), symmetric in (a, b)
 __device__ __forceinline__ double pair_mean(double a, double b) {
   const double hi = a > b ? a : b, lo = a > b ? b : a;
-  if (hi == ninf()) return hi;
   double t = dexp(lo - hi);
   t = 1.0 + t;
   t = dlog(t);
-  return (hi + t) - kLn2;
+  return hi == ninf() ? hi : (hi + t) - kLn2;
 }
 
 // log(exp(a) + exp(b)), symmetric in (a, b)
 __device__ __forceinline__ double log_add_exp(double a, double b) {
   const double hi = a > b ? a : b, lo = a > b ? b : a;
-  if (hi == ninf()) return hi;
   double t = dexp(lo - hi);
   t = 1.0 + t;
   t = dlog(t);
-  return hi + t;
+  return hi == ninf() ? hi : hi + t;
 }
 
 // probability that an island with log-weight lk takes its partner's block
 __device__ __forceinline__ double take_partner_prob(double lk, double lp) {
-  if (lp == ninf()) return 0.0;
-  if (lk == ninf()) return 1.0;
-  return 1.0 / (1.0 + dexp(lk - lp));
+  const double q = 1.0 / (1.0 + dexp(lk - lp));
+  return lp == ninf() ? 0.0 : (lk == ninf() ? 1.0 : q);
 }
 
 // ------------------------------------------------------------ cross-block data
@@ -278,17 +275,17 @@ __device__ __forceinline__ double team_scan_f64(double v, int TP, double* red) {
 struct EnfRec { double E, a, b; };
 
 __device__ __forceinline__ EnfRec enf_leaf(double L) {
-  if (L == ninf()) return EnfRec{L, 0.0, 0.0};
-  const double E = rint(L * kInvLn2);
-  const double w = dexp(fma(-E, kLn2Tail, fma(-E, kLn2Head, L)));
-  return EnfRec{E, w, w * w};
+  const bool dead = L == ninf();
+  const double E = dead ? 0.0 : rint(L * kInvLn2);
+  const double w = dexp(fma(-E, kLn2Tail, fma(-E, kLn2Head, dead ? 0.0 : L)));
+  return dead ? EnfRec{L, 0.0, 0.0} : EnfRec{E, w, w * w};
 }
 
+// Branch-free: an empty side (E = -inf, a = b = 0) contributes exact zeros.
 __device__ __forceinline__ EnfRec enf_join(const EnfRec& x, const EnfRec& y) {
-  if (x.E == ninf()) return y;
-  if (y.E == ninf()) return x;
   const double E = x.E > y.E ? x.E : y.E;
-  const int dx = static_cast<int>(x.E - E), dy = static_cast<int>(y.E - E);   // <= 0
+  // exponent gaps <= 0, clamped (an empty side's gap is -inf or NaN)
+  const int dx = static_cast<int>(fmax(x.E - E, -4000.0)), dy = static_cast<int>(fmax(y.E - E, -4000.0));
   return EnfRec{E, __builtin_ldexp(x.a, dx) + __builtin_ldexp(y.a, dy),
                 __builtin_ldexp(x.b, 2 * dx) + __builtin_ldexp(y.b, 2 * dy)};
 }
