@@ -121,6 +121,16 @@ __device__ __forceinline__ double dppd(double v) {
   return __longlong_as_double(static_cast<long long>(dpp64<CTRL>(static_cast<uint64_t>(__double_as_longlong(v)))));
 }
 
+// Lane l's value, in every lane (read through a scalar register).
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), l));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v >> 32)), l));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __longlong_as_double(static_cast<long long>(readlane_u64(static_cast<uint64_t>(__double_as_longlong(v)), l)));
+}
+
 // ------------------------------------------------------------ team / block reductions
 // A team is TP consecutive lanes (TP a power of two); TP <= 64 stays inside
 // one wave (shuffles only), TP > 64 spans TP/64 whole waves (LDS combine).
@@ -159,8 +169,12 @@ __device__ __forceinline__ double team_max(double v, int TP, double* red) {
   if (TP >= 4) v = fmax(v, dppd<0x4E>(v));
   if (TP >= 8) v = fmax(v, dppd<0x141>(v));
   if (TP >= 16) v = fmax(v, dppd<0x140>(v));
-  if (TP >= 32) v = fmax(v, __shfl_xor(v, 16, 64));
-  if (TP >= 64) v = fmax(v, __shfl_xor(v, 32, 64));
+  if (TP >= 64) {
+    // whole wave: the four row maxima through scalar registers
+    v = fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+  } else if (TP >= 32) {
+    v = fmax(v, __shfl_xor(v, 16, 64));
+  }
   if (TP > 64) {
     const int tid = threadIdx.x;
     if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -175,8 +189,12 @@ __device__ __forceinline__ double team_max(double v, int TP, double* red) {
 }
 
 __device__ __forceinline__ uint64_t team_sum_u64(uint64_t v, int TP, uint64_t* red) {
-  const int w = TP < 64 ? TP : 64;
-  for (int d = 1; d < w; d <<= 1) v += __shfl_xor(v, d, 64);
+  if (TP >= 2) v += dpp64<0xB1>(v);
+  if (TP >= 4) v += dpp64<0x4E>(v);
+  if (TP >= 8) v += dpp64<0x141>(v);
+  if (TP >= 16) v += dpp64<0x140>(v);
+  if (TP >= 64) v = (readlane_u64(v, 0) + readlane_u64(v, 16)) + (readlane_u64(v, 32) + readlane_u64(v, 48));
+  else if (TP >= 32) v += __shfl_xor(v, 16, 64);
   if (TP > 64) {
     const int tid = threadIdx.x;
     if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -223,8 +241,12 @@ __device__ __forceinline__ double team_sum_f64(double v, int TP, double* red) {
   if (TP >= 4) v += dppd<0x4E>(v);
   if (TP >= 8) v += dppd<0x141>(v);
   if (TP >= 16) v += dppd<0x140>(v);
-  if (TP >= 32) v += __shfl_xor(v, 16, 64);
-  if (TP >= 64) v += __shfl_xor(v, 32, 64);
+  if (TP >= 64) {
+    // the rows' sums through scalar registers, in the tree xor 16, xor 32 forms
+    v = (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+  } else if (TP >= 32) {
+    v += __shfl_xor(v, 16, 64);
+  }
   if (TP > 64) {
     const int tid = threadIdx.x;
     if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -299,14 +321,20 @@ __device__ __forceinline__ EnfRec enf_join(const EnfRec& x, const EnfRec& y) {
 // The lanes' part of wave_reduce_enf: lane l holds the record of its
 // aligned run; groups of 2, 4, ..., min(n, 64) lanes join (xor 1, xor 2,
 // then the 8- and 16-lane mirrors, whose partner holds exactly the other
-// half of the group as with xor 4, xor 8, then xor 16, xor 32).
+// half of the group as with xor 4, xor 8, then xor 16, xor 32; a whole wave
+// joins its four rows' records through scalar registers in that same tree).
 __device__ __forceinline__ EnfRec wave_butterfly_enf(EnfRec r, int n) {
   if (n >= 2) r = enf_join(r, EnfRec{dppd<0xB1>(r.E), dppd<0xB1>(r.a), dppd<0xB1>(r.b)});
   if (n >= 4) r = enf_join(r, EnfRec{dppd<0x4E>(r.E), dppd<0x4E>(r.a), dppd<0x4E>(r.b)});
   if (n >= 8) r = enf_join(r, EnfRec{dppd<0x141>(r.E), dppd<0x141>(r.a), dppd<0x141>(r.b)});
   if (n >= 16) r = enf_join(r, EnfRec{dppd<0x140>(r.E), dppd<0x140>(r.a), dppd<0x140>(r.b)});
-  if (n >= 32) r = enf_join(r, EnfRec{__shfl_xor(r.E, 16, 64), __shfl_xor(r.a, 16, 64), __shfl_xor(r.b, 16, 64)});
-  if (n >= 64) r = enf_join(r, EnfRec{__shfl_xor(r.E, 32, 64), __shfl_xor(r.a, 32, 64), __shfl_xor(r.b, 32, 64)});
+  auto row = [&](int l) { return EnfRec{readlane_f64(r.E, l), readlane_f64(r.a, l), readlane_f64(r.b, l)}; };
+  if (n >= 64) {
+    // rows (0, 1) and (2, 3), then the two halves: the tree xor 16, xor 32 forms
+    r = enf_join(enf_join(row(0), row(16)), enf_join(row(32), row(48)));
+  } else if (n >= 32) {
+    r = enf_join(r, EnfRec{__shfl_xor(r.E, 16, 64), __shfl_xor(r.a, 16, 64), __shfl_xor(r.b, 16, 64)});
+  }
   return r;
 }
 

@@ -404,7 +404,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       }
       const uint64_t incl = team_scan_u64(tsum, TP, red_u);
       // Q = sum_i q_i of the island: the scan's value in the team's last lane
-      const uint64_t Qk = TP <= 64 ? __shfl(incl, (tid & 63) | (TP - 1), 64) : team_sum_u64(tsum, TP, red_u);
+      const uint64_t Qk = TP == 64 ? readlane_u64(incl, 63)
+                          : (TP < 64 ? __shfl(incl, (tid & 63) | (TP - 1), 64) : team_sum_u64(tsum, TP, red_u));
       if (lane == 0 && active && !replay) {
         const double L = (Qk == 0) ? ninf() : Lpre + ((mx + dlog(static_cast<double>(Qk))) + a.cst_q);
         lvp(par)[li] = L;
