@@ -233,6 +233,38 @@ __device__ __forceinline__ uint64_t team_scan_u64(uint64_t v, int TP, uint64_t* 
   return v;
 }
 
+// DPP move of a 32-bit value where lanes without a source keep `old`
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ int dpp_keep(int v, int old) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWMASK, 0xf, false);
+}
+
+// Exclusive max-scan of an int over the team's lanes (lane order): the
+// largest value of the lanes before this one, -1 for the team's first lane.
+__device__ __forceinline__ int team_exclusive_max(int v, int TP, int* red) {
+  const int tid = threadIdx.x;
+  const int sl = tid & ((TP < 64 ? TP : 64) - 1);
+  // inclusive within the wave part of the team: rows first, then the row broadcasts
+  if (TP > 1) { const int t = dpp_keep<0x111>(v, -1); if (sl >= 1) v = v > t ? v : t; }
+  if (TP > 2) { const int t = dpp_keep<0x112>(v, -1); if (sl >= 2) v = v > t ? v : t; }
+  if (TP > 4) { const int t = dpp_keep<0x114>(v, -1); if (sl >= 4) v = v > t ? v : t; }
+  if (TP > 8) { const int t = dpp_keep<0x118>(v, -1); if (sl >= 8) v = v > t ? v : t; }
+  if (TP > 16) { const int t = dpp_keep<0x142, 0xa>(v, -1); v = v > t ? v : t; }
+  if (TP > 32) { const int t = dpp_keep<0x143, 0xc>(v, -1); v = v > t ? v : t; }
+  int wave_prev = -1;                          // the team's earlier waves (TP > 64)
+  if (TP > 64) {
+    if ((tid & 63) == 63) red[tid >> 6] = v;
+    __syncthreads();
+    const int w0 = (tid / TP) * (TP >> 6);
+    for (int i = w0; i < (tid >> 6); ++i) wave_prev = wave_prev > red[i] ? wave_prev : red[i];
+    __syncthreads();
+    v = v > wave_prev ? v : wave_prev;
+  }
+  int ex = dpp_keep<0x138>(v, -1);             // wave_shr:1, lane l reads lane l-1
+  if (sl == 0) ex = wave_prev;
+  return ex;
+}
+
 // sum of a double over the team's lanes (fixed pattern; every lane gets it):
 // partners xor 1, xor 2, the 8- and 16-lane mirrors, xor 16, xor 32 (each
 // adds the other half of its group, so every lane holds the same bits)

@@ -60,6 +60,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   __shared__ double red_d[kWaves];
   __shared__ uint64_t red_u[kWaves];
   __shared__ uint64_t bc_u[kBlock];
+  __shared__ int bc_i[kWaves];
   __shared__ int s_sstar;
   __shared__ double s_enf[kWaves], s_encmax[kWaves];
   __shared__ int s_src[kMaxIslandsPerBlock];          // this step's source island of each island
@@ -89,8 +90,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   const int64_t n0 = Plain ? 0 : a.n0, n1 = Plain ? a.T : a.n1;
 
   Store* sx = reinterpret_cast<Store*>(smem);                                    // [kBlock*NZ]
-  uint64_t* sC = reinterpret_cast<uint64_t*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));
-  int* sA = reinterpret_cast<int*>(sC + kBlock * PPT);                             // [kBlock*PPT]
+  int* sA = reinterpret_cast<int*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));   // [kBlock*PPT]
   double* lvb = reinterpret_cast<double*>(sA + kBlock * PPT);                      // [2][2c]
   double* up = lvb + 4 * c;                                                       // [2G]
   // with res_lds: this block's resampled states of the last two steps, by
@@ -415,47 +415,59 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       // ---- internal resampling ----
       if (n < a.T - 1) {
         Store* sxt = sx + team * TP * NZ;
-        uint64_t* sCt = sC + team * TP * PPT;
-        uint64_t run = incl - tsum;
+        int* sAt = sA + team * TP * PPT;
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
-          run += q[r];
-          sCt[j0 + r] = run;
 #pragma unroll
           for (int d = 0; d < DX; ++d) sxt[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
+          sAt[j0 + r] = -1;                                   // no run starts here (yet)
         }
         uint64_t U = 0;
         if (lane == 0 && active && Qk > 0)
           U = bounded_u64_from(wsys, key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, Qk);
         U = team_bcast(U, TP, bc_u);
+        // Slot j takes min{i : N C_i > U + j Q}.  Equivalently particle i owns
+        // the slots [S(C_{i-1}), S(C_i)) with S(C) = #{j < N : U + j Q < N C}
+        // = 0 if N C <= U, else min(N, floor((N C - U - 1) / Q) + 1): each
+        // particle marks the first slot of its run, and a slot's ancestor is
+        // the last mark at or before it.  The quotient is estimated in double
+        // precision (within one of the exact one, as x / Q <= N) and
+        // corrected in integers.
+        const double rQ = 1.0 / static_cast<double>(Qk);
+        auto S_of = [&](uint64_t C) -> int {
+          const uint64_t NC = static_cast<uint64_t>(N) * C;
+          const uint64_t xq = NC > U ? NC - U - 1 : 0;
+          uint64_t qd = static_cast<uint64_t>(floor(static_cast<double>(xq) * rQ));
+          qd = qd * Qk > xq ? qd - 1 : qd;
+          qd = xq - qd * Qk >= Qk ? qd + 1 : qd;
+          const uint64_t sv = qd + 1;
+          return NC <= U ? 0 : (sv < static_cast<uint64_t>(N) ? static_cast<int>(sv) : N);
+        };
+        uint64_t C = incl - tsum;                              // C_{j0-1}
+        int s_prev = S_of(C);
         team_sync(TP);
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          C += q[r];
+          const int s_cur = S_of(C);
+          if (active && Qk > 0 && j0 + r < N && s_cur > s_prev) sAt[s_prev] = j0 + r;
+          s_prev = s_cur;
+        }
+        team_sync(TP);
+        int mk[PPT];
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const int v = (j0 + r < N) ? sAt[j0 + r] : -1;
+          mk[r] = r == 0 ? v : (v > mk[r - 1] ? v : mk[r - 1]);
+        }
+        const int before = team_exclusive_max(mk[PPT - 1], TP, bc_i);
         Store* xo = static_cast<Store*>(a.x1[par]) + (static_cast<int64_t>(k) * N) * DX;
-        int* sAt = sA + team * TP * PPT;
         unsigned long long dig = 0;
-        // ancestors of this lane's slots: min{i : N C_i > U + j Q}; the
-        // lane's slots are consecutive and their ancestors non-decreasing, so
-        // one binary search finds the first and the rest advance from it
-        int prev = 0;
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           const int j = j0 + r;
           if (active && j < N) {
-            int anc = j;
-            if (Qk > 0) {
-              const uint64_t t = U + static_cast<uint64_t>(j) * Qk;
-              int lo = prev;
-              if (r == 0) {
-                int hi = N - 1;
-                while (lo < hi) {
-                  const int mid = (lo + hi) >> 1;
-                  if (static_cast<uint64_t>(N) * sCt[mid] > t) hi = mid; else lo = mid + 1;
-                }
-              } else {
-                while (static_cast<uint64_t>(N) * sCt[lo] <= t) ++lo;
-              }
-              anc = lo;
-              prev = lo;
-            }
+            const int anc = Qk > 0 ? (mk[r] > before ? mk[r] : before) : j;
             sAt[j] = anc;
             if (tr_anc) tr_anc[(n * m + k) * static_cast<int64_t>(N) + j] = anc;
             if (rec_anc) rec_anc[((n - n0) * m + k) * static_cast<int64_t>(N) + j] = static_cast<uint16_t>(anc);
@@ -589,7 +601,7 @@ inline size_t fwd_res_bytes(size_t store_bytes, int dx, int c, int N) {
 
 inline size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) {
   const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
-  return sx + 8 * size_t(kBlock) * ppt + 4 * size_t(kBlock) * ppt + 8 * 4 * size_t(c) + 8 * 2 * size_t(G);
+  return sx + 4 * size_t(kBlock) * ppt + 8 * 4 * size_t(c) + 8 * 2 * size_t(G);
 }
 
 template <class Model, typename Store, int PPT>
