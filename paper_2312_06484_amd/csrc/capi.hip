@@ -448,6 +448,7 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
     if (C > 1) {
       airpf::FwdArgs r = a;
       r.n0 = lo; r.n1 = hi; r.replay_pi = 1; r.ck_in = lo > 0 ? 1 : 0;
+      r.sstar_in = static_cast<const int32_t*>(ctx->s_sstar.p);
       r.rec_x = ctx->s_recx.p;
       r.rec_anc = static_cast<uint16_t*>(ctx->s_reca.p);
       r.tr_sstar = nullptr; r.tr_enf = nullptr; r.tr_lpost = nullptr; r.tr_anc = nullptr; r.tr_digest = nullptr;
@@ -881,6 +882,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
         const int64_t cidx = it.C - 1 - j;
         a.n0 = cidx * it.K; a.n1 = std::min(it.T, (cidx + 1) * it.K);
         a.replay_pi = 1; a.ck_in = a.n0 > 0 ? 1 : 0; a.ck_every = it.K;
+        a.sstar_in = static_cast<const int32_t*>(at(it.o_sstar));
         a.ck_x = at(it.o_ckx); a.ck_L = static_cast<double*>(at(it.o_ckL));
         a.tr_pi = static_cast<int32_t*>(at(it.o_pi));
         a.rec_x = at(it.o_recx); a.rec_anc = static_cast<uint16_t*>(at(it.o_reca));

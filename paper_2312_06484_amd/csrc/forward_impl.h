@@ -545,7 +545,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     }
     }  // tree
     ++n;
-    if (n < n1 && !never) {
+    // a replayed step whose maps stay inside blocks reads only this block's
+    // resampled states: the block barrier above orders them
+    const bool local_replay = replay && a.sstar_in && a.sstar_in[n - 1] <= lc;
+    if (n < n1 && !never && !local_replay) {
       grid_arrive(a.bar, bid, epoch);
       pending = true;
     }

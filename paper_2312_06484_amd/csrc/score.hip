@@ -98,7 +98,16 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
   const double logz = *a.logz;
 
   for (int64_t n = a.n_hi - 1; n >= a.n_lo; --n) {
-    if (n < a.n_hi - 1 && !grid_barrier(a.bar, a.G, bid, epoch, a.status)) return;
+    // the children of step n's particles are in their island's aligned
+    // 2^{s*}-block: inside this block when s* <= log2 c, and then the block
+    // barrier orders their adjoints
+    if (n < a.n_hi - 1) {
+      if (a.sstar_all[n] > a.lc) {
+        if (!grid_barrier(a.bar, a.G, bid, epoch, a.status)) return;
+      } else {
+        __syncthreads();
+      }
+    }
     const bool last = (n == a.T - 1);
     const int B = last ? 1 : (1 << a.sstar_all[n]);
     const int par = static_cast<int>(n & 1), npar = par ^ 1;
