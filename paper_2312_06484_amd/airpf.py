@@ -70,6 +70,10 @@ def lib():
         if not os.path.exists(LIBPATH):
             raise RuntimeError("libairpf.so is missing: build it with paper_2312_06484_amd/build.py "
                                "(or __graft_entry__.build()); the filter has no CPU fallback")
+        # torch first: its HIP runtime (soname libamdhip64.so.7) is then the
+        # one the library binds to.  Loaded the other way round, torch would
+        # bring up a second HIP/HSA runtime by file name that finds no device.
+        import torch  # noqa: F401
         L = C.CDLL(LIBPATH)
         L.airpf_status_str.restype = C.c_char_p
         L.airpf_status_str.argtypes = [C.c_int]

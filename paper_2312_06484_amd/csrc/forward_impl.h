@@ -545,9 +545,12 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     }
     }  // tree
     ++n;
-    // a replayed step whose maps stay inside blocks reads only this block's
-    // resampled states: the block barrier above orders them
-    const bool local_replay = replay && a.sstar_in && a.sstar_in[n - 1] <= lc;
+    // a recomputed step n reads step n-1's resampled blocks through the maps
+    // of s*_{n-1} and overwrites the buffer that step n-1 read through those
+    // of s*_{n-2}; when neither reaches outside this block (s* <= log2 c), a
+    // block barrier orders everything the step touches
+    const bool local_replay = replay && a.sstar_in && a.sstar_in[n - 1] <= lc &&
+                              (n < 2 || a.sstar_in[n - 2] <= lc);
     if (n < n1 && !never && !local_replay) {
       grid_arrive(a.bar, bid, epoch);
       pending = true;

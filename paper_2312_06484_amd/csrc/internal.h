@@ -33,8 +33,8 @@ struct FwdArgs {
   // ---- what the score needs (all optional) ----
   int64_t n0, n1;             // steps [n0, n1) of this launch (0, T for a plain run)
   int replay_pi;              // 1: island maps from tr_pi, no cascade, no island weights
-  const int32_t* sstar_in;    // replay (optional): s* of each step; a step whose stages stay
-                              // inside blocks (s* <= log2 c) needs no grid barrier
+  const int32_t* sstar_in;    // replay (optional): s* of each step; the barrier before step n
+                              // is a block barrier when s*_{n-1} and s*_{n-2} are <= log2 c
   int64_t ck_every;           // checkpoint interval K (0: none)
   void* ck_x;                 // Store*, [ceil(T/K)][m*N*DX] state entering step c*K
   double* ck_L;               // [ceil(T/K)][m] island log-weights entering step c*K

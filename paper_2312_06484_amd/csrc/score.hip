@@ -99,10 +99,12 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
 
   for (int64_t n = a.n_hi - 1; n >= a.n_lo; --n) {
     // the children of step n's particles are in their island's aligned
-    // 2^{s*}-block: inside this block when s* <= log2 c, and then the block
-    // barrier orders their adjoints
+    // 2^{s*_n}-block, and step n overwrites the adjoints that step n+1 read
+    // from the 2^{s*_{n+1}}-blocks of its own children: when both stay inside
+    // this block (s* <= log2 c), the block barrier orders every access
     if (n < a.n_hi - 1) {
-      if (a.sstar_all[n] > a.lc) {
+      const bool cross_next = n + 1 < a.T - 1 && a.sstar_all[n + 1] > a.lc;
+      if (a.sstar_all[n] > a.lc || cross_next) {
         if (!grid_barrier(a.bar, a.G, bid, epoch, a.status)) return;
       } else {
         __syncthreads();

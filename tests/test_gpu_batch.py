@@ -99,3 +99,30 @@ def test_batch_autotuned_tiling_changes_nothing(ctx, want_score):
         assert np.array_equal(lz0, lz1)
         if want_score:
             assert np.array_equal(gr0, gr1)
+
+
+def test_full_size_proposal_batch_score_matches_single(ctx):
+    """The 64-chain proposal workload at full size (T up to 2000, m up to
+    1024, many blocks per problem, checkpoints every 100 steps) with scores:
+    sampled items bit-identical to the same problem run alone.  At this size
+    blocks run many steps apart between grid barriers, so any missing
+    ordering between the recomputed forward's or the reverse pass's buffers
+    shows up here."""
+    import torch
+    dev = torch.device("cuda", 0)
+    items = W.batch_c4(64)
+    ydev = {}
+    probs = []
+    for it in items:
+        if it["T"] not in ydev:
+            ydev[it["T"]] = torch.tensor(W.sv_data(it["T"]), dtype=torch.float64, device=dev)
+        probs.append(dict(theta=it["theta"], y=ydev[it["T"]].data_ptr(), T=it["T"], m=it["m"], N=it["N"],
+                          seed=it["seed"]))
+    st, lz, gr, ist = ctx.run_batch(1, probs, tau=0.3, want_score=True, ckpt_every=100, y_on_device=True)
+    assert (ist == 0).all()
+    for i in range(0, 64, 5):
+        p = probs[i]
+        _, l1, g1 = ctx.score(1, p["theta"], None, p["m"], p["N"], p["seed"], tau=0.3, ckpt_every=100,
+                              y_device_ptr=p["y"], T=p["T"])
+        assert l1 == lz[i], i
+        assert np.array_equal(g1, gr[i]), i

@@ -72,3 +72,20 @@ def test_score_tiling_invariant(ctx):
             ref = (lz, g)
         else:
             assert lz == ref[0] and np.array_equal(g, ref[1])
+
+
+@pytest.mark.parametrize("tau", [0.3, 0.9])
+def test_score_tiling_invariant_many_blocks(ctx, tau):
+    """SV 4096 x 128 over 500 observations, checkpoints every 50 steps: 16 to
+    256 blocks, so stages stay inside a block on some steps and reach across
+    blocks on others (more often at tau = 0.9); the score and log Zhat must
+    not depend on the block count."""
+    T = 500
+    y = W.sv_data(T)
+    ref = None
+    for cap in (None, 16, 64):
+        _, lz, g = _with_cap(cap, lambda: ctx.score(1, W.SV_THETA, y, 4096, 128, 11, tau=tau, ckpt_every=50))
+        if ref is None:
+            ref = (lz, g)
+        else:
+            assert lz == ref[0] and np.array_equal(g, ref[1]), cap
