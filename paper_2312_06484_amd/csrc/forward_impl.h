@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_cooperative_groups.h>
 #include <stdint.h>
+#include <cstdlib>
 
 #include "dev_models.h"
 #include "dev_sync.h"
@@ -572,6 +573,418 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   }
 }
 
+// ------------------------------------------------------------ pipelined forward
+// Untraced runs whose resampled states fit the block's LDS copy and whose
+// teams lie inside one wave (TP <= 64), with 1/(2m) < tau <= 1.
+//
+// Most steps do not interact, and then a block's next step needs nothing
+// from the other blocks.  A block of this kernel has four worker waves
+// (the island passes, exactly those of forward_body) and one control wave
+// that does everything involving other blocks.  Between two joins (block
+// barriers) the workers run step n under the assumption s*_{n-1} = 0 (every
+// island continues from its own resampled block with its own weight, both
+// in LDS), while the control wave builds the island tree and ENF records of
+// step n-1, publishes them, waits for the other blocks, and evaluates the
+// stages of step n-1 one at a time until one does not interact.  After the
+// join, a step whose cascade found s* > 0 is run again with the walk's
+// sources (all blocks have passed the barrier by then).  Every value is
+// computed by the same operations as in forward_body, so the results are
+// identical.
+//
+// Stage 1 needs only the blocks' level-1 ENF records, so the control wave
+// publishes those alone and synchronises; the island tree and the other
+// levels' records follow (with a second barrier) only when stage 1
+// interacts, which every block decides alike.  Only then can another block
+// read this block's resampled states of that step (in the rerun of the next
+// step), so they are copied from LDS to HBM at that point, not by the
+// passes: a step whose stage 1 does not interact moves no state through
+// HBM at all.
+constexpr int kPipeBlock = kBlock + 64;
+
+template <class Model, typename Store, int PPT>
+__device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bid) {
+  constexpr int DX = Model::DX;
+  constexpr int NZ = PPT * DX;
+  static_assert(NZ % 4 == 0, "a lane consumes whole Philox blocks");
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red_d[kWaves];            // team helpers' scratch (unused for TP <= 64)
+  __shared__ uint64_t red_u[kWaves];
+  __shared__ uint64_t bc_u[kBlock];
+  __shared__ int bc_i[kWaves];
+  __shared__ int s_src[kMaxIslandsPerBlock];
+  __shared__ double s_lpre[kMaxIslandsPerBlock];
+  __shared__ int s_ctl[2];                    // s* of the step just decided; 1: leave
+
+  const int tid = threadIdx.x;
+  const bool ctl = tid >= kBlock;             // the control wave
+  const int lane64 = tid & 63;
+  const int TP = a.TP, tpb = kBlock / TP;
+  const int team = tid / TP, lane = tid & (TP - 1);
+  const int m = a.m, N = a.N, S = a.S, c = a.c, lc = a.lc, G = a.G;
+  const int64_t T = a.T;
+  const int kbase = bid * c;
+  const Key key = make_key(a.seed);
+  const int passes = (c + tpb - 1) / tpb;
+
+  Store* sx = reinterpret_cast<Store*>(smem);                                    // [kBlock*NZ]
+  int* sA = reinterpret_cast<int*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));   // [kBlock*PPT]
+  double* lvb = reinterpret_cast<double*>(sA + kBlock * PPT);                      // [2][2c]
+  double* up = lvb + 4 * c;                                                       // [2G]
+  Store* res = reinterpret_cast<Store*>(up + 2 * G);                              // [2][c*N*DX]
+  const int64_t res_words = static_cast<int64_t>(c) * N * DX;
+  auto lvp = [&](int par) { return lvb + 2 * c * par; };
+  auto wsync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+
+  // ================= worker waves: the island passes of step n =================
+  // spec: sources and entering weights under s*_{n-1} = 0
+  auto run_passes = [&](int64_t n, bool spec) {
+    const int par = static_cast<int>(n & 1), ppar = par ^ 1;
+    for (int p = 0; p < passes; ++p) {
+      const int li = p * tpb + team;
+      const bool active = li < c;
+      const int k = kbase + (active ? li : 0);
+      const int j0 = lane * PPT;
+      uint32_t wsys[4] = {0u, 0u, 0u, 0u};
+      if (n < T - 1 && lane == 0) draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
+      double x[PPT][DX];
+      double Lpre = 0.0;
+      if (n == 0) {
+        double z[NZ];
+        for (int g = 0; g < NZ / 4; ++g) {
+          double t[4];
+          normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
+        }
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * DX, x[r]);
+      } else {
+        const int src = spec ? k : s_src[active ? li : 0];
+        if (lane == 0 && active) Lpre = spec ? lvp(ppar)[li] : s_lpre[li];
+        Store xr[PPT][DX];
+        if (src >= kbase && src < kbase + c) {
+          const Store* xin = res + ppar * res_words + static_cast<int64_t>(src - kbase) * N * DX;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r)
+#pragma unroll
+            for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? xin[(j0 + r) * DX + d] : Store(0);
+        } else {
+          const Store* xin = static_cast<const Store*>(a.x1[ppar]) + (static_cast<int64_t>(src) * N) * DX;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r)
+#pragma unroll
+            for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? get(xin + (j0 + r) * DX + d) : Store(0);
+        }
+        double z[NZ];
+        for (int g = 0; g < NZ / 4; ++g) {
+          double t[4];
+          normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
+        }
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          double xp[DX];
+#pragma unroll
+          for (int d = 0; d < DX; ++d) xp[d] = static_cast<double>(xr[r][d]);
+          Model::template prop<Store>(a.mp, xp, z + r * DX, x[r]);
+        }
+      }
+
+      // ---- weighting ----
+      const double* yn = a.y + n * a.dy;
+      double lw[PPT];
+      double mx = ninf();
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        const bool valid = active && (j0 + r < N);
+        double v = valid ? Model::logpot(a.mp, x[r], yn) : ninf();
+        if (!(v == v)) v = ninf();
+        lw[r] = v;
+        mx = fmax(mx, v);
+      }
+      mx = team_max(mx, TP, red_d);
+      uint64_t q[PPT];
+      uint64_t tsum = 0;
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        q[r] = (mx == ninf()) ? 0 : static_cast<uint64_t>(dexp(lw[r] - mx) * 0x1p40);
+        tsum += q[r];
+      }
+      const uint64_t incl = team_scan_u64(tsum, TP, red_u);
+      const uint64_t Qk = TP == 64 ? readlane_u64(incl, 63) : __shfl(incl, (tid & 63) | (TP - 1), 64);
+      if (lane == 0 && active) {
+        const double L = (Qk == 0) ? ninf() : Lpre + ((mx + dlog(static_cast<double>(Qk))) + a.cst_q);
+        lvp(par)[li] = L;
+      }
+
+      // ---- internal resampling (systematic, by offspring counts) ----
+      if (n < T - 1) {
+        Store* sxt = sx + team * TP * NZ;
+        int* sAt = sA + team * TP * PPT;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+#pragma unroll
+          for (int d = 0; d < DX; ++d) sxt[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
+          sAt[j0 + r] = -1;
+        }
+        uint64_t U = 0;
+        if (lane == 0 && active && Qk > 0)
+          U = bounded_u64_from(wsys, key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, Qk);
+        U = team_bcast(U, TP, bc_u);
+        const double rQ = 1.0 / static_cast<double>(Qk);
+        auto S_of = [&](uint64_t C) -> int {
+          const uint64_t NC = static_cast<uint64_t>(N) * C;
+          const uint64_t xq = NC > U ? NC - U - 1 : 0;
+          uint64_t qd = static_cast<uint64_t>(floor(static_cast<double>(xq) * rQ));
+          qd = qd * Qk > xq ? qd - 1 : qd;
+          qd = xq - qd * Qk >= Qk ? qd + 1 : qd;
+          const uint64_t sv = qd + 1;
+          return NC <= U ? 0 : (sv < static_cast<uint64_t>(N) ? static_cast<int>(sv) : N);
+        };
+        uint64_t C = incl - tsum;
+        int s_prev = S_of(C);
+        team_sync(TP);
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          C += q[r];
+          const int s_cur = S_of(C);
+          if (active && Qk > 0 && j0 + r < N && s_cur > s_prev) sAt[s_prev] = j0 + r;
+          s_prev = s_cur;
+        }
+        team_sync(TP);
+        int mk[PPT];
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const int v = (j0 + r < N) ? sAt[j0 + r] : -1;
+          mk[r] = r == 0 ? v : (v > mk[r - 1] ? v : mk[r - 1]);
+        }
+        const int before = team_exclusive_max(mk[PPT - 1], TP, bc_i);
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const int j = j0 + r;
+          if (active && j < N) sAt[j] = Qk > 0 ? (mk[r] > before ? mk[r] : before) : j;
+        }
+        team_sync(TP);
+        if (active) {
+#pragma unroll
+          for (int r = 0; r < NZ; ++r) {
+            const int w = r * TP + lane;
+            const int j = w / DX, d = w - j * DX;
+            if (j < N) res[par * res_words + static_cast<int64_t>(li) * N * DX + w] = sxt[sAt[j] * DX + d];
+          }
+        }
+        team_sync(TP);
+      }
+    }
+  };
+
+  // ================= control wave =================
+  unsigned epoch = 0;
+  int up_top = 0;
+  auto build_upper_to = [&](int par, int level) {
+    if (up_top < lc + 1) {
+      for (int b = lane64; b < G; b += 64) up[b] = get(a.tree[par] + tree_off(m, lc + 1) + b);
+      wsync();
+      up_top = lc + 1;
+    }
+    for (; up_top < level; ++up_top) {
+      const int u = up_top + 1 - (lc + 1);
+      const int cnt = G >> u;
+      const int o_prev = 2 * G - ((2 * G) >> (u - 1)), o = 2 * G - ((2 * G) >> u);
+      for (int i = lane64; i < cnt; i += 64) up[o + i] = pair_mean(up[o_prev + 2 * i], up[o_prev + 2 * i + 1]);
+      wsync();
+    }
+  };
+  auto lt_value = [&](int par, int level, int idx) -> double {
+    if (level <= lc + 1) {
+      const int lo = kbase >> (level - 1);
+      if (idx >= lo && idx < lo + (c >> (level - 1))) return lvp(par)[2 * c - ((2 * c) >> (level - 1)) + (idx - lo)];
+      if (level == lc + 1) return up[idx];
+      return get(a.tree[par] + tree_off(m, level) + idx);
+    }
+    const int u = level - (lc + 1);
+    return up[2 * G - ((2 * G) >> u) + idx];
+  };
+  // this block's part of the island tree of step t (levels 2 .. lc+1 from
+  // the island log-weights), published with the ENF records of levels
+  // rec_from .. lc+1
+  auto publish = [&](int64_t t, int rec_from) {
+    const int par = static_cast<int>(t & 1);
+    double* lv = lvp(par);
+    if (c <= 64) {
+      double v = (lane64 < c) ? lv[lane64] : ninf();
+      for (int l = 2; l <= lc + 1; ++l) {
+        const int cnt = c >> (l - 1);
+        const int o = 2 * c - ((2 * c) >> (l - 1));
+        const double v0 = __shfl(v, (2 * lane64) & 63, 64), v1 = __shfl(v, (2 * lane64 + 1) & 63, 64);
+        const double nv = lane64 < cnt ? pair_mean(v0, v1) : ninf();
+        if (lane64 < cnt) lv[o + lane64] = nv;
+        v = nv;
+      }
+    } else {
+      for (int l = 2; l <= lc + 1; ++l) {
+        const int cnt = c >> (l - 1);
+        const int o_prev = 2 * c - ((2 * c) >> (l - 2)), o = 2 * c - ((2 * c) >> (l - 1));
+        for (int i = lane64; i < cnt; i += 64) lv[o + i] = pair_mean(lv[o_prev + 2 * i], lv[o_prev + 2 * i + 1]);
+        wsync();
+      }
+    }
+    wsync();
+    for (int l = 1; l <= lc + 1; ++l) {
+      const int cnt = c >> (l - 1);
+      const int o = 2 * c - ((2 * c) >> (l - 1));
+      double* dst = a.tree[par] + tree_off(m, l) + (kbase >> (l - 1));
+      for (int i = lane64; i < cnt; i += 64) put(dst + i, lv[o + i]);
+    }
+    for (int l = rec_from; l <= lc + 1; ++l) {
+      const int cnt = c >> (l - 1);
+      const int o = 2 * c - ((2 * c) >> (l - 1));
+      const EnfRec r = wave_reduce_enf(cnt, [&](int i) { return enf_leaf(lv[o + i]); });
+      if (lane64 == 0) {
+        double* pl = a.part[par] + static_cast<int64_t>(l - 1) * 3 * G;
+        put(pl + bid, r.E);
+        put(pl + G + bid, r.a);
+        put(pl + 2 * G + bid, r.b);
+      }
+    }
+  };
+  // the ENF record of this block's island log-weights alone (level 1)
+  auto publish_level1 = [&](int64_t t) {
+    const int par = static_cast<int>(t & 1);
+    const double* lv = lvp(par);
+    const EnfRec r = wave_reduce_enf(c, [&](int i) { return enf_leaf(lv[i]); });
+    if (lane64 == 0) {
+      double* pl = a.part[par];
+      put(pl + bid, r.E);
+      put(pl + G + bid, r.a);
+      put(pl + 2 * G + bid, r.b);
+    }
+  };
+  // the flag-array grid barrier of forward_body, taken by this wave alone
+  auto barrier = [&]() -> bool {
+    __builtin_amdgcn_s_waitcnt(0);
+    ++epoch;
+    if (lane64 == 0) put(&a.bar[bid], epoch);
+    int ok = 1;
+    for (int i = lane64; i < G && ok; i += 64) {
+      unsigned spins = 0;
+      while (get(&a.bar[i]) < epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 1023u) == 0 && (spins > (1u << 24) || get(a.status) != 0)) {
+          put(a.status, 1);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    return __all(ok) != 0;
+  };
+  // resampled blocks of step t from LDS to HBM
+  auto write_out = [&](int64_t t) {
+    const int par = static_cast<int>(t & 1);
+    Store* xo_blk = static_cast<Store*>(a.x1[par]) + static_cast<int64_t>(kbase) * N * DX;
+    for (int64_t w = lane64; w < res_words; w += 64) put(xo_blk + w, res[par * res_words + w]);
+  };
+  // Publish step t, wait for the other blocks, decide s*_t and walk; sets
+  // s_ctl[1] when the run ends here (every island dead, or a barrier that
+  // did not complete).  Stage 1 needs only the blocks' level-1 records: they
+  // alone are published first, and the tree and the other levels' records
+  // follow (with a second barrier) only when stage 1 interacts, which every
+  // block decides alike.
+  auto control_step = [&](int64_t t) {
+    if (S == 0) {                                     // one island: no stages
+      if (lane64 == 0) s_ctl[0] = 0;
+      return;
+    }
+    publish_level1(t);
+    if (!barrier()) { s_ctl[1] = 1; return; }
+    const int par = static_cast<int>(t & 1);
+    up_top = 0;
+    int sstar = 0;
+    for (int s = 1; s <= S; ++s) {
+      EnfRec r;
+      if (s <= lc + 1) {
+        const double* ps = a.part[par] + static_cast<int64_t>(s - 1) * 3 * G;
+        r = wave_reduce_enf(G, [&](int i) { return EnfRec{get(ps + i), get(ps + G + i), get(ps + 2 * G + i)}; });
+      } else {
+        build_upper_to(par, s);
+        const double* lvl = up + 2 * G - ((2 * G) >> (s - lc - 1));
+        r = wave_reduce_enf(G >> (s - lc - 1), [&](int i) { return enf_leaf(lvl[i]); });
+      }
+      // the reduction's result is in lanes below its size: take lane 0's
+      r = EnfRec{readlane_f64(r.E, 0), readlane_f64(r.a, 0), readlane_f64(r.b, 0)};
+      if (s == 1 && r.E == ninf()) {                                  // every island dead
+        if (bid == 0 && lane64 == 0) *a.out_logz = ninf();
+        s_ctl[1] = 1;
+        return;
+      }
+      const double blk = static_cast<double>(1 << (s - 1));
+      const double am = (blk * r.a) / static_cast<double>(m), bm = (blk * r.b) / static_cast<double>(m);
+      if (!((am * am) / bm < a.tau)) break;
+      sstar = s;
+      if (s == 1) {
+        write_out(t);
+        publish(t, 2);
+        if (!barrier()) { s_ctl[1] = 1; return; }
+      }
+    }
+    if (sstar > 0) {
+      if (sstar + 1 > lc + 1) build_upper_to(par, sstar + 1);
+      for (int li = lane64; li < c; li += 64) {
+        const int k = kbase + li;
+        int cur = k;
+        for (int s = sstar; s >= 1; --s) {
+          const int pr = cur ^ (1 << (s - 1));
+          const double lc_ = lt_value(par, s, cur >> (s - 1));
+          const double lp_ = lt_value(par, s, pr >> (s - 1));
+          uint32_t w[4];
+          draw4(key, static_cast<uint32_t>(s), static_cast<uint32_t>(cur), static_cast<uint32_t>(t), kTagIsl, 0, w);
+          if (uniform53(w[0], w[1]) < take_partner_prob(lc_, lp_)) cur = pr;
+        }
+        s_src[li] = cur;
+        s_lpre[li] = lt_value(par, sstar + 1, k >> sstar);
+      }
+    }
+    if (lane64 == 0) s_ctl[0] = sstar;
+  };
+
+  // ================= the step loop =================
+  if (ctl && lane64 == 0) { s_ctl[0] = 0; s_ctl[1] = 0; }
+  if (!ctl) run_passes(0, false);
+  __syncthreads();
+  for (int64_t n = 1; n < T; ++n) {
+    if (ctl) control_step(n - 1);
+    else run_passes(n, true);
+    __syncthreads();
+    if (s_ctl[1]) return;
+    if (s_ctl[0] > 0) {
+      // step n again, from the walk's sources
+      if (!ctl) run_passes(n, false);
+      __syncthreads();
+    }
+  }
+
+  // ---- log Zhat: the root of the island tree after the last weighting ----
+  if (!ctl) return;
+  publish(T - 1, lc + 2);
+  if (!barrier()) return;
+  if (bid == 0) {
+    up_top = 0;
+    build_upper_to(static_cast<int>((T - 1) & 1), S + 1);
+    if (lane64 == 0) *a.out_logz = up[2 * G - 2];
+  }
+}
+
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kPipeBlock) void forward_pipe_kernel(FwdArgs a) {
+  forward_pipe_body<Model, Store, PPT>(a, static_cast<int>(blockIdx.x));
+}
+
 template <class Model, typename Store, int PPT, bool Plain>
 __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
   forward_body<Model, Store, PPT, Plain>(a, static_cast<int>(blockIdx.x));
@@ -598,6 +1011,15 @@ inline int ilog2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
 inline bool fwd_is_plain(const FwdArgs& a) {
   return !a.tr_sstar && !a.tr_enf && !a.tr_lpost && !a.tr_anc && !a.tr_pi && !a.tr_digest && !a.tr_lpre && !a.rec_x &&
          !a.rec_anc && !a.ck_x && !a.ck_L && !a.ck_in && a.ck_every == 0 && !a.replay_pi && a.n0 == 0 && a.n1 == a.T;
+}
+
+// the pipelined kernel's conditions: untraced, resampled states resident in
+// LDS, teams inside one wave, and a tau at which stages can but need not
+// interact (speculation pays); AIRPF_PIPELINE=0 switches it off
+inline bool fwd_use_pipe(const FwdArgs& a) {
+  if (!fwd_is_plain(a) || !a.res_lds || a.TP > 64 || a.no_interaction || a.shortcut_all) return false;
+  const char* e = std::getenv("AIRPF_PIPELINE");
+  return !(e && e[0] == '0');
 }
 
 inline size_t fwd_res_bytes(size_t store_bytes, int dx, int c, int N) {
@@ -639,6 +1061,15 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
   plan->ppt = PPT; plan->tp = TP; plan->G = G; plan->c = a.c; plan->smem = smem;
   if (L.plan_only) return hipSuccess;
   void* args[] = {&a};
+  if (fwd_use_pipe(a)) {
+    // the pipelined kernel, when its five-wave blocks are co-resident at this G
+    auto pk = forward_pipe_kernel<Model, Store, PPT>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pk, kPipeBlock, smem) == hipSuccess &&
+        static_cast<long>(per_cu) * L.num_cus >= G)
+      return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(pk), dim3(G), dim3(kPipeBlock), args,
+                                        static_cast<unsigned>(smem), L.stream);
+  }
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(G), dim3(kBlock), args,
                                     static_cast<unsigned>(smem), L.stream);
 }

@@ -220,6 +220,12 @@ def test_untraced_run_without_interactions(ctx, orc, model, m, N, T, tau, f64, d
     ("lg1", 64, 64, 200, 0.9, True, None),         # frequent interactions
     ("lgd", 256, 32, 60, 0.5, False, 4),
     ("sv", 512, 37, 80, 0.6, False, None),         # ragged N
+    ("lg1", 1, 64, 40, 0.7, True, None),           # one island: no stages
+    ("sv", 2048, 64, 1, 0.3, False, None),         # a single observation
+    ("lg1", 256, 256, 2, 0.9, False, None),        # two observations
+    ("lg1", 1024, 64, 200, 0.97, False, None),     # stages reaching across blocks on many steps
+    ("sv", 16384, 16, 60, 0.8, False, None),       # 64 islands per block
+    ("lg1", 65536, 4, 30, 0.6, False, None),       # 256 islands per block
 ])
 def test_untraced_run_matches_traced(ctx, orc, model, m, N, T, tau, f64, dx):
     """An untraced run may take each step's passes before the step's
