@@ -884,6 +884,45 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     }
     return __all(ok) != 0;
   };
+  // the same barrier, and the level-1 records of step `par` joined as
+  // wave_reduce_enf(G, ...) joins them: each lane loads the records of its
+  // blocks as soon as their flags show this epoch, while it still waits for
+  // the others
+  auto barrier_level1 = [&](int par, EnfRec& out) -> bool {
+    __builtin_amdgcn_s_waitcnt(0);
+    ++epoch;
+    if (lane64 == 0) put(&a.bar[bid], epoch);
+    const double* ps = a.part[par];
+    const int per = G > 64 ? (G >> 6) : 1;                     // blocks per lane: 4, 2 or 1
+    const int i0 = G > 64 ? lane64 * per : lane64;
+    const int cnt = G > 64 ? per : (lane64 < G ? 1 : 0);
+    EnfRec rec[4] = {{ninf(), 0.0, 0.0}, {ninf(), 0.0, 0.0}, {ninf(), 0.0, 0.0}, {ninf(), 0.0, 0.0}};
+    const unsigned all = (1u << cnt) - 1u;
+    unsigned got = 0;
+    unsigned spins = 0;
+    int ok = 1;
+    while (got != all) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j < cnt && !(got & (1u << j)) && get(&a.bar[i0 + j]) >= epoch) {
+          rec[j] = EnfRec{get(ps + i0 + j), get(ps + G + i0 + j), get(ps + 2 * G + i0 + j)};
+          got |= 1u << j;
+        }
+      }
+      if (got == all) break;
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 1023u) == 0 && (spins > (1u << 24) || get(a.status) != 0)) {
+        put(a.status, 1);
+        ok = 0;
+        break;
+      }
+    }
+    EnfRec r = per == 4 ? enf_join(enf_join(rec[0], rec[1]), enf_join(rec[2], rec[3]))
+                        : (per == 2 ? enf_join(rec[0], rec[1]) : rec[0]);
+    r = wave_butterfly_enf(r, G);
+    out = EnfRec{readlane_f64(r.E, 0), readlane_f64(r.a, 0), readlane_f64(r.b, 0)};
+    return __all(ok) != 0;
+  };
   // resampled blocks of step t from LDS to HBM
   auto write_out = [&](int64_t t) {
     const int par = static_cast<int>(t & 1);
@@ -902,13 +941,16 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       return;
     }
     publish_level1(t);
-    if (!barrier()) { s_ctl[1] = 1; return; }
     const int par = static_cast<int>(t & 1);
+    EnfRec r1;
+    if (!barrier_level1(par, r1)) { s_ctl[1] = 1; return; }
     up_top = 0;
     int sstar = 0;
     for (int s = 1; s <= S; ++s) {
       EnfRec r;
-      if (s <= lc + 1) {
+      if (s == 1) {
+        r = r1;
+      } else if (s <= lc + 1) {
         const double* ps = a.part[par] + static_cast<int64_t>(s - 1) * 3 * G;
         r = wave_reduce_enf(G, [&](int i) { return EnfRec{get(ps + i), get(ps + G + i), get(ps + 2 * G + i)}; });
       } else {
