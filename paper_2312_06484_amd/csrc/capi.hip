@@ -33,9 +33,9 @@ struct DevBuf {
 };
 
 bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
-// at most 256 blocks of at most 256 islands each per problem
+// at most 1024 blocks of at most 256 islands each per problem
 constexpr int kMaxIslands = 65536;
-constexpr int kMaxBlocks = 256;
+constexpr int kMaxBlocks = 1024;
 int ilog2(int64_t v) { int s = 0; while ((int64_t(1) << s) < v) ++s; return s; }
 bool all_finite(const double* p, int64_t n) {
   for (int64_t i = 0; i < n; ++i) if (!std::isfinite(p[i])) return false;
@@ -193,6 +193,9 @@ struct Prepared {
   airpf::FwdPlan plan;
   airpf_options opt;
   int dx = 1, dy = 1, S = 0;
+  // bound of the block count of any launch of this problem (the kernel
+  // variant a launch takes, and so its G, may differ from the plan's)
+  int gmax = 1;
 };
 
 airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* theta, int32_t d_theta,
@@ -241,17 +244,19 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
 
   const size_t store = L.fp64 ? 8 : 4;
   const size_t nstate = size_t(m) * N * P->dx * store;
-  const int lc = ilog2(P->plan.c);
+  P->gmax = std::min(max_blocks, m);
+  // ENF records: (log2(m/G) + 1) levels of G blocks, largest at G = gmax
+  const size_t part_words = 3 * size_t(ilog2(m / P->gmax) + 1) * size_t(P->gmax);
   for (int p = 0; p < 2; ++p) {
     ST_OK(ctx->x1[p].ensure(nstate));
     ST_OK(ctx->tree[p].ensure(sizeof(double) * 2 * size_t(m)));
-    ST_OK(ctx->part[p].ensure(sizeof(double) * 3 * size_t(lc + 1) * P->plan.G));
+    ST_OK(ctx->part[p].ensure(sizeof(double) * part_words));
     a.x1[p] = ctx->x1[p].p;
     a.tree[p] = static_cast<double*>(ctx->tree[p].p);
     a.part[p] = static_cast<double*>(ctx->part[p].p);
   }
   // misc: [0,8) log Zhat, [8,12) status, [64, 64 + 4G) barrier flags
-  ST_OK(ctx->misc.ensure(64 + 4 * size_t(P->plan.G)));
+  ST_OK(ctx->misc.ensure(64 + 4 * size_t(P->gmax)));
   unsigned char* misc = static_cast<unsigned char*>(ctx->misc.p);
   a.out_logz = reinterpret_cast<double*>(misc);
   a.status = reinterpret_cast<int*>(misc + 8);
@@ -263,13 +268,13 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
     HIP_OK(hipMemcpyAsync(ctx->ybuf.p, y, sizeof(double) * size_t(T) * P->dy, hipMemcpyHostToDevice, s));
     a.y = static_cast<const double*>(ctx->ybuf.p);
   }
-  HIP_OK(airpf::fill_u32(misc, 0u, 16 + int64_t(P->plan.G), s));
+  HIP_OK(airpf::fill_u32(misc, 0u, 16 + int64_t(P->gmax), s));
   return AIRPF_OK;
 }
 
 // zero the barrier flags before a cooperative launch
 airpf_status reset_flags(airpf_ctx* ctx, const Prepared& P) {
-  HIP_OK(airpf::fill_u32(P.a.bar, 0u, P.plan.G, ctx->stream));
+  HIP_OK(airpf::fill_u32(P.a.bar, 0u, P.gmax, ctx->stream));
   return AIRPF_OK;
 }
 

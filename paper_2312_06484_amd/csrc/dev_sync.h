@@ -344,7 +344,7 @@ __device__ __forceinline__ EnfRec enf_join(const EnfRec& x, const EnfRec& y) {
                 __builtin_ldexp(x.b, 2 * dx) + __builtin_ldexp(y.b, 2 * dy)};
 }
 
-// One wave reduces n <= 256 ENF records (n a power of two) by the
+// One wave reduces n <= 1024 ENF records (n a power of two) by the
 // adjacent-pair tree: lane l first joins its aligned run of n/64 records,
 // then lanes join in a butterfly over groups of 2, 4, ..., min(n, 64).  The
 // join is commutative bit for bit and a lane's partner holds exactly the
@@ -376,10 +376,28 @@ __device__ __forceinline__ EnfRec wave_reduce_enf(int n, F rec) {
   EnfRec r{ninf(), 0.0, 0.0};
   if (n <= 64) {
     if (lane < n) r = rec(lane);
-  } else if (n == 128) {
-    r = enf_join(rec(2 * lane), rec(2 * lane + 1));
   } else {
-    r = enf_join(enf_join(rec(4 * lane), rec(4 * lane + 1)), enf_join(rec(4 * lane + 2), rec(4 * lane + 3)));
+    // the lane's run of per = n/64 records (2 to 16) by the adjacent-pair
+    // tree, kept as a binary counter: after record j, the partial of the
+    // aligned group of 2^t records ending at j is complete for every t with
+    // bit t of j + 1 clear below it
+    const int per = n >> 6;
+    EnfRec s1{ninf(), 0.0, 0.0}, s2 = s1, s4 = s1, s8 = s1, s16 = s1;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j < per) {
+        EnfRec x = rec(per * lane + j);
+        if ((j & 1) == 0) { s1 = x; continue; }
+        x = enf_join(s1, x);
+        if ((j & 2) == 0) { s2 = x; continue; }
+        x = enf_join(s2, x);
+        if ((j & 4) == 0) { s4 = x; continue; }
+        x = enf_join(s4, x);
+        if ((j & 8) == 0) { s8 = x; continue; }
+        s16 = enf_join(s8, x);
+      }
+    }
+    r = per == 2 ? s2 : (per == 4 ? s4 : (per == 8 ? s8 : s16));
   }
   return wave_butterfly_enf(r, n);
 }

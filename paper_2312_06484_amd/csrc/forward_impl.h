@@ -1055,11 +1055,12 @@ inline bool fwd_is_plain(const FwdArgs& a) {
          !a.rec_anc && !a.ck_x && !a.ck_L && !a.ck_in && a.ck_every == 0 && !a.replay_pi && a.n0 == 0 && a.n1 == a.T;
 }
 
-// the pipelined kernel's conditions: untraced, resampled states resident in
-// LDS, teams inside one wave, and a tau at which stages can but need not
-// interact (speculation pays); AIRPF_PIPELINE=0 switches it off
-inline bool fwd_use_pipe(const FwdArgs& a) {
-  if (!fwd_is_plain(a) || !a.res_lds || a.TP > 64 || a.no_interaction || a.shortcut_all) return false;
+// the pipelined kernel's conditions (besides resampled states resident in
+// LDS at its tiling): untraced, teams inside one wave, and a tau at which
+// stages can but need not interact (speculation pays); AIRPF_PIPELINE=0
+// switches it off
+inline bool fwd_pipe_candidate(const FwdArgs& a, int TP) {
+  if (!fwd_is_plain(a) || TP > 64 || a.no_interaction || a.shortcut_all) return false;
   const char* e = std::getenv("AIRPF_PIPELINE");
   return !(e && e[0] == '0');
 }
@@ -1074,46 +1075,62 @@ inline size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) 
   return sx + 4 * size_t(kBlock) * ppt + 8 * 4 * size_t(c) + 8 * 2 * size_t(G);
 }
 
+// The largest power-of-two block count G <= min(m / tpb, cap) whose blocks
+// (threads each, LDS by smem_of(G)) are all co-resident; 0 if none.
+template <class SmemOf>
+static int fit_blocks(const void* kern, int threads, const FwdLaunch& L, int m, int tpb, int cap, SmemOf smem_of,
+                      size_t* smem_out) {
+  int G = m / tpb;
+  if (G < 1) G = 1;
+  if (G > cap) G = cap;
+  G = 1 << ilog2i(G + 1) >> 1;                  // power of two <= G
+  for (; G >= 1; G >>= 1) {
+    const size_t smem = smem_of(G);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, smem) != hipSuccess) return 0;
+    if (static_cast<long>(per_cu) * L.num_cus >= G) { *smem_out = smem; return G; }
+  }
+  return 0;
+}
+
 template <class Model, typename Store, int PPT>
 static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
-  auto kern = fwd_is_plain(a) ? forward_kernel<Model, Store, PPT, true> : forward_kernel<Model, Store, PPT, false>;
   const int TP = pow2_ceil((a.N + PPT - 1) / PPT);
   const int tpb = kBlock / TP;
-  int G = a.m / tpb;
-  if (G < 1) G = 1;
-  if (G > L.max_blocks) G = L.max_blocks;
-  G = 1 << ilog2i(G + 1) >> 1;                  // power of two <= G
-  if (G < 1) G = 1;
-  size_t smem = 0;
-  for (; G >= 1; G >>= 1) {
+  auto smem_of = [&](int G) {
     const int c = a.m / G;
-    smem = fwd_smem_bytes(sizeof(Store), PPT, Model::DX, c, G) + fwd_res_bytes(sizeof(Store), Model::DX, c, a.N);
-    int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, smem);
-    if (e != hipSuccess) return e;
-    if (static_cast<long>(per_cu) * L.num_cus >= G) break;
+    return fwd_smem_bytes(sizeof(Store), PPT, Model::DX, c, G) + fwd_res_bytes(sizeof(Store), Model::DX, c, a.N);
+  };
+  auto set_plan = [&](int G, size_t smem) {
+    a.TP = TP;
+    a.G = G;
+    a.c = a.m / G;
+    a.lc = ilog2i(a.c);
+    a.res_lds = fwd_res_bytes(sizeof(Store), Model::DX, a.c, a.N) > 0;
+    plan->ppt = PPT; plan->tp = TP; plan->G = G; plan->c = a.c; plan->smem = smem;
+  };
+  void* args[] = {&a};
+  size_t smem = 0;
+  // the pipelined kernel: one five-wave block per CU at most, G <= 256 (its
+  // level-1 record wait reads at most four blocks per lane), and the
+  // resampled states resident in LDS
+  if (fwd_pipe_candidate(a, TP)) {
+    const void* pk = reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT>);
+    const int G = fit_blocks(pk, kPipeBlock, L, a.m, tpb, L.max_blocks < 256 ? L.max_blocks : 256, smem_of, &smem);
+    if (G >= 1 && a.m / G <= kMaxIslandsPerBlock && fwd_res_bytes(sizeof(Store), Model::DX, a.m / G, a.N) > 0) {
+      set_plan(G, smem);
+      if (L.plan_only) return hipSuccess;
+      return hipLaunchCooperativeKernel(pk, dim3(G), dim3(kPipeBlock), args, static_cast<unsigned>(smem), L.stream);
+    }
   }
+  const void* kern = fwd_is_plain(a) ? reinterpret_cast<const void*>(forward_kernel<Model, Store, PPT, true>)
+                                     : reinterpret_cast<const void*>(forward_kernel<Model, Store, PPT, false>);
+  const int G = fit_blocks(kern, kBlock, L, a.m, tpb, L.max_blocks, smem_of, &smem);
   if (G < 1) return hipErrorCooperativeLaunchTooLarge;
   if (a.m / G > kMaxIslandsPerBlock) return hipErrorInvalidValue;     // islands per block are bounded by the LDS plan
-  a.TP = TP;
-  a.G = G;
-  a.c = a.m / G;
-  a.lc = ilog2i(a.c);
-  a.res_lds = fwd_res_bytes(sizeof(Store), Model::DX, a.c, a.N) > 0;
-  plan->ppt = PPT; plan->tp = TP; plan->G = G; plan->c = a.c; plan->smem = smem;
+  set_plan(G, smem);
   if (L.plan_only) return hipSuccess;
-  void* args[] = {&a};
-  if (fwd_use_pipe(a)) {
-    // the pipelined kernel, when its five-wave blocks are co-resident at this G
-    auto pk = forward_pipe_kernel<Model, Store, PPT>;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pk, kPipeBlock, smem) == hipSuccess &&
-        static_cast<long>(per_cu) * L.num_cus >= G)
-      return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(pk), dim3(G), dim3(kPipeBlock), args,
-                                        static_cast<unsigned>(smem), L.stream);
-  }
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(G), dim3(kBlock), args,
-                                    static_cast<unsigned>(smem), L.stream);
+  return hipLaunchCooperativeKernel(kern, dim3(G), dim3(kBlock), args, static_cast<unsigned>(smem), L.stream);
 }
 
 // particles per lane: the smallest PPT with PPT*DX a multiple of four (a lane

@@ -226,6 +226,7 @@ def test_untraced_run_without_interactions(ctx, orc, model, m, N, T, tau, f64, d
     ("lg1", 1024, 64, 200, 0.97, False, None),     # stages reaching across blocks on many steps
     ("sv", 16384, 16, 60, 0.8, False, None),       # 64 islands per block
     ("lg1", 65536, 4, 30, 0.6, False, None),       # 256 islands per block
+    ("lgd", 2048, 64, 20, 0.5, False, 8),          # untraced serial kernel on more than 256 blocks
 ])
 def test_untraced_run_matches_traced(ctx, orc, model, m, N, T, tau, f64, dx):
     """An untraced run may take each step's passes before the step's

@@ -39,7 +39,8 @@ def _with_cap(cap, fn):
             os.environ["AIRPF_MAX_BLOCKS"] = old
 
 
-@pytest.mark.parametrize("kind,m,N,T,tau", [(0, 256, 64, 30, 0.6), (1, 1024, 32, 20, 0.95), (1, 64, 256, 25, 2.0)])
+@pytest.mark.parametrize("kind,m,N,T,tau", [(0, 256, 64, 30, 0.6), (1, 1024, 32, 20, 0.95), (1, 64, 256, 25, 2.0),
+                                            (0, 4096, 256, 12, 0.6)])   # more than 256 blocks uncapped
 def test_forward_tiling_invariant(ctx, kind, m, N, T, tau):
     from paper_2312_06484_amd import airpf
     y = W.lg1_data(T) if kind == 0 else W.sv_data(T)
