@@ -592,9 +592,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 // identical.
 //
 // Stage 1 needs only the blocks' level-1 ENF records, so the control wave
-// publishes those alone and synchronises; the island tree and the other
-// levels' records follow (with a second barrier) only when stage 1
-// interacts, which every block decides alike.  Only then can another block
+// publishes those alone (in a ring where a record is also the block's
+// arrival); the island tree and the other levels' records follow (with a
+// flag barrier) only when stage 1 interacts, which every block decides
+// alike.  Only then can another block
 // read this block's resampled states of that step (in the rerun of the next
 // step), so they are copied from LDS to HBM at that point, not by the
 // passes: a step whose stage 1 does not interact moves no state through
@@ -853,18 +854,6 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       }
     }
   };
-  // the ENF record of this block's island log-weights alone (level 1)
-  auto publish_level1 = [&](int64_t t) {
-    const int par = static_cast<int>(t & 1);
-    const double* lv = lvp(par);
-    const EnfRec r = wave_reduce_enf(c, [&](int i) { return enf_leaf(lv[i]); });
-    if (lane64 == 0) {
-      double* pl = a.part[par];
-      put(pl + bid, r.E);
-      put(pl + G + bid, r.a);
-      put(pl + 2 * G + bid, r.b);
-    }
-  };
   // the flag-array grid barrier of forward_body, taken by this wave alone
   auto barrier = [&]() -> bool {
     __builtin_amdgcn_s_waitcnt(0);
@@ -884,15 +873,27 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     }
     return __all(ok) != 0;
   };
-  // the same barrier, and the level-1 records of step `par` joined as
-  // wave_reduce_enf(G, ...) joins them: each lane loads the records of its
-  // blocks as soon as their flags show this epoch, while it still waits for
-  // the others
-  auto barrier_level1 = [&](int par, EnfRec& out) -> bool {
+  // Stage 1 of step t: this block's level-1 ENF record goes to slot t mod 3
+  // of a ring whose words are NaN until written; each lane waits until the
+  // records of its blocks (those wave_reduce_enf(G, ...) assigns it) are
+  // complete, and they are joined as wave_reduce_enf joins them.  A record
+  // is the block's arrival: no flag, and no wait for the record's own
+  // stores.  Once every block's record of step t is here, every block has
+  // read those of step t-1, so this block clears its slot of step t-1
+  // (reused at step t+2); that clearing completes before the block's next
+  // record is stored (the s_waitcnt below), so a block that sees that
+  // record sees the cleared slot.
+  auto level1 = [&](int64_t t, EnfRec& out) -> bool {
+    const int slot = static_cast<int>(t % 3), prev = static_cast<int>((t + 2) % 3);
+    const double* lv = lvp(static_cast<int>(t & 1));
+    const EnfRec mine = wave_reduce_enf(c, [&](int i) { return enf_leaf(lv[i]); });
+    double* rs = a.ring + static_cast<int64_t>(slot) * 3 * G;
     __builtin_amdgcn_s_waitcnt(0);
-    ++epoch;
-    if (lane64 == 0) put(&a.bar[bid], epoch);
-    const double* ps = a.part[par];
+    if (lane64 == 0) {
+      put(rs + bid, mine.E);
+      put(rs + G + bid, mine.a);
+      put(rs + 2 * G + bid, mine.b);
+    }
     const int per = G > 64 ? (G >> 6) : 1;                     // blocks per lane: 4, 2 or 1
     const int i0 = G > 64 ? lane64 * per : lane64;
     const int cnt = G > 64 ? per : (lane64 < G ? 1 : 0);
@@ -904,9 +905,12 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     while (got != all) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (j < cnt && !(got & (1u << j)) && get(&a.bar[i0 + j]) >= epoch) {
-          rec[j] = EnfRec{get(ps + i0 + j), get(ps + G + i0 + j), get(ps + 2 * G + i0 + j)};
-          got |= 1u << j;
+        if (j < cnt && !(got & (1u << j))) {
+          const double e = get(rs + i0 + j), va = get(rs + G + i0 + j), vb = get(rs + 2 * G + i0 + j);
+          if (e == e && va == va && vb == vb) {
+            rec[j] = EnfRec{e, va, vb};
+            got |= 1u << j;
+          }
         }
       }
       if (got == all) break;
@@ -921,7 +925,15 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
                         : (per == 2 ? enf_join(rec[0], rec[1]) : rec[0]);
     r = wave_butterfly_enf(r, G);
     out = EnfRec{readlane_f64(r.E, 0), readlane_f64(r.a, 0), readlane_f64(r.b, 0)};
-    return __all(ok) != 0;
+    const bool done = __all(ok) != 0;
+    if (done && lane64 == 0) {
+      double* rp = a.ring + static_cast<int64_t>(prev) * 3 * G;
+      const double nan = __longlong_as_double(static_cast<long long>(~0ull));
+      put(rp + bid, nan);
+      put(rp + G + bid, nan);
+      put(rp + 2 * G + bid, nan);
+    }
+    return done;
   };
   // resampled blocks of step t from LDS to HBM
   auto write_out = [&](int64_t t) {
@@ -940,10 +952,9 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       if (lane64 == 0) s_ctl[0] = 0;
       return;
     }
-    publish_level1(t);
     const int par = static_cast<int>(t & 1);
     EnfRec r1;
-    if (!barrier_level1(par, r1)) { s_ctl[1] = 1; return; }
+    if (!level1(t, r1)) { s_ctl[1] = 1; return; }
     up_top = 0;
     int sstar = 0;
     for (int s = 1; s <= S; ++s) {

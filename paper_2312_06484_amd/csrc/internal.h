@@ -23,6 +23,7 @@ struct FwdArgs {
   double* part[2];            // [(lc+1)*3*G] per level: the blocks' ENF records (E, a, b)
   unsigned* bar;              // [G] grid-barrier flags, zero before the launch
   int* status;                // [1] 0 ok, 1 barrier timed out
+  double* ring;               // pipelined kernel: [3 slots][E, a, b][G] level-1 ENF records, NaN before the launch
   double* out_logz;           // [1]
   int32_t* tr_sstar;
   double* tr_enf;
