@@ -289,7 +289,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
-                     "kernel": "forward_kernel", "kernel_ms": avg_k,
+                     "kernel": ("forward_kernel" if os.environ.get("AIRPF_PIPELINE", "1").startswith("0")
+                                else "forward_pipe_kernel"), "kernel_ms": avg_k,
                      "bytes_per_particle_step": bpp},
         "logz_err": err,
         "cpu_baseline": cpu,
