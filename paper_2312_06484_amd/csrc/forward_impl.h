@@ -602,7 +602,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 // HBM at all.
 constexpr int kPipeBlock = kBlock + 64;
 
-template <class Model, typename Store, int PPT>
+// Rec: the forward run of the score, which also keeps each step's island
+// maps, s*, entering weights, and checkpoints every ck_every steps (no
+// other trace, no replay).
+template <class Model, typename Store, int PPT, bool Rec>
 __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;
@@ -626,6 +629,12 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   const int kbase = bid * c;
   const Key key = make_key(a.seed);
   const int passes = (c + tpb - 1) / tpb;
+  int32_t* const tr_pi = Rec ? a.tr_pi : nullptr;
+  int32_t* const tr_sstar = Rec ? a.tr_sstar : nullptr;
+  double* const tr_lpre = Rec ? a.tr_lpre : nullptr;
+  void* const ck_x = Rec ? a.ck_x : nullptr;
+  double* const ck_L = Rec ? a.ck_L : nullptr;
+  const int64_t ck_every = Rec ? a.ck_every : 0;
 
   Store* sx = reinterpret_cast<Store*>(smem);                                    // [kBlock*NZ]
   int* sA = reinterpret_cast<int*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));   // [kBlock*PPT]
@@ -694,6 +703,23 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
           for (int d = 0; d < DX; ++d) xp[d] = static_cast<double>(xr[r][d]);
           Model::template prop<Store>(a.mp, xp, z + r * DX, x[r]);
         }
+      }
+
+      // ---- what the score keeps: the entering weight, and the state
+      // entering this weighting at checkpoint steps (a step run again
+      // rewrites them) ----
+      if (Rec && active) {
+        if (ck_every > 0 && n % ck_every == 0 && ck_x) {
+          Store* xc = static_cast<Store*>(ck_x) + (n / ck_every) * (static_cast<int64_t>(m) * N * DX) +
+                      static_cast<int64_t>(k) * N * DX;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r)
+#pragma unroll
+            for (int d = 0; d < DX; ++d)
+              if (j0 + r < N) xc[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
+          if (lane == 0) ck_L[(n / ck_every) * m + k] = Lpre;
+        }
+        if (lane == 0 && tr_lpre) tr_lpre[n * m + k] = Lpre;
       }
 
       // ---- weighting ----
@@ -949,7 +975,11 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   // block decides alike.
   auto control_step = [&](int64_t t) {
     if (S == 0) {                                     // one island: no stages
-      if (lane64 == 0) s_ctl[0] = 0;
+      if (lane64 == 0) {
+        s_ctl[0] = 0;
+        if (Rec && tr_sstar) tr_sstar[t] = 0;
+        if (Rec && tr_pi) tr_pi[t * m + kbase] = kbase;
+      }
       return;
     }
     const int par = static_cast<int>(t & 1);
@@ -1001,9 +1031,15 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
         }
         s_src[li] = cur;
         s_lpre[li] = lt_value(par, sstar + 1, k >> sstar);
+        if (Rec && tr_pi) tr_pi[t * m + k] = cur;
       }
+    } else if (Rec && tr_pi) {
+      for (int li = lane64; li < c; li += 64) tr_pi[t * m + kbase + li] = kbase + li;
     }
-    if (lane64 == 0) s_ctl[0] = sstar;
+    if (lane64 == 0) {
+      s_ctl[0] = sstar;
+      if (Rec && tr_sstar) tr_sstar[t] = sstar;
+    }
   };
 
   // ================= the step loop =================
@@ -1029,13 +1065,16 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   if (bid == 0) {
     up_top = 0;
     build_upper_to(static_cast<int>((T - 1) & 1), S + 1);
-    if (lane64 == 0) *a.out_logz = up[2 * G - 2];
+    if (lane64 == 0) {
+      *a.out_logz = up[2 * G - 2];
+      if (Rec && tr_sstar) tr_sstar[T - 1] = 0;
+    }
   }
 }
 
-template <class Model, typename Store, int PPT>
+template <class Model, typename Store, int PPT, bool Rec>
 __global__ __launch_bounds__(kPipeBlock) void forward_pipe_kernel(FwdArgs a) {
-  forward_pipe_body<Model, Store, PPT>(a, static_cast<int>(blockIdx.x));
+  forward_pipe_body<Model, Store, PPT, Rec>(a, static_cast<int>(blockIdx.x));
 }
 
 template <class Model, typename Store, int PPT, bool Plain>
@@ -1070,8 +1109,15 @@ inline bool fwd_is_plain(const FwdArgs& a) {
 // LDS at its tiling): untraced, teams inside one wave, and a tau at which
 // stages can but need not interact (speculation pays); AIRPF_PIPELINE=0
 // switches it off
+// the score's forward: island maps, s*, entering weights and checkpoints
+// kept, nothing else traced or replayed
+inline bool fwd_is_score_forward(const FwdArgs& a) {
+  return !a.tr_enf && !a.tr_lpost && !a.tr_anc && !a.tr_digest && !a.rec_x && !a.rec_anc && !a.ck_in &&
+         !a.replay_pi && a.n0 == 0 && a.n1 == a.T;
+}
+
 inline bool fwd_pipe_candidate(const FwdArgs& a, int TP) {
-  if (!fwd_is_plain(a) || TP > 64 || a.no_interaction || a.shortcut_all) return false;
+  if (!(fwd_is_plain(a) || fwd_is_score_forward(a)) || TP > 64 || a.no_interaction || a.shortcut_all) return false;
   const char* e = std::getenv("AIRPF_PIPELINE");
   return !(e && e[0] == '0');
 }
@@ -1126,7 +1172,8 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
   // level-1 record wait reads at most four blocks per lane), and the
   // resampled states resident in LDS
   if (fwd_pipe_candidate(a, TP)) {
-    const void* pk = reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT>);
+    const void* pk = fwd_is_plain(a) ? reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false>)
+                                     : reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, true>);
     const int G = fit_blocks(pk, kPipeBlock, L, a.m, tpb, L.max_blocks < 256 ? L.max_blocks : 256, smem_of, &smem);
     if (G >= 1 && a.m / G <= kMaxIslandsPerBlock && fwd_res_bytes(sizeof(Store), Model::DX, a.m / G, a.N) > 0) {
       set_plan(G, smem);
