@@ -436,9 +436,19 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
     HIP_OK(hipMemcpyAsync(keep_pi, a.tr_pi, 4 * size_t(T - 1) * m, hipMemcpyDeviceToDevice, s));
   if (keep_sstar) HIP_OK(hipMemcpyAsync(keep_sstar, a.tr_sstar, 4 * size_t(T), hipMemcpyDeviceToDevice, s));
 
-  // reverse, one segment at a time
-  b.mp = a.mp; b.y = a.y; b.T = T; b.m = m; b.N = N; b.S = P.S; b.c = P.plan.c; b.lc = ilog2(P.plan.c);
-  b.G = P.plan.G; b.dy = P.dy; b.seed = seed;
+  // reverse, one segment at a time, tiled as the serial forward kernel would
+  // be (the pipelined forward's tiling stops at 256 blocks; the reverse
+  // kernel's own co-residency bounds both): results do not depend on it
+  airpf::FwdPlan bplan;
+  {
+    airpf::FwdLaunch Lp = P.L;
+    Lp.plan_only = 1;
+    airpf::FwdArgs q = a;
+    q.replay_pi = 1;
+    if (airpf::launch_forward(Lp, q, &bplan) != hipSuccess) return AIRPF_E_DEVICE;
+  }
+  b.mp = a.mp; b.y = a.y; b.T = T; b.m = m; b.N = N; b.S = P.S; b.c = bplan.c; b.lc = ilog2(bplan.c);
+  b.G = bplan.G; b.dy = P.dy; b.seed = seed;
   b.log_mN = std::log(static_cast<double>(m) * static_cast<double>(N));
   b.c_log = a.cst_q + 40.0 * std::log(2.0) + std::log(static_cast<double>(N));
   b.logz = a.out_logz;
