@@ -39,6 +39,7 @@ __device__ __forceinline__ double round_store(double v) {
 
 struct LG1 {
   static constexpr int DX = 1;
+  static constexpr bool kThetaOuter = false;   // see LGD
   template <typename Store>
   __device__ static void init(const ModelArgs&, const double* z, double* x) { x[0] = round_store<Store>(z[0]); }
   template <typename Store>
@@ -69,6 +70,7 @@ struct LG1 {
 
 struct SV {
   static constexpr int DX = 1;
+  static constexpr bool kThetaOuter = false;   // see LGD
   template <typename Store>
   __device__ static void init(const ModelArgs& p, const double* z, double* x) {
     x[0] = round_store<Store>(fma(p.s0, z[0], p.th[0]));
@@ -129,6 +131,11 @@ struct LGD {
     }
     return -(ss * p.hr);
   }
+  // theta = A: the transition's theta-tangent contracted with the child's
+  // adjoint is lam xp^T (an outer product), and g and x_0 do not depend on
+  // theta, so a step's contribution of a slot is (sum over its children of
+  // lam) xp^T, formed once per slot instead of once per child
+  static constexpr bool kThetaOuter = true;
   static constexpr int P = D * D;
   __device__ static void dlogpot_dx(const ModelArgs& p, const double* x, const double* y, double* g) {
     const double inv_r = 2.0 * p.hr;

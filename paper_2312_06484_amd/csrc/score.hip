@@ -69,6 +69,58 @@ __device__ __forceinline__ double wave_reduce_scatter64(double (&acc)[64]) {
   return acc[0];
 }
 
+// The same reduce-scatter of acc[8i + c] = sum_r u[r][i] v[r][c] (64 entries,
+// an 8 x 8 outer product summed over the lane's slots), with the first
+// level's values formed as they are exchanged: only the 32 entries a lane
+// keeps are ever held at once.
+template <int PPT>
+__device__ __forceinline__ double wave_reduce_scatter64_outer(const double (&u)[PPT][9], const double (&v)[PPT][8]) {
+  const int l = threadIdx.x & 63;
+  const bool h = (l & 32) != 0;
+  double acc[64];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    double lo = 0.0, hi = 0.0;
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      lo += u[r][i >> 3] * v[r][i & 7];
+      hi += u[r][(i + 32) >> 3] * v[r][(i + 32) & 7];
+    }
+    const double send = h ? lo : hi, keep = h ? hi : lo;
+    acc[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const bool g = (l & 16) != 0;
+    const double send = g ? acc[i] : acc[i + 16], keep = g ? acc[i + 16] : acc[i];
+    acc[i] = keep + __shfl_xor(send, 16, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const bool g = (l & 8) != 0;
+    const double send = g ? acc[i] : acc[i + 8], keep = g ? acc[i + 8] : acc[i];
+    acc[i] = keep + dppd<0x128>(send);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const bool g = (l & 4) != 0;
+    const double send = g ? acc[i] : acc[i + 4], keep = g ? acc[i + 4] : acc[i];
+    acc[i] = keep + __shfl_xor(send, 4, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const bool g = (l & 2) != 0;
+    const double send = g ? acc[i] : acc[i + 2], keep = g ? acc[i + 2] : acc[i];
+    acc[i] = keep + dppd<0x4E>(send);
+  }
+  {
+    const bool g = (l & 1) != 0;
+    const double send = g ? acc[0] : acc[1], keep = g ? acc[1] : acc[0];
+    acc[0] = keep + dppd<0xB1>(send);
+  }
+  return acc[0];
+}
+
 template <class Model, typename Store, int PPT>
 __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
@@ -162,6 +214,15 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
 #pragma unroll
         for (int d = 0; d < DX; ++d) lam[r][d] = 0.0;
       }
+      double sl[PPT][NV];                        // per slot: sum over children of (lam, D)
+      double xp[PPT][DX];                        // parent value of each slot: x_n[k][a(j)]
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sl[r][v] = 0.0;
+#pragma unroll
+        for (int d = 0; d < DX; ++d) xp[r][d] = 0.0;
+      }
 
       if (last) {
         // final normalised weights: Wbar = exp(Lpre_k + log g - log(m N) - log Zhat)
@@ -176,12 +237,6 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
         for (int r = 0; r < PPT; ++r) sAt[j0 + r] = (active && j0 + r < N) ? static_cast<int>(an[j0 + r]) : 0x7fffffff;
         team_sync(TP);
 
-        double sl[PPT][NV];                      // per slot: sum over children of (lam, D)
-#pragma unroll
-        for (int r = 0; r < PPT; ++r)
-#pragma unroll
-          for (int v = 0; v < NV; ++v) sl[r][v] = 0.0;
-        double xp[PPT][DX];                      // parent value of each slot: x_n[k][a(j)]
 #pragma unroll
         for (int r = 0; r < PPT; ++r)
 #pragma unroll
@@ -224,7 +279,7 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
                   sl[r][d] += lc[d];
                 }
                 sl[r][DX] += static_cast<double>(get(del_in + static_cast<int64_t>(child) * N + j));
-                Model::prop_vjp_theta(a.mp, xp[r], z + r * DX, lc, acc);
+                if constexpr (!Model::kThetaOuter) Model::prop_vjp_theta(a.mp, xp[r], z + r * DX, lc, acc);
               }
             }
           }
@@ -313,11 +368,28 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
       // the island's gradient contribution, summed over its lanes in a fixed
       // pattern and added to the island's own accumulator (in step order)
       bool summed = false;
-      if constexpr (P == 64) {
+      if constexpr (Model::kThetaOuter && P == 64 && DX == 8) {
+        if (TP == 64) {
+          const double v = wave_reduce_scatter64_outer<PPT>(sl, xp);
+          if (active) a.gisl[static_cast<int64_t>(k) * P + (tid & 63)] += v;
+          summed = true;
+        }
+      } else if constexpr (P == 64) {
         if (TP == 64) {
           const double v = wave_reduce_scatter64(acc);
           if (active) a.gisl[static_cast<int64_t>(k) * P + (tid & 63)] += v;
           summed = true;
+        }
+      }
+      if constexpr (Model::kThetaOuter) {
+        // the outer products of the slots, where the fused path above did not run
+        if (!summed) {
+#pragma unroll
+          for (int r = 0; r < PPT; ++r)
+#pragma unroll
+            for (int i = 0; i < DX; ++i)
+#pragma unroll
+              for (int c2 = 0; c2 < DX; ++c2) acc[i * DX + c2] += sl[r][i] * xp[r][c2];
         }
       }
       if (!summed) {
@@ -337,10 +409,18 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(BwdArgs a) {
   backward_body<Model, Store, PPT>(a, static_cast<int>(blockIdx.x));
 }
 
-// three waves per SIMD for the batch (VGPRs capped at 168, a few spilled): the
-// reverse pass of many problems is limited by latency, not by registers
+// three waves per SIMD for the batch of models with a state of one, two or
+// four dimensions (VGPRs capped at 168, at most a few spilled): the reverse
+// pass of many problems is limited by latency, not by registers.  The others
+// take two (the cap spilled dozens to hundreds of registers to scratch for
+// d_x = 3 and 8).
 template <class Model, typename Store, int PPT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void backward_batch_kernel(const BwdArgs* probs, const int2* bmap) {
+  const int2 pb = bmap[blockIdx.x];
+  backward_body<Model, Store, PPT>(probs[pb.x], pb.y);
+}
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void backward_batch_kernel_wide(const BwdArgs* probs, const int2* bmap) {
   const int2 pb = bmap[blockIdx.x];
   backward_body<Model, Store, PPT>(probs[pb.x], pb.y);
 }
@@ -443,7 +523,9 @@ size_t backward_smem(int fp64, int ppt, int dx) { return bwd_smem_bytes(fp64 ? 8
 
 template <class Model, typename Store, int PPT>
 static hipError_t batch_bwd_t(const BatchLaunch& L, int* cap) {
-  auto kern = backward_batch_kernel<Model, Store, PPT>;
+  const void* kern;
+  if constexpr (Model::DX <= 2 || Model::DX == 4) kern = reinterpret_cast<const void*>(backward_batch_kernel<Model, Store, PPT>);
+  else kern = reinterpret_cast<const void*>(backward_batch_kernel_wide<Model, Store, PPT>);
   if (cap) {
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, L.smem);
@@ -453,8 +535,7 @@ static hipError_t batch_bwd_t(const BatchLaunch& L, int* cap) {
   const void* probs = L.probs;
   const int2* bmap = L.bmap;
   void* args[] = {&probs, &bmap};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(L.blocks), dim3(kBlock), args,
-                                    static_cast<unsigned>(L.smem), L.stream);
+  return hipLaunchCooperativeKernel(kern, dim3(L.blocks), dim3(kBlock), args, static_cast<unsigned>(L.smem), L.stream);
 }
 
 template <class Model, typename Store>
