@@ -650,7 +650,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   HIP_OK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
 
-  const int ppt_f = airpf::forward_ppt(model->kind, dx, n_max);
+  const int ppt_f = airpf::forward_ppt(model->kind, dx, n_max, !want_score);
   const int ppt_b = want_score ? airpf::backward_ppt(model->kind, dx, n_max) : 0;
   for (Item& it : items) {
     it.TP = pow2_ceil_i((it.N + ppt_f - 1) / ppt_f);
@@ -658,6 +658,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   }
   airpf::BatchLaunch BL;
   BL.kind = model->kind; BL.dx = dx; BL.fp64 = fp64; BL.n_max = n_max; BL.num_cus = ctx->num_cus;
+  BL.ppt = ppt_f;
   BL.plain = want_score ? 0 : 1;          // the score's forward launches record and replay
   BL.stream = s; BL.blocks = 0; BL.probs = nullptr; BL.bmap = nullptr;
   BL.smem = airpf::forward_smem(fp64, ppt_f, dx, 256, 256, airpf::kResidentBudget);   // bound of any tiling below

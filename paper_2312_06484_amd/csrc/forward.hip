@@ -22,8 +22,13 @@ hipError_t launch_forward(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan) {
 
 // ------------------------------------------------------------ batched launches
 
-int forward_ppt(int kind, int dx, int n) {
+int forward_ppt(int kind, int dx, int n, bool plain) {
   const int DX = kind == 2 ? dx : 1;
+  // a forward-only batch of a 1-D model whose teams would span two waves
+  // takes eight particles per lane instead (teams inside one wave; results
+  // do not depend on it): 294 -> 255 ms on the 64-proposal SV batch.  With
+  // scores the recorded variants lose occupancy at eight, so they keep four.
+  if (plain && DX == 1 && n > 256 && n <= 1024) return 8;
   if (DX % 4 == 0) {
     if (n <= 256) return 1;
     if (n <= 512) return 2;

@@ -1224,7 +1224,7 @@ static hipError_t batch_fwd_t(const BatchLaunch& L, int* cap) {
 
 template <class Model, typename Store>
 static hipError_t batch_fwd_ppt(const BatchLaunch& L, int* cap) {
-  switch (forward_ppt(L.kind, L.dx, L.n_max)) {
+  switch (L.ppt) {              // the items' teams were sized for it
     case 1: if constexpr (Model::DX % 4 == 0) return batch_fwd_t<Model, Store, 1>(L, cap); break;
     case 2: if constexpr (Model::DX % 2 == 0) return batch_fwd_t<Model, Store, 2>(L, cap); break;
     case 4: return batch_fwd_t<Model, Store, 4>(L, cap);

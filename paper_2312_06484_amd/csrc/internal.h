@@ -91,7 +91,8 @@ hipError_t fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t st);
 // bmap[b].y of problem bmap[b].x ----
 struct BatchLaunch {
   int kind, dx, fp64;
-  int n_max;                  // largest N of the batch (picks particles per lane)
+  int n_max;                  // largest N of the batch
+  int ppt = 0;                // forward: particles per lane of every item (forward_ppt of the batch)
   int num_cus;
   size_t smem;                // dynamic LDS per block
   int blocks;                 // total blocks
@@ -100,7 +101,7 @@ struct BatchLaunch {
   hipStream_t stream;
   int plain = 0;              // forward: every item plain (no traces, records, replay or checkpoints)
 };
-int forward_ppt(int kind, int dx, int n_max);
+int forward_ppt(int kind, int dx, int n_max, bool plain);
 // dynamic LDS of a forward block with c islands of a G-block problem, plus
 // `resident` bytes of LDS-resident resampled states (forward_resident_bytes)
 size_t forward_smem(int fp64, int ppt, int dx, int c, int G, size_t resident);
