@@ -119,8 +119,9 @@ def measure_modes(ctx, torch):
     """Every configuration of the benchmark table besides the headline one,
     each timed once (wall clock, inputs resident in HBM) after one warm-up
     call: the 1-D LG workload with interactions off, the SV workload forward
-    and forward + score, the 64-chain SV proposal batch (forward + score) in
-    one batched call versus one theta at a time, and the 8-D LG workload
+    and forward + score, the 64-chain SV proposal batch forward alone and
+    forward + score in one batched call, the latter also one theta at a
+    time, and the 8-D LG workload
     forward and forward + score."""
     from paper_2312_06484_amd import workloads as W
     out = {}
@@ -162,6 +163,12 @@ def measure_modes(ctx, torch):
     tb, (st, lzb, grb, ist) = timed(torch, lambda w: ctx.run_batch(1, probs, tau=0.3, want_score=True,
                                                                    ckpt_every=100, y_on_device=True,
                                                                    autotune=True))
+    # the forward alone (what a PMMH step calls), batched: the warm-up call
+    # measures and caches its tiling too
+    tf, (stf, lzf, _, istf) = timed(torch, lambda w: ctx.run_batch(1, probs, tau=0.3, want_score=False,
+                                                                    y_on_device=True, autotune=True))
+    out["batched_fwd_sv_64_chains"] = mode_record(total, tf, fwd_bytes(1, 4), total_particle_steps=total,
+                                                  items_ok=int((istf == 0).sum()), tiling="autotuned")
     out["batched_fwd_score_sv_64_chains"] = mode_record(total, tb, bpp, total_particle_steps=total,
                                                         items_ok=int((ist == 0).sum()), tiling="autotuned")
     t0 = time.perf_counter()
