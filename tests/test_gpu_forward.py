@@ -226,7 +226,7 @@ def test_untraced_run_without_interactions(ctx, orc, model, m, N, T, tau, f64, d
     ("lg1", 1024, 64, 200, 0.97, False, None),     # stages reaching across blocks on many steps
     ("sv", 16384, 16, 60, 0.8, False, None),       # 64 islands per block
     ("lg1", 65536, 4, 30, 0.6, False, None),       # 256 islands per block
-    ("lgd", 2048, 64, 20, 0.5, False, 8),          # untraced serial kernel on more than 256 blocks
+    ("lgd", 2048, 64, 20, 1.5, False, 8),          # untraced serial kernel (every stage interacts) on 512 blocks
 ])
 def test_untraced_run_matches_traced(ctx, orc, model, m, N, T, tau, f64, dx):
     """An untraced run may take each step's passes before the step's
@@ -245,3 +245,29 @@ def test_untraced_run_matches_traced(ctx, orc, model, m, N, T, tau, f64, dx):
     assert lz == lz_traced
     lo = orc.run(P, tau=tau, store_f32=not f64)
     assert abs(lz - lo) <= 1e-12 * max(1.0, abs(lo)), (lz, lo)
+
+
+@pytest.mark.parametrize("model,m,N,T,tau", [
+    ("lg1", 1024, 256, 200, 0.3),                  # the benchmark width
+    ("sv", 4096, 128, 100, 0.6),                   # two passes per block, more than 256 blocks
+])
+def test_untraced_serial_kernel_matches_traced(ctx, orc, model, m, N, T, tau):
+    """With the pipelined kernel switched off (AIRPF_PIPELINE=0) an untraced
+    run takes the serial kernel (speculative passes between publishing a step
+    and the barrier); its log Zhat must equal the traced run's bit for bit."""
+    import os
+    g, P = make_case(orc, model, m, N, T, 7, None)
+    print("case", model, m, N, T, tau, flush=True)
+    from paper_2312_06484_amd import airpf
+    gt = airpf.Trace(T, m, N, enf=False, anc=False, digest=False, lpost=False)
+    _, lz_traced = ctx.run(g["kind"], g["theta"], g["y"], m, N, 7, tau=tau, trace=gt)
+    old = os.environ.get("AIRPF_PIPELINE")
+    os.environ["AIRPF_PIPELINE"] = "0"
+    try:
+        _, lz = ctx.run(g["kind"], g["theta"], g["y"], m, N, 7, tau=tau)
+    finally:
+        if old is None:
+            os.environ.pop("AIRPF_PIPELINE", None)
+        else:
+            os.environ["AIRPF_PIPELINE"] = old
+    assert lz == lz_traced
