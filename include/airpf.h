@@ -32,6 +32,11 @@
  *     AIRPF_E_DOMAIN (theta outside its support) *log_z_out is -inf; on other
  *     errors outputs are set to NaN where they exist.  A run in which every
  *     island's weight vanishes is a valid estimate: AIRPF_OK, log Zhat = -inf.
+ *   - Tiling never changes a result.  Environment switches, read at each
+ *     call, only change how the work is laid out: AIRPF_MAX_BLOCKS=<n> caps
+ *     the blocks of a single-problem launch, AIRPF_PIPELINE=0 switches off
+ *     the pipelined forward kernel (worker waves beside a control wave),
+ *     AIRPF_TILER="alpha,beta" sets the batch tiler's cost ratio beta/alpha.
  */
 #ifndef AIRPF_H
 #define AIRPF_H
