@@ -119,6 +119,18 @@ def test_deterministic(ctx):
     assert a == b and a != c
 
 
+@pytest.mark.parametrize("kind,m,N,T,tau", [(0, 1024, 256, 400, 0.3), (1, 4096, 128, 200, 0.6), (0, 512, 64, 300, 0.97)])
+def test_pipelined_runs_are_deterministic(ctx, kind, m, N, T, tau):
+    """Untraced runs (the pipelined kernel: records exchanged through a
+    ring of NaN-initialised slots, blocks far apart in time) repeated with one
+    seed give one value bit for bit, and another seed another."""
+    y = W.lg1_data(T) if kind == 0 else W.sv_data(T)
+    th = W.LG1_THETA if kind == 0 else W.SV_THETA
+    vals = [ctx.run(kind, th, y, m, N, 11)[1] for _ in range(6)]
+    assert all(v == vals[0] for v in vals), vals
+    assert ctx.run(kind, th, y, m, N, 12)[1] != vals[0]
+
+
 def test_close_to_kalman(ctx):
     from oracle import kalman
     T = 1000
