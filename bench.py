@@ -169,6 +169,20 @@ def measure_modes(ctx, torch):
                                                                     y_on_device=True, autotune=True))
     out["batched_fwd_sv_64_chains"] = mode_record(total, tf, fwd_bytes(1, 4), total_particle_steps=total,
                                                   items_ok=int((istf == 0).sum()), tiling="autotuned")
+    # PMMH on the SV posterior: 64 chains, each iteration's 64 proposals
+    # scored by one batched forward (T = 500, 256 islands of 128 particles)
+    import numpy as np
+    from paper_2312_06484_amd import pmmh
+    Tp, mp_, Np, iters = 500, 256, 128, 20
+    ll = pmmh.BatchedLogLik(ctx, 1, W.sv_data(Tp), mp_, Np, tau=0.3)
+    th0 = np.tile(np.array(W.SV_THETA), (64, 1))
+    step = [0.05, 0.01, 0.02]
+    pmmh.run(ll, pmmh.sv_log_prior, th0, 2, step, seed=1)          # warm-up (workspaces, tiling)
+    res = pmmh.run(ll, pmmh.sv_log_prior, th0, iters, step, seed=2)
+    out["pmmh_sv_t500_m256_n128_64_chains"] = mode_record(
+        res["runs"] * mp_ * Np * Tp, res["seconds"], fwd_bytes(1, 4), iterations=iters,
+        chain_iterations_per_s=64 * iters / res["seconds"], acceptance=float(res["accepted"].mean()),
+        ms_per_iteration=res["seconds"] / iters * 1e3)
     out["batched_fwd_score_sv_64_chains"] = mode_record(total, tb, bpp, total_particle_steps=total,
                                                         items_ok=int((ist == 0).sum()), tiling="autotuned")
     t0 = time.perf_counter()
