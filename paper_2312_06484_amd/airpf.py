@@ -160,7 +160,8 @@ class Context:
     # ------------------------------------------------------------------ calls
 
     @staticmethod
-    def _args(kind, theta, y, tau, fp64, dx, dy, consts, y_device_ptr, T, score_mode=PATHSPACE, ckpt_every=0):
+    def _args(kind, theta, y, tau, fp64, dx, dy, consts, y_device_ptr, T, score_mode=PATHSPACE, ckpt_every=0,
+              resampling=SYSTEMATIC):
         theta = np.ascontiguousarray(theta, dtype=np.float64)
         model = _Model()
         model.kind, model.dx, model.dy = int(kind), int(dx), int(dy)
@@ -168,7 +169,7 @@ class Context:
         model.consts = _p(cst, _dp)
         model.n_consts = 0 if cst is None else cst.size
         opt = _Options()
-        opt.tau, opt.resampling, opt.precision = float(tau), SYSTEMATIC, FP64 if fp64 else FP32
+        opt.tau, opt.resampling, opt.precision = float(tau), int(resampling), FP64 if fp64 else FP32
         opt.score_mode, opt.ckpt_every, opt.flags = int(score_mode), int(ckpt_every), 0
         if y_device_ptr is not None:
             ptr = C.c_void_p(int(y_device_ptr))
@@ -182,11 +183,12 @@ class Context:
         return theta, model, cst, opt, ptr, Tn, yy
 
     def run(self, kind, theta, y, m, N, seed, tau=0.3, fp64=False, dx=1, dy=1, consts=None,
-            trace=None, y_device_ptr=None, T=None, raise_on_error=True):
+            trace=None, y_device_ptr=None, T=None, raise_on_error=True, resampling=SYSTEMATIC):
         """airpf_run: returns (status, log Zhat).  ``y`` is a host array, or
-        pass ``y_device_ptr`` (int) and ``T`` for observations already in HBM."""
+        pass ``y_device_ptr`` (int) and ``T`` for observations already in HBM.
+        ``resampling``: SYSTEMATIC or MULTINOMIAL internal resampling."""
         theta, model, cst, opt, ptr, Tn, keep = self._args(kind, theta, y, tau, fp64, dx, dy, consts,
-                                                           y_device_ptr, T)
+                                                           y_device_ptr, T, resampling=resampling)
         out = C.c_double(np.nan)
         tr = trace._c() if trace is not None else None
         st = lib().airpf_run(self._h, C.byref(model), _p(theta, _dp), theta.size, ptr, Tn, int(m), int(N),
@@ -197,10 +199,11 @@ class Context:
         return st, out.value
 
     def score(self, kind, theta, y, m, N, seed, tau=0.3, fp64=False, dx=1, dy=1, consts=None,
-              ckpt_every=0, score_mode=PATHSPACE, trace=None, y_device_ptr=None, T=None, raise_on_error=True):
+              ckpt_every=0, score_mode=PATHSPACE, trace=None, y_device_ptr=None, T=None, raise_on_error=True,
+              resampling=SYSTEMATIC):
         """airpf_score: returns (status, log Zhat, gradient)."""
         theta, model, cst, opt, ptr, Tn, keep = self._args(kind, theta, y, tau, fp64, dx, dy, consts,
-                                                           y_device_ptr, T, score_mode, ckpt_every)
+                                                           y_device_ptr, T, score_mode, ckpt_every, resampling)
         out = C.c_double(np.nan)
         grad = np.full(theta.size, np.nan)
         tr = trace._c() if trace is not None else None

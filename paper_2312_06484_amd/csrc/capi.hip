@@ -209,10 +209,11 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   const airpf_options& opt = P->opt;
   if (!(opt.tau == opt.tau)) return AIRPF_E_INVALID_ARG;
   if (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) return AIRPF_E_INVALID_ARG;
-  if (opt.resampling != AIRPF_SYSTEMATIC) return AIRPF_E_UNSUPPORTED;
+  if (opt.resampling != AIRPF_SYSTEMATIC && opt.resampling != AIRPF_MULTINOMIAL) return AIRPF_E_INVALID_ARG;
 
   airpf::FwdArgs& a = P->a;
   std::memset(&a, 0, sizeof(a));
+  a.multinomial = opt.resampling == AIRPF_MULTINOMIAL ? 1 : 0;
   const airpf_status st = prepare_model(model, theta, d_theta, N, &a.mp, &a.cst_q, &P->dx, &P->dy);
   if (st == AIRPF_E_DOMAIN) { *log_z_out = -INFINITY; return st; }
   if (st != AIRPF_OK) return st;
@@ -356,6 +357,8 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   if (!grad_out) { set_nan(log_z_out); return AIRPF_E_INVALID_ARG; }
   const airpf_options opt = opt_in ? *opt_in : default_options();
   if (opt.score_mode == AIRPF_PATHWISE) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
+  // the reverse pass finds a particle's children as a run of sorted ancestors
+  if (opt.resampling == AIRPF_MULTINOMIAL) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
   if (opt.score_mode != AIRPF_PATHSPACE || opt.ckpt_every < 0) { set_nan(log_z_out); return AIRPF_E_INVALID_ARG; }
   if (model && ((model->kind == AIRPF_LGD && N > 512) || (model->kind != AIRPF_LGD && N > 1024))) {
     set_nan(log_z_out);

@@ -101,6 +101,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   // this block's part of the island tree (levels 1 .. lc+1, level l at
   // offset 2c - 2c/2^(l-1)), one copy per step parity: the walk of step n
   // reads step n-1's copy while the weighting writes step n's
+  // multinomial resampling: each team's inclusive cumulative weights
+  // ([kBlock*PPT] uint64), after the resampled states when those are in LDS
+  uint64_t* sC = reinterpret_cast<uint64_t*>(
+      (reinterpret_cast<uintptr_t>(a.res_lds ? res + 2 * res_words : res) + 15) & ~static_cast<uintptr_t>(15));
   auto lvp = [&](int par) { return lvb + 2 * c * par; };
 
   unsigned epoch = 0;
@@ -423,6 +427,37 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           for (int d = 0; d < DX; ++d) sxt[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
           sAt[j0 + r] = -1;                                   // no run starts here (yet)
         }
+        if (a.multinomial) {
+          // N independent draws from the island's weighted particles: slot j
+          // takes the first particle whose cumulative weight exceeds U_j,
+          // U_j uniform on [0, Q) (its own draw at (slot j, island, step))
+          uint64_t* sCt = sC + team * TP * PPT;
+          uint64_t Cr = incl - tsum;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r) {
+            Cr += q[r];
+            sCt[j0 + r] = Cr;
+          }
+          team_sync(TP);
+#pragma unroll
+          for (int r = 0; r < PPT; ++r) {
+            const int j = j0 + r;
+            if (active && j < N) {
+              int anc = j;
+              if (Qk > 0) {
+                const uint64_t Uj = bounded_u64(key, static_cast<uint32_t>(j), static_cast<uint32_t>(k),
+                                                static_cast<uint32_t>(n), kTagMult, Qk);
+                int lo = 0, hi = N - 1;
+                while (lo < hi) {
+                  const int mid = (lo + hi) >> 1;
+                  if (sCt[mid] > Uj) hi = mid; else lo = mid + 1;
+                }
+                anc = lo;
+              }
+              sAt[j] = anc;
+            }
+          }
+        } else {
         uint64_t U = 0;
         if (lane == 0 && active && Qk > 0)
           U = bounded_u64_from(wsys, key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, Qk);
@@ -462,14 +497,20 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           mk[r] = r == 0 ? v : (v > mk[r - 1] ? v : mk[r - 1]);
         }
         const int before = team_exclusive_max(mk[PPT - 1], TP, bc_i);
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const int j = j0 + r;
+          if (active && j < N) sAt[j] = Qk > 0 ? (mk[r] > before ? mk[r] : before) : j;
+        }
+        }  // systematic
+        team_sync(TP);
         Store* xo = static_cast<Store*>(a.x1[par]) + (static_cast<int64_t>(k) * N) * DX;
         unsigned long long dig = 0;
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           const int j = j0 + r;
           if (active && j < N) {
-            const int anc = Qk > 0 ? (mk[r] > before ? mk[r] : before) : j;
-            sAt[j] = anc;
+            const int anc = sAt[j];
             if (tr_anc) tr_anc[(n * m + k) * static_cast<int64_t>(N) + j] = anc;
             if (rec_anc) rec_anc[((n - n0) * m + k) * static_cast<int64_t>(N) + j] = static_cast<uint16_t>(anc);
             if (tr_digest) dig += digest_term(n, k, j, anc);
@@ -1117,7 +1158,9 @@ inline bool fwd_is_score_forward(const FwdArgs& a) {
 }
 
 inline bool fwd_pipe_candidate(const FwdArgs& a, int TP) {
-  if (!(fwd_is_plain(a) || fwd_is_score_forward(a)) || TP > 64 || a.no_interaction || a.shortcut_all) return false;
+  if (!(fwd_is_plain(a) || fwd_is_score_forward(a)) || TP > 64 || a.no_interaction || a.shortcut_all ||
+      a.multinomial)
+    return false;
   const char* e = std::getenv("AIRPF_PIPELINE");
   return !(e && e[0] == '0');
 }
@@ -1156,7 +1199,8 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
   const int tpb = kBlock / TP;
   auto smem_of = [&](int G) {
     const int c = a.m / G;
-    return fwd_smem_bytes(sizeof(Store), PPT, Model::DX, c, G) + fwd_res_bytes(sizeof(Store), Model::DX, c, a.N);
+    return fwd_smem_bytes(sizeof(Store), PPT, Model::DX, c, G) + fwd_res_bytes(sizeof(Store), Model::DX, c, a.N) +
+           (a.multinomial ? 16 + 8 * size_t(kBlock) * PPT : 0);     // the cumulative weights of multinomial draws
   };
   auto set_plan = [&](int G, size_t smem) {
     a.TP = TP;

@@ -18,6 +18,7 @@ struct FwdArgs {
   int shortcut_all;           // tau > 1: every stage interacts
   int no_interaction;         // tau <= 1/(2m): no stage can interact (ENF >= 1/m)
   int res_lds;                // 1: a block also keeps its resampled states in LDS (one copy per step parity)
+  int multinomial;            // internal resampling: 0 systematic, 1 multinomial (N independent draws)
   void* x1[2];                // Store*, resampled blocks, [m*N*DX] particle-major
   double* tree[2];            // [2m] pair-mean tree of island log-weights
   double* part[2];            // [(lc+1)*3*G] per level: the blocks' ENF records (E, a, b)

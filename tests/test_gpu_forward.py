@@ -283,3 +283,34 @@ def test_untraced_serial_kernel_matches_traced(ctx, orc, model, m, N, T, tau):
         else:
             os.environ["AIRPF_PIPELINE"] = old
     assert lz == lz_traced
+
+
+@pytest.mark.parametrize("model,m,N,T,tau,f64,dx", [
+    ("lg1", 8, 32, 60, 0.5, True, None),
+    ("sv", 64, 37, 30, 0.7, False, None),          # ragged island size
+    ("lgd", 16, 64, 12, 0.8, True, 4),
+    ("lg1", 256, 256, 20, 0.3, False, None),       # the benchmark's island size, several blocks
+    ("sv", 4, 1000, 8, 2.0, False, None),          # islands of several waves, every stage interacts
+])
+def test_multinomial_parity(ctx, orc, model, m, N, T, tau, f64, dx):
+    """Multinomial internal resampling (N independent draws, slot j from its
+    own uniform on [0, Q)): ancestors, island maps, s* and digests bit-exact
+    against the oracle, log Zhat to 1e-12; the untraced run equals the traced."""
+    from paper_2312_06484_amd import airpf
+    g, P = make_case(orc, model, m, N, T, 4, dx)
+    print("case", model, dx, m, N, T, tau, flush=True)
+    gt = airpf.Trace(T, m, N)
+    kw = dict(tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"], consts=g["consts"], resampling=airpf.MULTINOMIAL)
+    _, lz = ctx.run(g["kind"], g["theta"], g["y"], m, N, 4, trace=gt, **kw)
+    ot = orc.Trace(P)
+    lo = orc.run(P, tau=tau, scheme=1, store_f32=not f64, trace=ot)
+    assert_parity(lz, gt, lo, ot, P)
+    _, lz2 = ctx.run(g["kind"], g["theta"], g["y"], m, N, 4, **kw)
+    assert lz2 == lz
+
+
+def test_multinomial_score_is_unsupported(ctx):
+    from paper_2312_06484_amd import airpf
+    st, lz, g = ctx.score(0, W.LG1_THETA, W.lg1_data(10), 4, 16, 1, resampling=airpf.MULTINOMIAL,
+                          raise_on_error=False)
+    assert st == airpf.E_UNSUPPORTED and np.isnan(g).all()
