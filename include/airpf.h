@@ -85,7 +85,13 @@ typedef struct {
   double tau;         /* ENF threshold of the adaptation line of Algorithm 1:
                          stage s interacts iff ENF_{n,s} < tau.  tau <= 1/m never
                          interacts (independent filters), tau > 1 always does. */
-  int32_t resampling; /* airpf_resampling; the GPU implements AIRPF_SYSTEMATIC */
+  int32_t resampling; /* airpf_resampling of the internal (within-island) step:
+                         AIRPF_SYSTEMATIC everywhere; AIRPF_MULTINOMIAL (slot j
+                         takes the first particle whose cumulative fixed-point
+                         weight exceeds its own uniform draw on [0, Q)) in
+                         airpf_run only -- airpf_score and airpf_run_batch return
+                         AIRPF_E_UNSUPPORTED for it; any other value is
+                         AIRPF_E_INVALID_ARG */
   int32_t precision;  /* storage precision of the particle state; all particle
                          arithmetic is double precision either way */
   int32_t score_mode; /* airpf_score_mode (airpf_score only) */
