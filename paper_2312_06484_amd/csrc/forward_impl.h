@@ -52,7 +52,9 @@ namespace airpf {
 // Plain: a run with no traces, no score records, no replay and no
 // checkpoints, compiled on its own so that none of those paths (nor the
 // registers they hold) exist in it.
-template <class Model, typename Store, int PPT, bool Plain>
+// Mult: multinomial internal resampling (a kernel of its own, so that the
+// systematic kernels carry none of its code or registers).
+template <class Model, typename Store, int PPT, bool Plain, bool Mult = false>
 __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;                 // normals per lane per step
@@ -427,7 +429,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           for (int d = 0; d < DX; ++d) sxt[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
           sAt[j0 + r] = -1;                                   // no run starts here (yet)
         }
-        if (a.multinomial) {
+        if constexpr (Mult) {
           // N independent draws from the island's weighted particles: slot j
           // takes the first particle whose cumulative weight exceeds U_j,
           // U_j uniform on [0, Q) (its own draw at (slot j, island, step))
@@ -439,7 +441,9 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
             sCt[j0 + r] = Cr;
           }
           team_sync(TP);
-#pragma unroll
+          // one slot at a time (not unrolled): the draws would otherwise hold
+          // registers the rest of the kernel needs
+#pragma unroll 1
           for (int r = 0; r < PPT; ++r) {
             const int j = j0 + r;
             if (active && j < N) {
@@ -503,7 +507,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           if (active && j < N) sAt[j] = Qk > 0 ? (mk[r] > before ? mk[r] : before) : j;
         }
         }  // systematic
-        team_sync(TP);
+        // (each lane reads back only the ancestors of its own slots)
         Store* xo = static_cast<Store*>(a.x1[par]) + (static_cast<int64_t>(k) * N) * DX;
         unsigned long long dig = 0;
 #pragma unroll
@@ -1123,6 +1127,12 @@ __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
   forward_body<Model, Store, PPT, Plain>(a, static_cast<int>(blockIdx.x));
 }
 
+// multinomial internal resampling (single problem, traced or not)
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void forward_mult_kernel(FwdArgs a) {
+  forward_body<Model, Store, PPT, false, true>(a, static_cast<int>(blockIdx.x));
+}
+
 // Several problems in one cooperative launch: block b runs block bmap[b].y of
 // problem bmap[b].x; each problem synchronises only its own blocks.
 template <class Model, typename Store, int PPT, bool Plain>
@@ -1225,8 +1235,9 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
       return hipLaunchCooperativeKernel(pk, dim3(G), dim3(kPipeBlock), args, static_cast<unsigned>(smem), L.stream);
     }
   }
-  const void* kern = fwd_is_plain(a) ? reinterpret_cast<const void*>(forward_kernel<Model, Store, PPT, true>)
-                                     : reinterpret_cast<const void*>(forward_kernel<Model, Store, PPT, false>);
+  const void* kern = a.multinomial    ? reinterpret_cast<const void*>(forward_mult_kernel<Model, Store, PPT>)
+                     : fwd_is_plain(a) ? reinterpret_cast<const void*>(forward_kernel<Model, Store, PPT, true>)
+                                       : reinterpret_cast<const void*>(forward_kernel<Model, Store, PPT, false>);
   const int G = fit_blocks(kern, kBlock, L, a.m, tpb, L.max_blocks, smem_of, &smem);
   if (G < 1) return hipErrorCooperativeLaunchTooLarge;
   if (a.m / G > kMaxIslandsPerBlock) return hipErrorInvalidValue;     // islands per block are bounded by the LDS plan
