@@ -291,6 +291,9 @@ def test_untraced_serial_kernel_matches_traced(ctx, orc, model, m, N, T, tau):
     ("lgd", 16, 64, 12, 0.8, True, 4),
     ("lg1", 256, 256, 20, 0.3, False, None),       # the benchmark's island size, several blocks
     ("sv", 4, 1000, 8, 2.0, False, None),          # islands of several waves, every stage interacts
+    ("lg1", 1, 64, 20, 0.5, True, None),           # one island: no stages
+    ("sv", 16, 1, 12, 0.9, False, None),           # one particle per island
+    ("lg1", 32, 48, 1, 0.3, False, None),          # a single observation: no resampling
 ])
 def test_multinomial_parity(ctx, orc, model, m, N, T, tau, f64, dx):
     """Multinomial internal resampling (N independent draws, slot j from its
