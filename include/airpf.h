@@ -136,7 +136,10 @@ airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, const double* t
  * a time (K = 0: the whole history is kept when it fits the workspace
  * budget, otherwise K = ceil(sqrt(T))).  Supported: N <= 1024 (LG1, SV),
  * N <= 512 (LGD); opt->score_mode AIRPF_PATHWISE returns
- * AIRPF_E_UNSUPPORTED in this build.  grad_out is host memory. */
+ * AIRPF_E_UNSUPPORTED in this build.  grad_out is host memory.  A run in
+ * which every island's weight vanishes returns AIRPF_OK, log Zhat = -inf and
+ * a zero score (no reverse pass is made; airpf_run_batch does the same per
+ * problem). */
 airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, const double* theta,
                          int32_t d_theta, const double* y, int64_t T, int32_t m, int32_t N,
                          uint64_t seed, const airpf_options* opt, double* log_z_out,

@@ -439,6 +439,26 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
     HIP_OK(hipMemcpyAsync(keep_pi, a.tr_pi, 4 * size_t(T - 1) * m, hipMemcpyDeviceToDevice, s));
   if (keep_sstar) HIP_OK(hipMemcpyAsync(keep_sstar, a.tr_sstar, 4 * size_t(T), hipMemcpyDeviceToDevice, s));
 
+  // A run in which every island died stopped at that step, so its records end
+  // there: the estimate is zero and its score is taken as zero, with no
+  // reverse sweep.  A forward pass that failed skips the sweep too.
+  {
+    double lz_fwd = 0.0;
+    int st_fwd = 0;
+    HIP_OK(hipMemcpyAsync(&lz_fwd, a.out_logz, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(&st_fwd, a.status, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (st_fwd != 0 || lz_fwd == -INFINITY) {
+      HIP_OK(hipEventRecord(ctx->ev[1], s));
+      a.tr_pi = keep_pi;
+      a.tr_sstar = keep_sstar;
+      ST_OK(copy_trace(ctx, P, trace));
+      const airpf_status fs = finish(ctx, P, log_z_out);
+      for (int p = 0; p < d_theta; ++p) grad_out[p] = fs == AIRPF_OK ? 0.0 : std::nan("");
+      return fs;
+    }
+  }
+
   // reverse, one segment at a time, tiled as the serial forward kernel would
   // be (the pipelined forward's tiling stops at 256 blocks; the reverse
   // kernel's own co-residency bounds both): results do not depend on it
@@ -888,6 +908,15 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   if (st != AIRPF_OK) { for (const Item& it : items) item_status[it.idx] = st; return st; }
 
   if (want_score) {
+    // a problem whose islands all died stopped at that step (its records end
+    // there): no reverse sweep, its score is zero; a failed forward launch
+    // skips every sweep (reported below)
+    std::vector<double> lz_fwd(items.size());
+    int st_fwd = 0;
+    HIP_OK(hipMemcpyAsync(lz_fwd.data(), at(o_logz), 8 * lz_fwd.size(), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(&st_fwd, d_status, 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    auto swept = [&](const Item& it) { return st_fwd == 0 && lz_fwd[&it - items.data()] != -INFINITY; };
     for (Item& it : items) HIP_OK(airpf::fill_u32(at(it.o_gisl), 0u, 2 * int64_t(it.m) * Pn, s));
     int64_t Cmax = 0;
     for (const Item& it : items) Cmax = std::max(Cmax, it.C);
@@ -896,7 +925,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
       std::vector<int64_t> st_act, st_rec;
       for (Item& it : items) {
         const int64_t cidx = it.C - 1 - j;
-        if (cidx < 0) continue;
+        if (cidx < 0 || !swept(it)) continue;
         const int64_t lo = cidx * it.K, hi = std::min(it.T, (cidx + 1) * it.K);
         act.push_back(&it);
         st_act.push_back(hi - lo);
