@@ -121,8 +121,9 @@ def measure_modes(ctx, torch):
     call: the 1-D LG workload with interactions off, the SV workload forward
     and forward + score, the 64-chain SV proposal batch forward alone and
     forward + score in one batched call, the latter also one theta at a
-    time, and the 8-D LG workload
-    forward and forward + score."""
+    time, 64 PMMH chains (random walk, and Langevin proposals from the
+    batched scores) with their effective sample sizes, and the 8-D LG
+    workload forward and forward + score."""
     from paper_2312_06484_amd import workloads as W
     out = {}
     dev = "cuda"
@@ -170,19 +171,34 @@ def measure_modes(ctx, torch):
     out["batched_fwd_sv_64_chains"] = mode_record(total, tf, fwd_bytes(1, 4), total_particle_steps=total,
                                                   items_ok=int((istf == 0).sum()), tiling="autotuned")
     # PMMH on the SV posterior: 64 chains, each iteration's 64 proposals
-    # scored by one batched forward (T = 500, 256 islands of 128 particles)
+    # scored by one batched forward (T = 500, 256 islands of 128 particles);
+    # then particle MALA, each iteration one batched forward + score.  The
+    # effective sample size per coordinate (mu, phi, sigma) is taken over the
+    # iterations after the first 10, across the 64 chains
     import numpy as np
     from paper_2312_06484_amd import pmmh
-    Tp, mp_, Np, iters = 500, 256, 128, 20
-    ll = pmmh.BatchedLogLik(ctx, 1, W.sv_data(Tp), mp_, Np, tau=0.3)
+    Tp, mp_, Np, iters, burn = 500, 256, 128, 60, 10
+    ysv = W.sv_data(Tp)
     th0 = np.tile(np.array(W.SV_THETA), (64, 1))
+
+    def chain_record(res, bpp):
+        ess = [pmmh.effective_sample_size(res["theta"][burn + 1:, :, i]) for i in range(3)]
+        return mode_record(res["runs"] * mp_ * Np * Tp, res["seconds"], bpp, iterations=iters,
+                           chain_iterations_per_s=64 * iters / res["seconds"],
+                           acceptance=float(res["accepted"].mean()), ms_per_iteration=res["seconds"] / iters * 1e3,
+                           ess_mu_phi_sigma=ess, ess_per_s_mu_phi_sigma=[e / res["seconds"] for e in ess],
+                           lag1_acf_mu_phi_sigma=[float(pmmh.autocorrelation(res["theta"][burn + 1:, :, i], 1)[1])
+                                                  for i in range(3)])
+    ll = pmmh.BatchedLogLik(ctx, 1, ysv, mp_, Np, tau=0.3)
     step = [0.05, 0.01, 0.02]
     pmmh.run(ll, pmmh.sv_log_prior, th0, 2, step, seed=1)          # warm-up (workspaces, tiling)
     res = pmmh.run(ll, pmmh.sv_log_prior, th0, iters, step, seed=2)
-    out["pmmh_sv_t500_m256_n128_64_chains"] = mode_record(
-        res["runs"] * mp_ * Np * Tp, res["seconds"], fwd_bytes(1, 4), iterations=iters,
-        chain_iterations_per_s=64 * iters / res["seconds"], acceptance=float(res["accepted"].mean()),
-        ms_per_iteration=res["seconds"] / iters * 1e3)
+    out["pmmh_sv_t500_m256_n128_64_chains"] = chain_record(res, fwd_bytes(1, 4))
+    sc = pmmh.BatchedScore(ctx, 1, ysv, mp_, Np, tau=0.3)
+    step = [0.08, 0.015, 0.03]
+    pmmh.run_mala(sc, pmmh.sv_log_prior, pmmh.sv_grad_log_prior, th0, 2, step, seed=1)
+    res = pmmh.run_mala(sc, pmmh.sv_log_prior, pmmh.sv_grad_log_prior, th0, iters, step, seed=2)
+    out["pmala_sv_t500_m256_n128_64_chains"] = chain_record(res, fwd_score_bytes(1, 4))
     out["batched_fwd_score_sv_64_chains"] = mode_record(total, tb, bpp, total_particle_steps=total,
                                                         items_ok=int((ist == 0).sum()), tiling="autotuned")
     t0 = time.perf_counter()
