@@ -257,10 +257,11 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
     a.part[p] = static_cast<double*>(ctx->part[p].p);
   }
   // misc: [0,8) log Zhat, [8,12) status, [64, 64 + 4G) barrier flags, then
-  // the level-1 record ring of the pipelined kernel (9G doubles, G <= 256)
+  // the level-1 record ring of the pipelined kernel (kRingCopies copies of
+  // 9G doubles, G <= 256)
   const size_t ring_off = (64 + 4 * size_t(P->gmax) + 255) & ~size_t(255);
   const int gring = std::min(P->gmax, 256);
-  ST_OK(ctx->misc.ensure(ring_off + 8 * 9 * size_t(gring)));
+  ST_OK(ctx->misc.ensure(ring_off + 8 * 9 * size_t(gring) * airpf::kRingCopies));
   unsigned char* misc = static_cast<unsigned char*>(ctx->misc.p);
   a.out_logz = reinterpret_cast<double*>(misc);
   a.status = reinterpret_cast<int*>(misc + 8);
@@ -274,7 +275,7 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
     a.y = static_cast<const double*>(ctx->ybuf.p);
   }
   HIP_OK(airpf::fill_u32(misc, 0u, 16 + int64_t(P->gmax), s));
-  HIP_OK(airpf::fill_u32(misc + ring_off, 0xFFFFFFFFu, 2 * 9 * int64_t(gring), s));   // all-ones words: NaN
+  HIP_OK(airpf::fill_u32(misc + ring_off, 0xFFFFFFFFu, 2 * 9 * int64_t(gring) * airpf::kRingCopies, s));   // NaN
   return AIRPF_OK;
 }
 

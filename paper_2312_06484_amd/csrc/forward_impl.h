@@ -945,7 +945,10 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     return __all(ok) != 0;
   };
   // Stage 1 of step t: this block's level-1 ENF record goes to slot t mod 3
-  // of a ring whose words are NaN until written; each lane waits until the
+  // of a ring whose words are NaN until written (into each of the ring's
+  // copies, by one lane per copy; the block polls one copy, and what is said
+  // here holds copy by copy, the clearing and the next record of a copy
+  // being stored by the same lane); each lane waits until the
   // records of its blocks (those wave_reduce_enf(G, ...) assigns it) are
   // complete, and they are joined as wave_reduce_enf joins them.  A record
   // is the block's arrival: no flag, and no wait for the record's own
@@ -957,14 +960,17 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   auto level1 = [&](int64_t t, EnfRec& out) -> bool {
     const int slot = static_cast<int>(t % 3), prev = static_cast<int>((t + 2) % 3);
     const double* lv = lvp(static_cast<int>(t & 1));
-    const EnfRec mine = wave_reduce_enf(c, [&](int i) { return enf_leaf(lv[i]); });
-    double* rs = a.ring + static_cast<int64_t>(slot) * 3 * G;
+    const EnfRec own = wave_reduce_enf(c, [&](int i) { return enf_leaf(lv[i]); });
+    const EnfRec mine{readlane_f64(own.E, 0), readlane_f64(own.a, 0), readlane_f64(own.b, 0)};
+    const int64_t copy_stride = 9 * static_cast<int64_t>(G);
     __builtin_amdgcn_s_waitcnt(0);
-    if (lane64 == 0) {
-      put(rs + bid, mine.E);
-      put(rs + G + bid, mine.a);
-      put(rs + 2 * G + bid, mine.b);
+    if (lane64 < kRingCopies) {                                 // lane r writes copy r
+      double* w = a.ring + lane64 * copy_stride + static_cast<int64_t>(slot) * 3 * G;
+      put(w + bid, mine.E);
+      put(w + G + bid, mine.a);
+      put(w + 2 * G + bid, mine.b);
     }
+    const double* rs = a.ring + (bid & (kRingCopies - 1)) * copy_stride + static_cast<int64_t>(slot) * 3 * G;
     const int per = G > 64 ? (G >> 6) : 1;                     // blocks per lane: 4, 2 or 1
     const int i0 = G > 64 ? lane64 * per : lane64;
     const int cnt = G > 64 ? per : (lane64 < G ? 1 : 0);
@@ -997,8 +1003,8 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     r = wave_butterfly_enf(r, G);
     out = EnfRec{readlane_f64(r.E, 0), readlane_f64(r.a, 0), readlane_f64(r.b, 0)};
     const bool done = __all(ok) != 0;
-    if (done && lane64 == 0) {
-      double* rp = a.ring + static_cast<int64_t>(prev) * 3 * G;
+    if (done && lane64 < kRingCopies) {
+      double* rp = a.ring + lane64 * copy_stride + static_cast<int64_t>(prev) * 3 * G;
       const double nan = __longlong_as_double(static_cast<long long>(~0ull));
       put(rp + bid, nan);
       put(rp + G + bid, nan);

@@ -7,6 +7,12 @@
 
 namespace airpf {
 
+// copies of the pipelined kernel's level-1 record ring: every block writes
+// its record into each copy and reads the copy of its own XCD (blocks are
+// dealt to the eight XCDs round-robin), so the polls of the 256 blocks are
+// spread over eight sets of lines instead of converging on one
+constexpr int kRingCopies = 8;
+
 // Kernel argument block of the persistent forward launch (one problem).
 struct FwdArgs {
   ModelArgs mp;
@@ -24,7 +30,7 @@ struct FwdArgs {
   double* part[2];            // [(lc+1)*3*G] per level: the blocks' ENF records (E, a, b)
   unsigned* bar;              // [G] grid-barrier flags, zero before the launch
   int* status;                // [1] 0 ok, 1 barrier timed out
-  double* ring;               // pipelined kernel: [3 slots][E, a, b][G] level-1 ENF records, NaN before the launch
+  double* ring;               // pipelined kernel: [kRingCopies][3 slots][E, a, b][G] level-1 ENF records, NaN before the launch
   double* out_logz;           // [1]
   int32_t* tr_sstar;
   double* tr_enf;
