@@ -38,9 +38,9 @@ def lg1(theta, y, grad=True):
     yy = torch.tensor(np.asarray(y, dtype=np.float64))
     ll = _lg1(th, yy)
     if not grad:
-        return float(ll), None
+        return float(ll.detach()), None
     ll.backward()
-    return float(ll), th.grad.numpy().copy()
+    return float(ll.detach()), th.grad.numpy().copy()
 
 
 def _lgd(A, H, q, r, p0, y):
