@@ -185,6 +185,7 @@ def effective_sample_size(x):
     monotone positive sequence (pairs of consecutive lags summed, cut at the
     first negative pair, forced non-increasing).  The between-chain spread
     enters through the pooled variance, so chains stuck apart count as few
+    samples.  Antithetic chains (tau < 1) are capped at C n log10(C n)
     samples."""
     x = np.asarray(x, dtype=np.float64)
     n, C = x.shape
