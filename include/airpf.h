@@ -89,7 +89,8 @@ typedef struct {
                          AIRPF_SYSTEMATIC everywhere; AIRPF_MULTINOMIAL (slot j
                          takes the first particle whose cumulative fixed-point
                          weight exceeds its own uniform draw on [0, Q)) in
-                         airpf_run only -- airpf_score and airpf_run_batch return
+                         airpf_run and in airpf_run_batch without scores --
+                         airpf_score and a batch with want_score return
                          AIRPF_E_UNSUPPORTED for it; any other value is
                          AIRPF_E_INVALID_ARG */
   int32_t precision;  /* storage precision of the particle state; all particle

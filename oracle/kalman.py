@@ -74,4 +74,4 @@ def lgd(A, H, q, r, p0, y, grad=True):
     if not grad:
         return float(ll), None
     ll.backward()
-    return float(ll), At.grad.numpy().reshape(-1).copy()
+    return float(ll.detach()), At.grad.numpy().reshape(-1).copy()

@@ -215,11 +215,12 @@ class Context:
         return st, out.value, grad
 
     def run_batch(self, kind, problems, tau=0.3, fp64=False, dx=1, dy=1, consts=None, want_score=False,
-                  ckpt_every=0, y_on_device=False, autotune=False, raise_on_error=True):
+                  ckpt_every=0, y_on_device=False, autotune=False, raise_on_error=True, resampling=SYSTEMATIC):
         """airpf_run_batch.  ``problems``: dicts with theta, y (host array, or a
         device pointer int with ``y_on_device`` and then T), m, N, seed;
         ``autotune`` sets AIRPF_FLAG_AUTOTUNE (measured tiling, cached per
-        batch shape in the context).
+        batch shape in the context); ``resampling`` MULTINOMIAL is forward
+        only.
         Returns (status, log_z[B], grad[B, d_theta] or None, item_status[B])."""
         B = len(problems)
         model = _Model()
@@ -228,7 +229,7 @@ class Context:
         model.consts = _p(cst, _dp)
         model.n_consts = 0 if cst is None else cst.size
         opt = _Options()
-        opt.tau, opt.resampling, opt.precision = float(tau), SYSTEMATIC, FP64 if fp64 else FP32
+        opt.tau, opt.resampling, opt.precision = float(tau), int(resampling), FP64 if fp64 else FP32
         opt.score_mode, opt.ckpt_every = PATHSPACE, int(ckpt_every)
         opt.flags = (FLAG_Y_ON_DEVICE if y_on_device else 0) | (FLAG_AUTOTUNE if autotune else 0)
         arr = (_Problem * max(B, 1))()

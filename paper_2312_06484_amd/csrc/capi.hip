@@ -634,7 +634,10 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   if (want_score && !grad_out) return AIRPF_E_INVALID_ARG;
   if (!(opt.tau == opt.tau) || (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) || opt.ckpt_every < 0)
     return AIRPF_E_INVALID_ARG;
-  if (opt.resampling != AIRPF_SYSTEMATIC) return AIRPF_E_UNSUPPORTED;
+  if (opt.resampling != AIRPF_SYSTEMATIC && opt.resampling != AIRPF_MULTINOMIAL) return AIRPF_E_INVALID_ARG;
+  // multinomial draws: forward only (the reverse pass needs sorted ancestors)
+  if (opt.resampling == AIRPF_MULTINOMIAL && want_score) return AIRPF_E_UNSUPPORTED;
+  const int mult = opt.resampling == AIRPF_MULTINOMIAL ? 1 : 0;
   if (want_score && opt.score_mode != AIRPF_PATHSPACE)
     return opt.score_mode == AIRPF_PATHWISE ? AIRPF_E_UNSUPPORTED : AIRPF_E_INVALID_ARG;
   const bool y_dev = (opt.flags & AIRPF_FLAG_Y_ON_DEVICE) != 0;
@@ -684,8 +687,9 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   BL.kind = model->kind; BL.dx = dx; BL.fp64 = fp64; BL.n_max = n_max; BL.num_cus = ctx->num_cus;
   BL.ppt = ppt_f;
   BL.plain = want_score ? 0 : 1;          // the score's forward launches record and replay
+  BL.multinomial = mult;
   BL.stream = s; BL.blocks = 0; BL.probs = nullptr; BL.bmap = nullptr;
-  BL.smem = airpf::forward_smem(fp64, ppt_f, dx, 256, 256, airpf::kResidentBudget);   // bound of any tiling below
+  BL.smem = airpf::forward_smem(fp64, ppt_f, dx, 256, 256, airpf::kResidentBudget, mult);   // bound of any tiling below
   int cap_f = 0, cap_fp = 0;
   HIP_OK(airpf::forward_batch_capacity(BL, &cap_f));
   {
@@ -797,6 +801,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
         a.lc = ilog2(a.c); a.dy = dy; a.seed = it.seed; a.tau = opt.tau; a.cst_q = it.cst_q;
         a.shortcut_all = opt.tau > 1.0 + 1e-9;
         a.no_interaction = opt.tau <= 0.5 / it.m;
+        a.multinomial = mult;
         const size_t res = airpf::forward_resident_bytes(fp64, dx, a.c, it.N);
         a.res_lds = res > 0;
         res_max = std::max(res_max, res);
@@ -838,7 +843,8 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
     airpf::BatchLaunch L = BL;
     if (probe) L.plain = 1;
     L.blocks = int(bmap.size());
-    L.smem = mode == 0 ? airpf::forward_smem(fp64, ppt_f, dx, c_max, G_max, res_max) : airpf::backward_smem(fp64, ppt_b, dx);
+    L.smem = mode == 0 ? airpf::forward_smem(fp64, ppt_f, dx, c_max, G_max, res_max, mult)
+                       : airpf::backward_smem(fp64, ppt_b, dx);
     void* d_args = at(o_args);
     if (mode == 0) HIP_OK(hipMemcpyAsync(d_args, fa.data(), sizeof(airpf::FwdArgs) * fa.size(), hipMemcpyHostToDevice, s));
     else HIP_OK(hipMemcpyAsync(d_args, ba.data(), sizeof(airpf::BwdArgs) * ba.size(), hipMemcpyHostToDevice, s));

@@ -38,8 +38,10 @@ int forward_ppt(int kind, int dx, int n, bool plain) {
   return n <= 1024 ? 4 : 8;
 }
 
-size_t forward_smem(int fp64, int ppt, int dx, int c, int G, size_t resident) {
-  return fwd_smem_bytes(fp64 ? 8 : 4, ppt, dx, c, G) + resident;
+size_t forward_smem(int fp64, int ppt, int dx, int c, int G, size_t resident, int multinomial) {
+  // multinomial draws also keep each team's cumulative weights (16-byte aligned)
+  return fwd_smem_bytes(fp64 ? 8 : 4, ppt, dx, c, G) + resident +
+         (multinomial ? 16 + 8 * size_t(kBlock) * ppt : 0);
 }
 
 size_t forward_resident_bytes(int fp64, int dx, int c, int N) { return fwd_res_bytes(fp64 ? 8 : 4, dx, c, N); }

@@ -1147,6 +1147,13 @@ __global__ __launch_bounds__(kBlock) void forward_batch_kernel(const FwdArgs* pr
   forward_body<Model, Store, PPT, Plain>(probs[pb.x], pb.y);
 }
 
+// the same with multinomial internal resampling
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void forward_batch_mult_kernel(const FwdArgs* probs, const int2* bmap) {
+  const int2 pb = bmap[blockIdx.x];
+  forward_body<Model, Store, PPT, false, true>(probs[pb.x], pb.y);
+}
+
 }  // namespace airpf
 
 // ============================================================ host launcher
@@ -1269,7 +1276,8 @@ static hipError_t dispatch_ppt(const FwdLaunch& L, const FwdArgs& a, FwdPlan* pl
 
 template <class Model, typename Store, int PPT>
 static hipError_t batch_fwd_t(const BatchLaunch& L, int* cap) {
-  auto kern = L.plain ? forward_batch_kernel<Model, Store, PPT, true> : forward_batch_kernel<Model, Store, PPT, false>;
+  auto kern = L.multinomial ? forward_batch_mult_kernel<Model, Store, PPT>
+              : (L.plain ? forward_batch_kernel<Model, Store, PPT, true> : forward_batch_kernel<Model, Store, PPT, false>);
   if (cap) {
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, L.smem);

@@ -107,11 +107,12 @@ struct BatchLaunch {
   const int2* bmap;           // device [blocks]
   hipStream_t stream;
   int plain = 0;              // forward: every item plain (no traces, records, replay or checkpoints)
+  int multinomial = 0;        // forward: multinomial internal resampling (every item's FwdArgs says so too)
 };
 int forward_ppt(int kind, int dx, int n_max, bool plain);
 // dynamic LDS of a forward block with c islands of a G-block problem, plus
 // `resident` bytes of LDS-resident resampled states (forward_resident_bytes)
-size_t forward_smem(int fp64, int ppt, int dx, int c, int G, size_t resident);
+size_t forward_smem(int fp64, int ppt, int dx, int c, int G, size_t resident, int multinomial = 0);
 // LDS for both parity copies of a block's resampled states, or 0 when they
 // exceed the budget kResidentBudget (the states then come from HBM only)
 size_t forward_resident_bytes(int fp64, int dx, int c, int N);

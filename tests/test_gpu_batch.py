@@ -126,3 +126,26 @@ def test_full_size_proposal_batch_score_matches_single(ctx):
                               y_device_ptr=p["y"], T=p["T"])
         assert l1 == lz[i], i
         assert np.array_equal(g1, gr[i]), i
+
+
+def test_batch_multinomial_matches_single(ctx):
+    # multinomial internal resampling in the batched forward: every item
+    # bit-identical to the same problem run alone (whose ancestors are
+    # bit-exact with the oracle's multinomial scheme); scores unsupported
+    from paper_2312_06484_amd import airpf
+    probs = [dict(theta=W.LG1_THETA, y=W.lg1_data(40), m=64, N=128, seed=1),
+             dict(theta=W.LG1_THETA, y=W.lg1_data(25), m=16, N=37, seed=2),
+             dict(theta=W.LG1_THETA, y=W.lg1_data(33), m=256, N=256, seed=3),
+             dict(theta=W.LG1_THETA, y=W.lg1_data(12), m=1, N=64, seed=4),
+             dict(theta=W.LG1_THETA, y=W.lg1_data(30), m=8, N=700, seed=5)]
+    print("batch multinomial", flush=True)
+    for tau in (0.3, 2.0):
+        st, lz, _, ist = ctx.run_batch(0, probs, tau=tau, resampling=airpf.MULTINOMIAL)
+        assert st == airpf.OK and (ist == airpf.OK).all()
+        for i, p in enumerate(probs):
+            s1, l1 = ctx.run(0, p["theta"], p["y"], p["m"], p["N"], p["seed"], tau=tau, resampling=airpf.MULTINOMIAL)
+            assert s1 == airpf.OK and lz[i] == l1, (tau, i, lz[i], l1)
+        _, lz_sys, _, _ = ctx.run_batch(0, probs, tau=tau)
+        assert not np.array_equal(lz_sys, lz)           # a different scheme, a different estimate
+    st, _, _, _ = ctx.run_batch(0, probs, want_score=True, resampling=airpf.MULTINOMIAL, raise_on_error=False)
+    assert st == airpf.E_UNSUPPORTED
