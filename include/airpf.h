@@ -52,7 +52,7 @@ typedef enum {
   AIRPF_E_DOMAIN = 2,      /* theta outside the model's parameter space */
   AIRPF_E_NOMEM = 3,       /* device workspace could not be allocated */
   AIRPF_E_DEVICE = 4,      /* a HIP call or a kernel failed */
-  AIRPF_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+  AIRPF_E_UNSUPPORTED = 5  /* valid request the library does not implement */
 } airpf_status;
 
 /* State-space models (concrete instances of the HMM of Section 1.2).
@@ -137,7 +137,7 @@ airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, const double* t
  * a time (K = 0: the whole history is kept when it fits the workspace
  * budget, otherwise K = ceil(sqrt(T))).  Supported: N <= 1024 (LG1, SV),
  * N <= 512 (LGD); opt->score_mode AIRPF_PATHWISE returns
- * AIRPF_E_UNSUPPORTED in this build.  grad_out is host memory.  A run in
+ * AIRPF_E_UNSUPPORTED.  grad_out is host memory.  A run in
  * which every island's weight vanishes returns AIRPF_OK, log Zhat = -inf and
  * a zero score (no reverse pass is made; airpf_run_batch does the same per
  * problem). */

@@ -3,9 +3,8 @@
 For linear-Gaussian models d log Z / d theta is known in closed form (the
 Kalman filter, differentiated).  The path-space score is a consistent
 estimator of it: over independent seeds its mean approaches the Kalman
-gradient and its spread shrinks as m N grows (the survey's prototype
-numbers show the same trend; the pathwise estimator would converge to a
-different value).  The thresholds are statistical: 4 standard errors of the
+gradient and its spread shrinks as m N grows (the pathwise estimator,
+which holds the ancestors fixed, would converge to a different value).  The thresholds are statistical: 4 standard errors of the
 seed mean plus a small allowance for the estimator's O(1/(mN)) bias.
 """
 import os
