@@ -122,8 +122,9 @@ def measure_modes(ctx, torch):
     and forward + score, the 64-chain SV proposal batch forward alone and
     forward + score in one batched call, the latter also one theta at a
     time, 64 PMMH chains (random walk, and Langevin proposals from the
-    batched scores) with their effective sample sizes, and the 8-D LG
-    workload forward and forward + score."""
+    batched scores) with their effective sample sizes, the ENF study (IBPF
+    against AIRPF, traced runs), and the 8-D LG workload forward and
+    forward + score."""
     from paper_2312_06484_amd import workloads as W
     out = {}
     dev = "cuda"
@@ -199,6 +200,15 @@ def measure_modes(ctx, torch):
     pmmh.run_mala(sc, pmmh.sv_log_prior, pmmh.sv_grad_log_prior, th0, 2, step, seed=1)
     res = pmmh.run_mala(sc, pmmh.sv_log_prior, pmmh.sv_grad_log_prior, th0, iters, step, seed=2)
     out["pmala_sv_t500_m256_n128_64_chains"] = chain_record(res, fwd_score_bytes(1, 4))
+    # effective number of filters along a run: IBPF (tau = 0) against AIRPF
+    # (tau = 0.3) on the same 400 observations of the 1-D LG model, 256 x 8
+    from paper_2312_06484_amd import studies
+    Te = 400
+    t0 = time.perf_counter()
+    enf = studies.ibpf_vs_airpf(ctx, 0, W.LG1_THETA, W.lg1_data(Te), 256, 8, 3, tau=0.3)
+    out["enf_study_lg1_t400_m256_n8"] = {"seconds": time.perf_counter() - t0,
+                                         "ibpf": enf["ibpf"]["summary"], "airpf": enf["airpf"]["summary"],
+                                         "log_z": {"ibpf": enf["ibpf"]["log_z"], "airpf": enf["airpf"]["log_z"]}}
     out["batched_fwd_score_sv_64_chains"] = mode_record(total, tb, bpp, total_particle_steps=total,
                                                         items_ok=int((ist == 0).sum()), tiling="autotuned")
     t0 = time.perf_counter()
