@@ -1,0 +1,34 @@
+"""A long data record of the 1-D LG model: 200000 observations on 8 islands
+of 16 particles (one block); stages interact at most steps.
+The step index runs past 16 bits in the draw counters, the record ring of
+the pipelined kernel turns over tens of thousands of times and the serial
+kernel's barrier epochs count as high; the stage counts and the per-step
+digests of every ancestor and island map stay bit-exact with the oracle,
+log Zhat to 1e-12 relative, and the untraced (pipelined) run equals the
+traced one."""
+import numpy as np
+import pytest
+
+from paper_2312_06484_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_long_record(orc):
+    from paper_2312_06484_amd import airpf
+    T, m, N, tau, seed = 200000, 8, 16, 0.5, 11
+    y = W.lg1_data(T)
+    P = orc.Problem(orc.LG1, list(W.LG1_THETA), y, m, N, seed)
+    ot = orc.Trace(P, anc=False, pi=False, lpost=False, enf=False, digest=True, logz_inc=False)
+    lo = orc.run(P, tau=tau, store_f32=True, trace=ot)
+    ctx = airpf.Context(0)
+    print("long record", T, m, N, flush=True)
+    gt = airpf.Trace(T, m, N, sstar=True, enf=False, lpost=False, anc=False, pi=False, digest=True)
+    _, lz_t = ctx.run(0, W.LG1_THETA, y, m, N, seed, tau=tau, trace=gt)
+    _, lz = ctx.run(0, W.LG1_THETA, y, m, N, seed, tau=tau)
+    ctx.close()
+    assert lz == lz_t
+    assert abs(lz - lo) <= 1e-12 * abs(lo), (lz, lo)
+    np.testing.assert_array_equal(gt.sstar, ot.sstar)
+    np.testing.assert_array_equal(gt.digest[: 2 * (T - 1)], ot.digest[: 2 * (T - 1)])
+    assert 0 < ot.sstar.mean() < 3
