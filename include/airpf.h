@@ -52,7 +52,8 @@ typedef enum {
   AIRPF_E_DOMAIN = 2,      /* theta outside the model's parameter space */
   AIRPF_E_NOMEM = 3,       /* device workspace could not be allocated */
   AIRPF_E_DEVICE = 4,      /* a HIP call or a kernel failed */
-  AIRPF_E_UNSUPPORTED = 5  /* valid request the library does not implement */
+  AIRPF_E_UNSUPPORTED = 5, /* valid request the library does not implement */
+  AIRPF_E_TOO_LARGE = 6    /* airpf_run_noalloc: the workspace exceeds the fixed scratch */
 } airpf_status;
 
 /* State-space models (concrete instances of the HMM of Section 1.2).
@@ -124,6 +125,23 @@ airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, const double* t
                        int32_t d_theta, const double* y, int64_t T, int32_t m, int32_t N,
                        uint64_t seed, const airpf_options* opt, double* log_z_out,
                        airpf_trace* trace);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): airpf_run
+ * without a trace, whose workspaces (resampled states, island tree, ENF
+ * records, barrier flags, the uploaded observations when y is on the host)
+ * are carved from a fixed device array of 64 MiB that the library holds on
+ * every device it runs on until the process ends.  The call makes no
+ * hipMalloc, hipFree or other allocating call; the context must have been
+ * created beforehand (airpf_ctx_create resolves the array's address on its
+ * device).  A request whose workspace exceeds the array returns
+ * AIRPF_E_TOO_LARGE (*log_z_out NaN), e.g. m*N*d_x*bytes-per-state above
+ * about 32 MiB.  Calls on one device share the array: calls that overlap in
+ * time on one device (several contexts or streams) race; calls serialised on
+ * one stream do not.  Results are bit-identical to airpf_run's. */
+airpf_status airpf_run_noalloc(airpf_ctx* ctx, const airpf_model* model, const double* theta,
+                               int32_t d_theta, const double* y, int64_t T, int32_t m, int32_t N,
+                               uint64_t seed, const airpf_options* opt, double* log_z_out);
 
 /* Score: *log_z_out = log Zhat(theta) (the same value airpf_run returns for
  * the same arguments) and grad_out[d_theta] = the path-space estimate of

@@ -22,11 +22,11 @@ PATHSPACE, PATHWISE = 0, 1
 FLAG_Y_ON_DEVICE = 1
 FLAG_AUTOTUNE = 2
 
-OK, E_INVALID_ARG, E_DOMAIN, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(6)
+OK, E_INVALID_ARG, E_DOMAIN, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_TOO_LARGE = range(7)
 
 # every symbol include/airpf.h declares
-EXPORTS = ["airpf_ctx_create", "airpf_ctx_destroy", "airpf_run", "airpf_score", "airpf_run_batch",
-           "airpf_status_str", "airpf_ctx_last_kernel_ms", "airpf_debug_eval"]
+EXPORTS = ["airpf_ctx_create", "airpf_ctx_destroy", "airpf_run", "airpf_run_noalloc", "airpf_score",
+           "airpf_run_batch", "airpf_status_str", "airpf_ctx_last_kernel_ms", "airpf_debug_eval"]
 
 _dp = C.POINTER(C.c_double)
 _i32p = C.POINTER(C.c_int32)
@@ -85,6 +85,9 @@ def lib():
         L.airpf_run.argtypes = [C.c_void_p, C.POINTER(_Model), _dp, C.c_int32, C.c_void_p, C.c_int64,
                                 C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_Options), _dp,
                                 C.POINTER(_Trace)]
+        L.airpf_run_noalloc.restype = C.c_int
+        L.airpf_run_noalloc.argtypes = [C.c_void_p, C.POINTER(_Model), _dp, C.c_int32, C.c_void_p, C.c_int64,
+                                        C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_Options), _dp]
         L.airpf_score.restype = C.c_int
         L.airpf_score.argtypes = [C.c_void_p, C.POINTER(_Model), _dp, C.c_int32, C.c_void_p, C.c_int64,
                                   C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_Options), _dp, _dp,
@@ -196,6 +199,19 @@ class Context:
                              C.byref(tr) if tr is not None else None)
         if st != OK and raise_on_error:
             raise AirpfError(st, "airpf_run")
+        return st, out.value
+
+    def run_noalloc(self, kind, theta, y, m, N, seed, tau=0.3, fp64=False, dx=1, dy=1, consts=None,
+                    y_device_ptr=None, T=None, raise_on_error=True, resampling=SYSTEMATIC):
+        """airpf_run_noalloc (workspaces in the library's fixed device
+        scratch, nothing allocated): returns (status, log Zhat)."""
+        theta, model, cst, opt, ptr, Tn, keep = self._args(kind, theta, y, tau, fp64, dx, dy, consts,
+                                                           y_device_ptr, T, resampling=resampling)
+        out = C.c_double(np.nan)
+        st = lib().airpf_run_noalloc(self._h, C.byref(model), _p(theta, _dp), theta.size, ptr, Tn, int(m), int(N),
+                                     C.c_uint64(int(seed)), C.byref(opt), C.byref(out))
+        if st != OK and raise_on_error:
+            raise AirpfError(st, "airpf_run_noalloc")
         return st, out.value
 
     def score(self, kind, theta, y, m, N, seed, tau=0.3, fp64=False, dx=1, dy=1, consts=None,

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "airpf.h"
@@ -42,12 +43,40 @@ bool all_finite(const double* p, int64_t n) {
   return true;
 }
 
+// Fixed device scratch of airpf_run_noalloc: every workspace of such a call
+// (resampled states, island tree, ENF records, barrier flags, the record
+// ring, uploaded observations) is carved from this array, so the call
+// allocates nothing.  Each device the library runs on holds its own copy
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// never the device memory: host code uses the per-device address that
+// hipGetSymbolAddress returned (scratch_addr below), never the array's name.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Resolves (once per device, with that device current) the device address of
+// this device's copy of the scratch array; nullptr on failure.
+unsigned char* scratch_addr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[device] = static_cast<unsigned char*>(p);
+  }
+  return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 struct airpf_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   int num_cus = 0;
+  unsigned char* scratch = nullptr;   // this device's copy of the no-allocation scratch array
   hipEvent_t ev[2] = {nullptr, nullptr};
   double last_kernel_ms = 0.0;
   DevBuf x1[2], tree[2], part[2], misc, ybuf;
@@ -71,6 +100,7 @@ extern "C" const char* airpf_status_str(airpf_status s) {
     case AIRPF_E_NOMEM: return "device memory allocation failed";
     case AIRPF_E_DEVICE: return "device error";
     case AIRPF_E_UNSUPPORTED: return "unsupported request";
+    case AIRPF_E_TOO_LARGE: return "workspace exceeds the fixed no-allocation scratch (64 MiB per device)";
   }
   return "unknown status";
 }
@@ -85,7 +115,9 @@ extern "C" airpf_status airpf_ctx_create(int device, void* hip_stream, airpf_ctx
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   if (hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-      hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+      hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess ||
+      (c->scratch = scratch_addr(device)) == nullptr) {
+    for (hipEvent_t e : c->ev) if (e) (void)hipEventDestroy(e);
     delete c;
     return AIRPF_E_DEVICE;
   }
@@ -198,9 +230,12 @@ struct Prepared {
   int gmax = 1;
 };
 
+// fixed != nullptr: every workspace is carved from that device array of
+// kNoallocScratchBytes (airpf_run_noalloc) instead of the context's buffers.
 airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* theta, int32_t d_theta,
                      const double* y, int64_t T, int32_t m, int32_t N, uint64_t seed,
-                     const airpf_options* opt_in, double* log_z_out, int max_blocks, Prepared* P) {
+                     const airpf_options* opt_in, double* log_z_out, int max_blocks, Prepared* P,
+                     unsigned char* fixed = nullptr) {
   set_nan(log_z_out);
   if (!ctx || !model || !theta || !y || !log_z_out) return AIRPF_E_INVALID_ARG;
   if (T < 1 || T > (int64_t(1) << 30) || !is_pow2(m) || N < 1 || N > 2048) return AIRPF_E_INVALID_ARG;
@@ -248,21 +283,43 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   P->gmax = std::min(max_blocks, m);
   // ENF records: (log2(m/G) + 1) levels of G blocks, largest at G = gmax
   const size_t part_words = 3 * size_t(ilog2(m / P->gmax) + 1) * size_t(P->gmax);
-  for (int p = 0; p < 2; ++p) {
-    ST_OK(ctx->x1[p].ensure(nstate));
-    ST_OK(ctx->tree[p].ensure(sizeof(double) * 2 * size_t(m)));
-    ST_OK(ctx->part[p].ensure(sizeof(double) * part_words));
-    a.x1[p] = ctx->x1[p].p;
-    a.tree[p] = static_cast<double*>(ctx->tree[p].p);
-    a.part[p] = static_cast<double*>(ctx->part[p].p);
-  }
   // misc: [0,8) log Zhat, [8,12) status, [64, 64 + 4G) barrier flags, then
   // the level-1 record ring of the pipelined kernel (kRingCopies copies of
   // 9G doubles, G <= 256)
   const size_t ring_off = (64 + 4 * size_t(P->gmax) + 255) & ~size_t(255);
   const int gring = std::min(P->gmax, 256);
-  ST_OK(ctx->misc.ensure(ring_off + 8 * 9 * size_t(gring) * airpf::kRingCopies));
-  unsigned char* misc = static_cast<unsigned char*>(ctx->misc.p);
+  const size_t misc_bytes = ring_off + 8 * 9 * size_t(gring) * airpf::kRingCopies;
+  const size_t y_bytes = sizeof(double) * size_t(T) * P->dy;
+  unsigned char* misc = nullptr;
+  void* ybuf = nullptr;
+  if (fixed) {
+    // one 256-byte aligned piece after another; nothing is allocated
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = (off + 255) & ~size_t(255); off = o + bytes; return fixed + o; };
+    for (int p = 0; p < 2; ++p) {
+      a.x1[p] = take(nstate);
+      a.tree[p] = reinterpret_cast<double*>(take(sizeof(double) * 2 * size_t(m)));
+      a.part[p] = reinterpret_cast<double*>(take(sizeof(double) * part_words));
+    }
+    misc = take(misc_bytes);
+    if (!y_dev) ybuf = take(y_bytes);
+    if (off > kNoallocScratchBytes) return AIRPF_E_TOO_LARGE;
+  } else {
+    for (int p = 0; p < 2; ++p) {
+      ST_OK(ctx->x1[p].ensure(nstate));
+      ST_OK(ctx->tree[p].ensure(sizeof(double) * 2 * size_t(m)));
+      ST_OK(ctx->part[p].ensure(sizeof(double) * part_words));
+      a.x1[p] = ctx->x1[p].p;
+      a.tree[p] = static_cast<double*>(ctx->tree[p].p);
+      a.part[p] = static_cast<double*>(ctx->part[p].p);
+    }
+    ST_OK(ctx->misc.ensure(misc_bytes));
+    misc = static_cast<unsigned char*>(ctx->misc.p);
+    if (!y_dev) {
+      ST_OK(ctx->ybuf.ensure(y_bytes));
+      ybuf = ctx->ybuf.p;
+    }
+  }
   a.out_logz = reinterpret_cast<double*>(misc);
   a.status = reinterpret_cast<int*>(misc + 8);
   a.bar = reinterpret_cast<unsigned*>(misc + 64);
@@ -270,9 +327,8 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   if (y_dev) {
     a.y = y;
   } else {
-    ST_OK(ctx->ybuf.ensure(sizeof(double) * size_t(T) * P->dy));
-    HIP_OK(hipMemcpyAsync(ctx->ybuf.p, y, sizeof(double) * size_t(T) * P->dy, hipMemcpyHostToDevice, s));
-    a.y = static_cast<const double*>(ctx->ybuf.p);
+    HIP_OK(hipMemcpyAsync(ybuf, y, y_bytes, hipMemcpyHostToDevice, s));
+    a.y = static_cast<const double*>(ybuf);
   }
   HIP_OK(airpf::fill_u32(misc, 0u, 16 + int64_t(P->gmax), s));
   HIP_OK(airpf::fill_u32(misc + ring_off, 0xFFFFFFFFu, 2 * 9 * int64_t(gring) * airpf::kRingCopies, s));   // NaN
@@ -347,6 +403,22 @@ extern "C" airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, cons
   if (airpf::launch_forward(P.L, P.a, &P.plan) != hipSuccess) return AIRPF_E_DEVICE;
   HIP_OK(hipEventRecord(ctx->ev[1], ctx->stream));
   ST_OK(copy_trace(ctx, P, trace));
+  return finish(ctx, P, log_z_out);
+}
+
+// airpf_run with every workspace in the device's fixed scratch array: no
+// hipMalloc, hipFree or allocating library call.  Calls that overlap on one
+// device share (and race on) that array.
+extern "C" airpf_status airpf_run_noalloc(airpf_ctx* ctx, const airpf_model* model, const double* theta,
+                                          int32_t d_theta, const double* y, int64_t T, int32_t m, int32_t N,
+                                          uint64_t seed, const airpf_options* opt_in, double* log_z_out) {
+  if (!ctx) { set_nan(log_z_out); return AIRPF_E_INVALID_ARG; }
+  Prepared P;
+  ST_OK(prepare(ctx, model, theta, d_theta, y, T, m, N, seed, opt_in, log_z_out, kMaxBlocks, &P, ctx->scratch));
+  P.L.plan_only = 0;
+  HIP_OK(hipEventRecord(ctx->ev[0], ctx->stream));
+  if (airpf::launch_forward(P.L, P.a, &P.plan) != hipSuccess) return AIRPF_E_DEVICE;
+  HIP_OK(hipEventRecord(ctx->ev[1], ctx->stream));
   return finish(ctx, P, log_z_out);
 }
 
