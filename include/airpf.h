@@ -96,7 +96,7 @@ typedef struct {
                          AIRPF_E_INVALID_ARG */
   int32_t precision;  /* storage precision of the particle state; all particle
                          arithmetic is double precision either way */
-  int32_t score_mode; /* airpf_score_mode (airpf_score only) */
+  int32_t score_mode; /* airpf_score_mode (airpf_score, airpf_run_batch with scores) */
   int32_t ckpt_every; /* checkpoint interval of the score's recomputation (0: auto) */
   uint32_t flags;     /* AIRPF_FLAG_* */
 } airpf_options;
@@ -144,18 +144,23 @@ airpf_status airpf_run_noalloc(airpf_ctx* ctx, const airpf_model* model, const d
                                uint64_t seed, const airpf_options* opt, double* log_z_out);
 
 /* Score: *log_z_out = log Zhat(theta) (the same value airpf_run returns for
- * the same arguments) and grad_out[d_theta] = the path-space estimate of
- * d log Z / d theta: the final-weight average over final particles of the
- * derivative of the summed log g along each particle's ancestral path, with
- * the noise and every discrete decision of the run held fixed and the
- * fixed-point weights read as exact (the derivative is not part of the
- * paper; it is the score a gradient-based PMCMC proposal consumes).
+ * the same arguments) and grad_out[d_theta] = an estimate of
+ * d log Z / d theta with the noise and every discrete decision of the run
+ * held fixed and the fixed-point weights read as exact (the derivative is
+ * not part of the paper; it is the score a gradient-based PMCMC proposal
+ * consumes).  opt->score_mode picks the estimator:
+ *   AIRPF_PATHSPACE  the final-weight average over final particles of the
+ *                    derivative of the summed log g along each particle's
+ *                    ancestral path (consistent for d log Z / d theta);
+ *   AIRPF_PATHWISE   the derivative of the run's own log Zhat (the
+ *                    estimator of Algorithm 1's gamma^N_T(1)) with the
+ *                    ancestors, island maps and stage counts fixed.
  * opt->ckpt_every = K: the forward pass keeps a checkpoint every K steps and
  * the reverse pass recomputes the particle history one segment of K steps at
  * a time (K = 0: the whole history is kept when it fits the workspace
  * budget, otherwise K = ceil(sqrt(T))).  Supported: N <= 1024 (LG1, SV),
- * N <= 512 (LGD); opt->score_mode AIRPF_PATHWISE returns
- * AIRPF_E_UNSUPPORTED.  grad_out is host memory.  A run in
+ * N <= 512 (LGD); any other score_mode is AIRPF_E_INVALID_ARG.  grad_out is
+ * host memory.  A run in
  * which every island's weight vanishes returns AIRPF_OK, log Zhat = -inf and
  * a zero score (no reverse pass is made; airpf_run_batch does the same per
  * problem). */

@@ -7,8 +7,10 @@ or ``python paper_2312_06484_amd/build.py``); there is no fallback path.
 Naming follows the paper: m islands (filters), N particles per island (the
 paper's M), T observations, tau the ENF threshold of Algorithm 1.
 """
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -61,6 +63,18 @@ class _Trace(C.Structure):
 
 
 _lib = None
+_live = weakref.WeakSet()          # open contexts, closed at interpreter exit
+
+
+def _close_all():
+    """At interpreter exit: destroy every open context (each synchronises its
+    stream first), so no work of this library is in flight when the process
+    tears down the HIP runtime."""
+    for ctx in list(_live):
+        try:
+            ctx.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -100,6 +114,7 @@ def lib():
         L.airpf_debug_eval.restype = C.c_int
         L.airpf_debug_eval.argtypes = [C.c_void_p, C.c_int32, C.c_int64, _dp, _u32p, _dp, _dp, _u32p]
         _lib = L
+        atexit.register(_close_all)
     return _lib
 
 
@@ -138,6 +153,7 @@ class Context:
         st = lib().airpf_ctx_create(int(device), C.c_void_p(stream) if stream else None, C.byref(self._h))
         if st != OK:
             raise AirpfError(st, "airpf_ctx_create")
+        _live.add(self)
 
     def close(self):
         if self._h:
@@ -231,7 +247,8 @@ class Context:
         return st, out.value, grad
 
     def run_batch(self, kind, problems, tau=0.3, fp64=False, dx=1, dy=1, consts=None, want_score=False,
-                  ckpt_every=0, y_on_device=False, autotune=False, raise_on_error=True, resampling=SYSTEMATIC):
+                  ckpt_every=0, y_on_device=False, autotune=False, raise_on_error=True, resampling=SYSTEMATIC,
+                  score_mode=PATHSPACE):
         """airpf_run_batch.  ``problems``: dicts with theta, y (host array, or a
         device pointer int with ``y_on_device`` and then T), m, N, seed;
         ``autotune`` sets AIRPF_FLAG_AUTOTUNE (measured tiling, cached per
@@ -246,7 +263,7 @@ class Context:
         model.n_consts = 0 if cst is None else cst.size
         opt = _Options()
         opt.tau, opt.resampling, opt.precision = float(tau), int(resampling), FP64 if fp64 else FP32
-        opt.score_mode, opt.ckpt_every = PATHSPACE, int(ckpt_every)
+        opt.score_mode, opt.ckpt_every = int(score_mode), int(ckpt_every)
         opt.flags = (FLAG_Y_ON_DEVICE if y_on_device else 0) | (FLAG_AUTOTUNE if autotune else 0)
         arr = (_Problem * max(B, 1))()
         keep = []

@@ -81,7 +81,7 @@ struct airpf_ctx {
   double last_kernel_ms = 0.0;
   DevBuf x1[2], tree[2], part[2], misc, ybuf;
   DevBuf t_sstar, t_enf, t_lpost, t_anc, t_pi, t_dig;
-  DevBuf s_pi, s_sstar, s_lpre, s_ckx, s_ckL, s_recx, s_reca, s_lam[2], s_del[2], s_grad;
+  DevBuf s_pi, s_sstar, s_lpre, s_ckx, s_ckL, s_recx, s_reca, s_lam[2], s_del[2], s_grad, s_nu;
   DevBuf dbg_in, dbg_in32, dbg_out, dbg_out2, dbg_out32;
   DevBuf batch;
   // tiler cost ratios (pass time / step overhead) measured by AIRPF_FLAG_AUTOTUNE,
@@ -133,7 +133,7 @@ extern "C" airpf_status airpf_ctx_destroy(airpf_ctx* c) {
                     &c->ybuf, &c->t_sstar, &c->t_enf, &c->t_lpost, &c->t_anc, &c->t_pi, &c->t_dig,
                     &c->dbg_in, &c->dbg_in32, &c->dbg_out, &c->dbg_out2, &c->dbg_out32, &c->s_pi,
                     &c->s_sstar, &c->s_lpre, &c->s_ckx, &c->s_ckL, &c->s_recx, &c->s_reca, &c->s_lam[0],
-                    &c->s_lam[1], &c->s_del[0], &c->s_del[1], &c->s_grad, &c->batch})
+                    &c->s_lam[1], &c->s_del[0], &c->s_del[1], &c->s_grad, &c->s_nu, &c->batch})
     b->release();
   for (hipEvent_t e : c->ev) if (e) (void)hipEventDestroy(e);
   delete c;
@@ -429,10 +429,12 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   if (grad_out) for (int i = 0; i < d_theta; ++i) grad_out[i] = std::nan("");
   if (!grad_out) { set_nan(log_z_out); return AIRPF_E_INVALID_ARG; }
   const airpf_options opt = opt_in ? *opt_in : default_options();
-  if (opt.score_mode == AIRPF_PATHWISE) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
+  if ((opt.score_mode != AIRPF_PATHSPACE && opt.score_mode != AIRPF_PATHWISE) || opt.ckpt_every < 0) {
+    set_nan(log_z_out);
+    return AIRPF_E_INVALID_ARG;
+  }
   // the reverse pass finds a particle's children as a run of sorted ancestors
   if (opt.resampling == AIRPF_MULTINOMIAL) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
-  if (opt.score_mode != AIRPF_PATHSPACE || opt.ckpt_every < 0) { set_nan(log_z_out); return AIRPF_E_INVALID_ARG; }
   if (model && ((model->kind == AIRPF_LGD && N > 512) || (model->kind != AIRPF_LGD && N > 1024))) {
     set_nan(log_z_out);
     return AIRPF_E_UNSUPPORTED;
@@ -490,6 +492,7 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   }
   const int Pn = d_theta;
   ST_OK(ctx->s_grad.ensure(8 * size_t(m) * Pn + 8 * 64));
+  ST_OK(ctx->s_nu.ensure(8 * 2 * size_t(m)));
 
   // forward: keep island maps, stage counts, entering weights, checkpoints;
   // with a single segment the particle history is recorded right away
@@ -547,6 +550,10 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   b.G = bplan.G; b.dy = P.dy; b.seed = seed;
   b.log_mN = std::log(static_cast<double>(m) * static_cast<double>(N));
   b.c_log = a.cst_q + 40.0 * std::log(2.0) + std::log(static_cast<double>(N));
+  b.log_N = std::log(static_cast<double>(N));
+  b.pathwise = opt.score_mode == AIRPF_PATHWISE ? 1 : 0;
+  b.nu[0] = static_cast<double*>(ctx->s_nu.p);
+  b.nu[1] = b.nu[0] + m;
   b.logz = a.out_logz;
   b.rec_x = ctx->s_recx.p;
   b.rec_anc = static_cast<const uint16_t*>(ctx->s_reca.p);
@@ -650,7 +657,7 @@ struct Item {
   const double* y_dev = nullptr;
   size_t o_y = 0, o_x1[2] = {0, 0}, o_tree[2] = {0, 0}, o_part[2] = {0, 0}, o_flags = 0;
   size_t o_pi = 0, o_sstar = 0, o_lpre = 0, o_ckx = 0, o_ckL = 0, o_recx = 0, o_reca = 0;
-  size_t o_lam[2] = {0, 0}, o_del[2] = {0, 0}, o_gisl = 0, o_gsum = 0;
+  size_t o_lam[2] = {0, 0}, o_del[2] = {0, 0}, o_gisl = 0, o_gsum = 0, o_nu = 0;
 };
 
 // Tiler.  Modelled time of a problem over `steps` filter steps on G blocks:
@@ -710,8 +717,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   // multinomial draws: forward only (the reverse pass needs sorted ancestors)
   if (opt.resampling == AIRPF_MULTINOMIAL && want_score) return AIRPF_E_UNSUPPORTED;
   const int mult = opt.resampling == AIRPF_MULTINOMIAL ? 1 : 0;
-  if (want_score && opt.score_mode != AIRPF_PATHSPACE)
-    return opt.score_mode == AIRPF_PATHWISE ? AIRPF_E_UNSUPPORTED : AIRPF_E_INVALID_ARG;
+  if (want_score && opt.score_mode != AIRPF_PATHSPACE && opt.score_mode != AIRPF_PATHWISE) return AIRPF_E_INVALID_ARG;
   const bool y_dev = (opt.flags & AIRPF_FLAG_Y_ON_DEVICE) != 0;
   const bool fp64 = opt.precision == AIRPF_FP64;
   const size_t store = fp64 ? 8 : 4;
@@ -827,6 +833,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
         it.o_del[p] = ar.take(mN * store);
       }
       it.o_gisl = ar.take(8 * size_t(it.m) * Pn);
+      it.o_nu = ar.take(8 * 2 * size_t(it.m));
       it.o_gsum = ar.take(8 * size_t(Pn));
     }
   }
@@ -897,6 +904,10 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
         b.dy = dy; b.seed = it.seed;
         b.log_mN = std::log(static_cast<double>(it.m) * static_cast<double>(it.N));
         b.c_log = it.cst_q + 40.0 * std::log(2.0) + std::log(static_cast<double>(it.N));
+        b.log_N = std::log(static_cast<double>(it.N));
+        b.pathwise = opt.score_mode == AIRPF_PATHWISE ? 1 : 0;
+        b.nu[0] = static_cast<double*>(at(it.o_nu));
+        b.nu[1] = b.nu[0] + it.m;
         b.logz = static_cast<const double*>(at(o_logz)) + (&it - items.data());
         b.rec_x = at(it.o_recx);
         b.rec_anc = static_cast<const uint16_t*>(at(it.o_reca));

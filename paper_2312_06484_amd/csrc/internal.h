@@ -62,6 +62,9 @@ struct BwdArgs {
   int m, N, S, TP, c, lc, G, dy;
   uint64_t seed;
   double log_mN, c_log;       // log(m N) and the constant of log g
+  double log_N;               // log N
+  int pathwise;               // seed: 0 path-space (descendants' final weights), 1 pathwise (island weights)
+  double* nu[2];              // pathwise: [m] d log Zhat / d (island log-weight after step n's weighting), by step parity
   const double* logz;         // [1] log Zhat of the forward run (device)
   int64_t n_lo, n_hi;
   const void* rec_x;          // Store*, [(n_hi-n_lo)][m*N*DX], index n - n_lo

@@ -10,6 +10,15 @@
 //               D_{T-1} = Wbar;  D_n(k,i) = sum over children (k', j) of D_{n+1}(k', j)
 //   lam_n(k,i) = D_n(k,i) dlw/dx (x_n^{k,i}) + sum_children (dF/dx)^T lam_{n+1}(k', j)
 //   G += D_n dlogg/dtheta + sum over mutations lam_{n+1} . dF/dtheta + lam_0 . dx_0/dtheta
+// The pathwise seed (the derivative of the run's own log Zhat with every
+// decision held fixed) replaces D_n by the adjoint of log g_n(x_n^{k,i})
+// through the island weights: with nu_{n,k} = d log Zhat / d L_{n,k}, L_{n,k}
+// island k's log-weight after step n's weighting,
+//   D_n(k,i)  = nu_{n,k} softmax_i(log g_n^{k,.}),
+//   nu_{n,k}  = (sum of nu_{n+1,k'} over k's aligned 2^{s*_n}-block) W_{n,k} / (block's sum of W_n)
+// (the entering weight of step n+1 is the block mean of the W_n, the
+// composite of the stages' pair means), nu_{T-1,k} = W_{T-1,k} / sum W_{T-1};
+// lam and the theta terms follow as above.  At T-1 both seeds coincide.
 // Children of (n, k, i): slots j of islands k' with pi_n(k') = k and
 // a_{n,k}(j) = i.  The islands with pi_n(k') = k all lie in k's aligned
 // 2^{s*_n}-block, so each source island scans that block (ballot, ascending
@@ -250,8 +259,10 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
         const int blo = k & ~(B - 1);
         const Store* lam_in = static_cast<const Store*>(a.lam[npar]);
         const Store* del_in = static_cast<const Store*>(a.del[npar]);
+        double nu_acc = 0.0;                     // pathwise: this lane's part of the block sum of nu_{n+1}
         for (int it = 0; it < B; it += W) {
           const int cand = blo + it + sl_lane;
+          if (a.pathwise && active && it + sl_lane < B) nu_acc += get(a.nu[npar] + cand);
           const bool match = active && (it + sl_lane < B) &&
                              (pi_cached ? s_pi[cand - R_lo] : a.pi_all[n * m + cand]) == k;
           const unsigned long long ball = __ballot(match);
@@ -328,6 +339,26 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
             D[r] = tot[DX];
           }
         }
+        if (a.pathwise) {
+          // D_n(k,i) = (block sum of nu_{n+1}) W_{n,k} softmax_i / (block sum of W_n):
+          // exp(Lpre_{n,k} + log g_i - log N - Lpre_{n+1,k} - s* log 2), the block
+          // mean of the W_n being the entering weight of step n+1
+          const double nuB = team_sum_f64(nu_acc, W, red_d);
+          const double lpre = a.lpre_all[n * m + k], lnext = a.lpre_all[(n + 1) * m + k];
+          const double sh = a.c_log - a.log_N - lnext - static_cast<double>(a.sstar_all[n]) * kLn2;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r)
+            D[r] = (active && j0 + r < N && lw[r] != ninf() && lpre != ninf() && lnext != ninf())
+                       ? nuB * dexp((lpre + lw[r]) + sh) : 0.0;
+        }
+      }
+      if (a.pathwise) {
+        // nu_{n,k} = sum_i D_n(k,i), read by step n-1
+        double dsum = 0.0;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) dsum += D[r];
+        dsum = team_sum_f64(dsum, TP, red_d);
+        if (lane == 0 && active) put(a.nu[par] + k, dsum);
       }
 
       // ---- the weighting terms of step n ----

@@ -42,13 +42,14 @@ def test_batch_forward_matches_single(ctx, fp64):
         assert v == ref
 
 
-@pytest.mark.parametrize("K", [0, 7])
-def test_batch_score_matches_single(ctx, K):
+@pytest.mark.parametrize("K,mode", [(0, 0), (7, 0), (0, 1), (7, 1)])
+def test_batch_score_matches_single(ctx, K, mode):
     items = sv_batch(9, seed=2)
-    st, lz, gr, ist = ctx.run_batch(1, items, tau=0.6, want_score=True, ckpt_every=K)
+    st, lz, gr, ist = ctx.run_batch(1, items, tau=0.6, want_score=True, ckpt_every=K, score_mode=mode)
     assert (ist == 0).all()
     for it, v, g in zip(items, lz, gr):
-        _, ref, gref = ctx.score(1, it["theta"], it["y"], it["m"], it["N"], it["seed"], tau=0.6, ckpt_every=K)
+        _, ref, gref = ctx.score(1, it["theta"], it["y"], it["m"], it["N"], it["seed"], tau=0.6, ckpt_every=K,
+                                 score_mode=mode)
         assert v == ref
         assert np.array_equal(g, gref)
 
