@@ -70,7 +70,7 @@ def cpu_baseline(wl, y, gpu_ctx, budget_steps):
     P = orc.Problem(kinds[wl["kind"]], wl["theta"], ys, wl["m"], wl["N"], 1, dx=wl["dx"], dy=wl["dy"],
                     consts=wl["consts"])
     t0 = time.perf_counter()
-    lo = orc.run(P, tau=0.3, store_f32=wl["f32"])
+    lo = orc.run(P, tau=0.3, f32=wl["f32"])
     dt = time.perf_counter() - t0
     _, lg = gpu_ctx.run(wl["kind"], wl["theta"], ys, wl["m"], wl["N"], 1, tau=0.3, fp64=not wl["f32"],
                         dx=wl["dx"], dy=wl["dy"], consts=wl["consts"])

@@ -35,7 +35,7 @@ class _Problem(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("scheme", C.c_int32),
-                ("store_f32", C.c_int32), ("replay", C.c_int32),
+                ("f32", C.c_int32), ("replay", C.c_int32),
                 ("exact_weights", C.c_int32)]
 
 
@@ -59,6 +59,11 @@ def lib():
         L.orc_log.restype = C.c_double; L.orc_log.argtypes = [C.c_double]
         L.orc_cossin2pi.argtypes = [C.c_double, _dp, _dp]
         L.orc_boxmuller.argtypes = [C.c_uint32, C.c_uint32, _dp, _dp]
+        L.orc_expf.restype = C.c_float; L.orc_expf.argtypes = [C.c_float]
+        L.orc_logf.restype = C.c_float; L.orc_logf.argtypes = [C.c_float]
+        L.orc_cossin2pif.argtypes = [C.c_float, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.orc_boxmullerf.argtypes = [C.c_uint32, C.c_uint32, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.orc_island_normalsf.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_int64, _dp]
         L.orc_u53.restype = C.c_double; L.orc_u53.argtypes = [C.c_uint32, C.c_uint32]
         L.orc_bounded.restype = C.c_uint64
         L.orc_bounded.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64]
@@ -111,6 +116,33 @@ def boxmuller(wa, wb):
     a, b = C.c_double(), C.c_double()
     lib().orc_boxmuller(int(wa), int(wb), C.byref(a), C.byref(b))
     return a.value, b.value
+
+
+def expf(x):
+    """binary32 counterpart of exp (runs with binary32 particles)"""
+    return lib().orc_expf(float(x))
+
+
+def logf(x):
+    return lib().orc_logf(float(x))
+
+
+def cossin2pif(v):
+    c, s = C.c_float(), C.c_float()
+    lib().orc_cossin2pif(float(v), C.byref(c), C.byref(s))
+    return c.value, s.value
+
+
+def boxmullerf(wa, wb):
+    a, b = C.c_float(), C.c_float()
+    lib().orc_boxmullerf(int(wa), int(wb), C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def island_normalsf(seed, n, k, count):
+    z = np.zeros(count, dtype=np.float64)
+    lib().orc_island_normalsf(int(seed), int(n), int(k), int(count), _ptr(z, _dp))
+    return z
 
 
 def u53(hi, lo):
@@ -204,22 +236,24 @@ class Trace:
         return t
 
 
-def _opts(tau, scheme, store_f32, replay=0):
+def _opts(tau, scheme, f32, replay=0):
     o = _Opts()
-    o.tau, o.scheme, o.store_f32, o.replay, o.exact_weights = float(tau), int(scheme), int(store_f32), int(replay), 0
+    o.tau, o.scheme, o.f32, o.replay, o.exact_weights = float(tau), int(scheme), int(f32), int(replay), 0
     return o
 
 
-def run(prob, tau=0.3, scheme=0, store_f32=False, trace=None):
-    """Forward AIRPF; returns log Zhat (fixed-point weights)."""
-    p, o = prob._c(), _opts(tau, scheme, store_f32)
+def run(prob, tau=0.3, scheme=0, f32=False, trace=None):
+    """Forward AIRPF; returns log Zhat (fixed-point weights).  ``f32``:
+    binary32 particles (state, normals, model, weights; island log-weights
+    and log Zhat in double)."""
+    p, o = prob._c(), _opts(tau, scheme, f32)
     t = trace._c() if trace is not None else None
     return lib().orc_airpf_run(C.byref(p), C.byref(o), C.byref(t) if t is not None else None)
 
 
-def score(prob, tau=0.3, scheme=0, store_f32=False, trace=None):
+def score(prob, tau=0.3, scheme=0, f32=False, trace=None):
     """Forward-mode score; returns (log Zhat, grad_pathwise, grad_pathspace)."""
-    p, o = prob._c(), _opts(tau, scheme, store_f32)
+    p, o = prob._c(), _opts(tau, scheme, f32)
     t = trace._c() if trace is not None else None
     gpw = np.zeros(prob.theta.size)
     gps = np.zeros(prob.theta.size)
@@ -228,13 +262,13 @@ def score(prob, tau=0.3, scheme=0, store_f32=False, trace=None):
     return lz, gpw, gps
 
 
-def frozen(prob, trace, store_f32=False):
+def frozen(prob, trace, f32=False):
     """Replay the genealogy in ``trace`` at prob.theta with exact weights.
 
     Returns (F, S, logw): F the exact-weight log Zhat along that genealogy,
     S[k*N+i] the summed log g along final particle (k,i)'s ancestral path and
     logw[k*N+i] its unnormalised final log-weight."""
-    p, o = prob._c(), _opts(0.0, 0, store_f32, replay=1)
+    p, o = prob._c(), _opts(0.0, 0, f32, replay=1)
     t = trace._c()
     S = np.zeros(prob.m * prob.N)
     lw = np.zeros(prob.m * prob.N)
@@ -242,9 +276,9 @@ def frozen(prob, trace, store_f32=False):
     return F, S, lw
 
 
-def bpf(prob, k=0, store_f32=False, want_anc=False):
+def bpf(prob, k=0, f32=False, want_anc=False):
     """Textbook bootstrap filter on island k's draws; returns (loglik, anc)."""
     p = prob._c()
     a = np.zeros(prob.T * prob.N, dtype=np.int32) if want_anc else None
-    ll = lib().orc_bpf_run(C.byref(p), int(k), int(store_f32), _ptr(a, _i32p))
+    ll = lib().orc_bpf_run(C.byref(p), int(k), int(f32), _ptr(a, _i32p))
     return ll, a

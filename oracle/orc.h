@@ -36,7 +36,9 @@ typedef struct {
 typedef struct {
   double tau;            /* ENF threshold; <= 1/m never interacts           */
   int32_t scheme;        /* 0 systematic, 1 multinomial                     */
-  int32_t store_f32;     /* 1: state rounded to binary32 when stored         */
+  int32_t f32;           /* 1: binary32 particles: state, normals, model and
+                            weights in single precision (island log-weights
+                            and log Zhat stay double)                        */
   int32_t replay;        /* 1: ancestors, island maps, stage counts read
                             from the trace instead of being drawn            */
   int32_t exact_weights; /* 1: island weights from the unquantised sum       */
@@ -62,12 +64,19 @@ uint64_t orc_bounded(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
                      uint32_t tag, uint64_t Q);
 void orc_island_normals(uint64_t seed, int64_t n, int32_t k, int64_t count,
                         double* z);
+void orc_island_normalsf(uint64_t seed, int64_t n, int32_t k, int64_t count,
+                         double* z);
 
 /* ---- own double-precision elementary functions (orc_math.c) ---- */
 double orc_exp(double x);
 double orc_log(double x);
 void orc_cossin2pi(double v, double* c, double* s);
 void orc_boxmuller(uint32_t wa, uint32_t wb, double* z0, double* z1);
+/* binary32 counterparts (runs with single-precision particle arithmetic) */
+float orc_expf(float x);
+float orc_logf(float x);
+void orc_cossin2pif(float v, float* c, float* s);
+void orc_boxmullerf(uint32_t wa, uint32_t wb, float* z0, float* z1);
 
 /* ---- fixed-point resampling (orc_airpf.c) ---- */
 void orc_quantise(const double* lw, int32_t N, uint64_t* q, double* mx);

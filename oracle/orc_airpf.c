@@ -167,7 +167,7 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
   const int64_t T = P->T;
   const int S = ilog2(m);
   orc_model M;
-  orc_model_setup(&M, P, O->store_f32);
+  orc_model_setup(&M, P, O->f32);
   const int nd = orc_model_noise_dim(&M);
   const int Pn = P->d_theta;
   const int want_score = so && (so->grad_pathwise || so->grad_pathspace);
@@ -234,7 +234,7 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
       for (int32_t j = 0; j < N; ++j)
         lwk[j] = nan_to_ninf(orc_model_logpot(&M, x + ((int64_t)k * N + j) * dx, yn));
       double mx;
-      orc_quantise(lwk, N, q + (int64_t)k * N, &mx);
+      orc_model_quantise(&M, lwk, N, q + (int64_t)k * N, &mx);
       uint64_t Q = 0;
       double se = 0.0;
       for (int32_t j = 0; j < N; ++j) {

@@ -25,13 +25,13 @@ static int64_t slots_below(uint64_t B, uint64_t U, uint64_t Q) {
   return (int64_t)((B - U + Q - 1) / Q);
 }
 
-double orc_bpf_run(const orc_problem* P, int32_t k, int32_t store_f32, int32_t* anc_out) {
+double orc_bpf_run(const orc_problem* P, int32_t k, int32_t f32, int32_t* anc_out) {
   if (P->N < 1 || P->N > 2048 || P->T < 1 || P->dx < 1 || P->dx > ORC_MAX_DX ||
       P->dy < 1 || P->dy > ORC_MAX_DY)
     return NAN;
   const int32_t N = P->N, dx = P->dx, dy = P->dy;
   orc_model Mo;
-  orc_model_setup(&Mo, P, store_f32);
+  orc_model_setup(&Mo, P, f32);
   const int nd = orc_model_noise_dim(&Mo);
   double* x = malloc(sizeof(double) * N * dx);
   double* xn = malloc(sizeof(double) * N * dx);
@@ -44,18 +44,15 @@ double orc_bpf_run(const orc_problem* P, int32_t k, int32_t store_f32, int32_t* 
   double ll = 0.0;
   const double cst = Mo.c_log - 40.0 * log(2.0) - log((double)N);
   for (int64_t n = 0; n < P->T; ++n) {
-    double mx = -INFINITY;
     for (int32_t j = 0; j < N; ++j) {
       double v = orc_model_logpot(&Mo, x + j * dx, P->y + n * dy);
       if (v != v) v = -INFINITY;
       lw[j] = v;
-      if (v > mx) mx = v;
     }
+    double mx;
+    orc_model_quantise(&Mo, lw, N, q, &mx);
     uint64_t Q = 0;
-    for (int32_t j = 0; j < N; ++j) {
-      q[j] = (mx == -INFINITY) ? 0 : (uint64_t)(orc_exp(lw[j] - mx) * 0x1p40);
-      Q += q[j];
-    }
+    for (int32_t j = 0; j < N; ++j) Q += q[j];
     if (Q == 0) { ll = -INFINITY; break; }
     ll = ll + ((mx + orc_log((double)Q)) + cst);
     if (n == P->T - 1) break;

@@ -134,3 +134,95 @@ void orc_boxmuller(uint32_t wa, uint32_t wb, double* z0, double* z1) {
   *z0 = r * c;
   *z1 = r * s;
 }
+
+/* ------------------------------------------------------------------------
+ * Binary32 counterparts, for runs whose particle arithmetic is single
+ * precision (state, normals, model, weights).  Same methods with the
+ * polynomials cut to single-precision accuracy, every operation a correctly
+ * rounded IEEE binary32 +, -, *, /, sqrt, fmaf or rintf:
+ *   expf : Cody-Waite with a 15-bit ln2 head (k ln2_hi exact for |k| < 512),
+ *          e^r = 1 + (r + r^2 Q(r)), Q of degree 5 (1/2! .. 1/7!) by
+ *          Estrin; the scaling 2^k is exact because results below 2^-126
+ *          are returned as 0 (k < -125) and k > 127 overflows to +inf.
+ *   logf : x = 2^e f, f in [sqrt(2)/2, sqrt(2)], 2 atanh(s) to s^9.
+ *   cos/sin(2 pi v): quarter-turn reduction, sin to th^9, cos to th^10.
+ * Box-Muller: u1 = fmaf((float)wa, 2^-32, 2^-33), v = (float)wb 2^-32
+ * ((float) of a 32-bit word rounds to nearest even), r = sqrtf(-2 logf u1).
+ * Accuracy against libm: within a couple of binary32 ulp (tests).
+ * ------------------------------------------------------------------------ */
+
+static float bits_to_float(uint32_t b) { float f; memcpy(&f, &b, 4); return f; }
+static uint32_t float_to_bits(float f) { uint32_t b; memcpy(&b, &f, 4); return b; }
+
+float orc_expf(float x) {
+  if (x != x) return x;
+  const float kf = rintf(x * 0x1.715476p+0f);          /* x / ln 2           */
+  float r = fmaf(-kf, 0x1.62e400p-1f, x);              /* ln2 head, 15 bits  */
+  r = fmaf(-kf, 0x1.7f7d1cp-20f, r);                   /* ln2 tail           */
+  const float r2 = r * r, r4 = r2 * r2;
+  const float q0 = fmaf(0x1.555556p-3f, r, 0x1.000000p-1f);    /* 1/3!, 1/2! */
+  const float q1 = fmaf(0x1.111112p-7f, r, 0x1.555556p-5f);    /* 1/5!, 1/4! */
+  const float q2 = fmaf(0x1.a01a02p-13f, r, 0x1.6c16c2p-10f);  /* 1/7!, 1/6! */
+  const float Q = fmaf(q2, r4, fmaf(q1, r2, q0));
+  const float p = 1.0f + fmaf(r2, Q, r);
+  if (kf > 127.0f) return INFINITY;
+  if (kf < -125.0f) return 0.0f;
+  return ldexpf(p, (int)kf);                           /* exact: normal range */
+}
+
+float orc_logf(float x) {
+  if (x != x || x < 0.0f) return NAN;
+  if (x == 0.0f) return -INFINITY;
+  if (x == INFINITY) return INFINITY;
+  int e = 0;
+  if (x < 0x1p-126f) { x = x * 0x1p+24f; e = -24; }    /* subnormal input    */
+  const uint32_t b = float_to_bits(x);
+  e += (int)((b >> 23) & 0xff) - 127;
+  float f = bits_to_float((b & 0x007fffffu) | 0x3f800000u);
+  if (f > 0x1.6a09e6p+0f) { f = f * 0.5f; e += 1; }     /* f > sqrt(2)        */
+  const float s = (f - 1.0f) / (f + 1.0f);
+  const float z = s * s;
+  /* 2 atanh(s) = 2 (s + s z P(z)), P(z) = 1/3 + z/5 + z^2/7 + z^3/9 (Estrin) */
+  const float P = fmaf(fmaf(0x1.c71c72p-4f, z, 0x1.24924ap-3f), z * z,
+                       fmaf(0x1.99999ap-3f, z, 0x1.555556p-2f));
+  float t = fmaf(s * z, P, s);
+  t = t + t;
+  const float ef = (float)e;
+  const float hi = ef * 0x1.62e400p-1f;                /* exact              */
+  const float lo = ef * 0x1.7f7d1cp-20f;
+  return hi + (lo + t);
+}
+
+void orc_cossin2pif(float v, float* c, float* s) {
+  const float q = rintf(v * 4.0f);
+  const float w = v - q * 0.25f;                       /* exact, |w| <= 1/8  */
+  const float th = w * 0x1.921fb6p+2f;                 /* 2 pi w             */
+  const float z = th * th, z2 = z * z;
+  /* sin th = th (1 - z/3! + z^2/5! - z^3/7! + z^4/9!),
+     cos th = 1 - z/2! + z^2/4! - z^3/6! + z^4/8! - z^5/10! (Estrin) */
+  const float a0 = fmaf(-0x1.555556p-3f, z, 1.0f);                     /* -1/3!       */
+  const float a1 = fmaf(-0x1.a01a02p-13f, z, 0x1.111112p-7f);          /* -1/7!, 1/5! */
+  const float ps = fmaf(fmaf(0x1.71de3ap-19f, z2, a1), z2, a0);        /* 1/9!        */
+  const float sn = th * ps;
+  const float g0 = fmaf(-0x1.000000p-1f, z, 1.0f);                     /* -1/2!       */
+  const float g1 = fmaf(-0x1.6c16c2p-10f, z, 0x1.555556p-5f);          /* -1/6!, 1/4! */
+  const float g2 = fmaf(-0x1.27e4fcp-22f, z, 0x1.a01a02p-16f);         /* -1/10!, 1/8! */
+  const float cs = fmaf(fmaf(g2, z2, g1), z2, g0);
+  const int quad = ((int)q) & 3;
+  switch (quad) {
+    case 0: *c = cs;  *s = sn;  break;
+    case 1: *c = -sn; *s = cs;  break;
+    case 2: *c = -cs; *s = -sn; break;
+    default: *c = sn; *s = -cs; break;
+  }
+}
+
+void orc_boxmullerf(uint32_t wa, uint32_t wb, float* z0, float* z1) {
+  const float u1 = fmaf((float)wa, 0x1p-32f, 0x1p-33f);   /* in [2^-33, 1]  */
+  const float v = (float)wb * 0x1p-32f;                   /* in [0, 1]      */
+  const float r = sqrtf(-2.0f * orc_logf(u1));
+  float c, s;
+  orc_cossin2pif(v, &c, &s);
+  *z0 = r * c;
+  *z1 = r * s;
+}

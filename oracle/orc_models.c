@@ -3,13 +3,19 @@
  * latent kernel K, observation density g_n = G(., y_n), initial law pi_0).
  * TEST INFRASTRUCTURE ONLY (see orc.h).
  *
- * All arithmetic is double precision; a state stored in binary32 is rounded
- * once, right after it is produced, and every later use reads the rounded
- * value.  Each formula is written in the exact operation order the GPU
- * library follows (explicit fma where fused, no contraction elsewhere).
+ * Double-precision runs use the forms below in double arithmetic.  Runs with
+ * binary32 particles (f32) evaluate the same model in single precision:
+ * parameters and derived constants rounded to binary32 once (the derived
+ * ones computed in double first), observations rounded to binary32, normals
+ * from the binary32 Box-Muller, every operation a binary32 one, and the
+ * quantised weight q = (uint64)(expf(lw - mx) * 2^40) with the difference
+ * taken in binary32.  Each formula is written in the exact operation order
+ * the GPU library follows (explicit fma where fused, no contraction
+ * elsewhere); binary32 forms differ only where noted.
  *
  *   LG1  theta = (a, sx, sy):  x_0 = z;  x' = fma(a, x, sx*z);
- *        log g = -(1/2) r^2 + c,  r = (y - x)/sy,  c = -log sy - log(2 pi)/2.
+ *        log g = -(1/2) r^2 + c,  r = (y - x)/sy,  c = -log sy - log(2 pi)/2
+ *        (binary32: r = (y - x) * isy with isy = 1/sy rounded).
  *   SV   theta = (mu, phi, sigma), s0 = sigma / sqrt(1 - phi^2):
  *        x_0 = fma(s0, z, mu);  x' = fma(phi, x - mu, fma(sigma, z, mu));
  *        log g = fma(-h, exp(-x), -x/2) + c,  h = y^2/2,  c = -log(2 pi)/2.
@@ -33,28 +39,33 @@
 #include "orc.h"
 #include "orc_models.h"
 
-static double store(const orc_model* M, double v) {
-  return M->store_f32 ? (double)(float)v : v;
-}
-
-void orc_model_setup(orc_model* M, const orc_problem* P, int store_f32) {
+void orc_model_setup(orc_model* M, const orc_problem* P, int f32) {
   M->kind = P->kind; M->dx = P->dx; M->dy = P->dy; M->P = P->d_theta;
-  M->store_f32 = store_f32;
-  for (int i = 0; i < P->d_theta && i < ORC_MAX_P; ++i) M->th[i] = P->theta[i];
+  M->f32 = f32;
+  for (int i = 0; i < P->d_theta && i < ORC_MAX_P; ++i) {
+    M->th[i] = P->theta[i];
+    M->thf[i] = (float)P->theta[i];
+  }
   const double LOG2PI = log(2.0 * M_PI);
   switch (P->kind) {
     case ORC_LG1:
       M->c_log = -log(M->th[2]) - 0.5 * LOG2PI;
+      M->isyf = (float)(1.0 / M->th[2]);
       break;
     case ORC_SV:
       M->s0 = M->th[2] / sqrt(1.0 - M->th[1] * M->th[1]);
+      M->s0f = (float)M->s0;
       M->c_log = -0.5 * LOG2PI;
       break;
     case ORC_LGD: {
       const double q = P->consts[0], r = P->consts[1], p0 = P->consts[2];
       M->q = q; M->r = r; M->p0 = p0;
       M->sq = sqrt(q); M->sp0 = sqrt(p0); M->hr = 1.0 / (2.0 * r);
-      for (int i = 0; i < P->dy * P->dx; ++i) M->H[i] = P->consts[3 + i];
+      M->sqf = (float)M->sq; M->sp0f = (float)M->sp0; M->hrf = (float)M->hr;
+      for (int i = 0; i < P->dy * P->dx; ++i) {
+        M->H[i] = P->consts[3 + i];
+        M->Hf[i] = (float)M->H[i];
+      }
       M->c_log = -(0.5 * (double)P->dy) * log(2.0 * M_PI * r);
       break;
     }
@@ -77,28 +88,62 @@ void orc_model_noise(const orc_model* M, uint64_t seed, int64_t n, int32_t k,
       orc_draw(seed, (uint32_t)j, (uint32_t)k, (uint32_t)n, TAG_BIN, 0, w);
       z[j] = (double)w[0];
     }
+  } else if (M->f32) {
+    orc_island_normalsf(seed, n, k, (int64_t)N * M->dx, z);
   } else {
     orc_island_normals(seed, n, k, (int64_t)N * M->dx, z);
   }
 }
 
 void orc_model_init(const orc_model* M, const double* z, double* x) {
+  if (M->f32 && M->kind != ORC_BIN) {
+    switch (M->kind) {
+      case ORC_LG1: x[0] = (double)(float)z[0]; break;
+      case ORC_SV: x[0] = (double)fmaf(M->s0f, (float)z[0], M->thf[0]); break;
+      case ORC_LGD:
+        for (int d = 0; d < M->dx; ++d) x[d] = (double)(M->sp0f * (float)z[d]);
+        break;
+    }
+    return;
+  }
   switch (M->kind) {
-    case ORC_LG1: x[0] = store(M, z[0]); break;
-    case ORC_SV: x[0] = store(M, fma(M->s0, z[0], M->th[0])); break;
+    case ORC_LG1: x[0] = z[0]; break;
+    case ORC_SV: x[0] = fma(M->s0, z[0], M->th[0]); break;
     case ORC_LGD:
-      for (int d = 0; d < M->dx; ++d) x[d] = store(M, M->sp0 * z[d]);
+      for (int d = 0; d < M->dx; ++d) x[d] = M->sp0 * z[d];
       break;
     case ORC_BIN: x[0] = (double)(((uint32_t)z[0]) >> 31); break;
   }
 }
 
 void orc_model_prop(const orc_model* M, const double* xp, const double* z, double* x) {
+  if (M->f32 && M->kind != ORC_BIN) {
+    switch (M->kind) {
+      case ORC_LG1:
+        x[0] = (double)fmaf(M->thf[0], (float)xp[0], M->thf[1] * (float)z[0]);
+        break;
+      case ORC_SV: {
+        const float mu = M->thf[0], phi = M->thf[1], sig = M->thf[2];
+        x[0] = (double)fmaf(phi, (float)xp[0] - mu, fmaf(sig, (float)z[0], mu));
+        break;
+      }
+      case ORC_LGD: {
+        const int dx = M->dx;
+        for (int i = 0; i < dx; ++i) {
+          float acc = M->sqf * (float)z[i];
+          for (int c = 0; c < dx; ++c) acc = fmaf(M->thf[i * dx + c], (float)xp[c], acc);
+          x[i] = (double)acc;
+        }
+        break;
+      }
+    }
+    return;
+  }
   switch (M->kind) {
-    case ORC_LG1: x[0] = store(M, fma(M->th[0], xp[0], M->th[1] * z[0])); break;
+    case ORC_LG1: x[0] = fma(M->th[0], xp[0], M->th[1] * z[0]); break;
     case ORC_SV: {
       const double mu = M->th[0], phi = M->th[1], sig = M->th[2];
-      x[0] = store(M, fma(phi, xp[0] - mu, fma(sig, z[0], mu)));
+      x[0] = fma(phi, xp[0] - mu, fma(sig, z[0], mu));
       break;
     }
     case ORC_LGD: {
@@ -106,7 +151,7 @@ void orc_model_prop(const orc_model* M, const double* xp, const double* z, doubl
       for (int i = 0; i < dx; ++i) {
         double acc = M->sq * z[i];
         for (int c = 0; c < dx; ++c) acc = fma(M->th[i * dx + c], xp[c], acc);
-        x[i] = store(M, acc);
+        x[i] = acc;
       }
       break;
     }
@@ -120,6 +165,30 @@ void orc_model_prop(const orc_model* M, const double* xp, const double* z, doubl
 
 /* per-particle part of log g_n(x) (the model constant c is not included) */
 double orc_model_logpot(const orc_model* M, const double* x, const double* y) {
+  if (M->f32 && M->kind != ORC_BIN) {
+    switch (M->kind) {
+      case ORC_LG1: {
+        const float r = ((float)y[0] - (float)x[0]) * M->isyf;
+        return (double)(-0.5f * (r * r));
+      }
+      case ORC_SV: {
+        const float yf = (float)y[0], xf = (float)x[0];
+        const float h = 0.5f * (yf * yf);
+        return (double)fmaf(-h, orc_expf(-xf), -0.5f * xf);
+      }
+      case ORC_LGD: {
+        const int dx = M->dx, dy = M->dy;
+        float ss = 0.0f;
+        for (int i = 0; i < dy; ++i) {
+          float e = (float)y[i];
+          for (int c = 0; c < dx; ++c) e = fmaf(-M->Hf[i * dx + c], (float)x[c], e);
+          ss = fmaf(e, e, ss);
+        }
+        return (double)(-(ss * M->hrf));
+      }
+    }
+    return NAN;
+  }
   switch (M->kind) {
     case ORC_LG1: {
       const double r = (y[0] - x[0]) / M->th[2];
@@ -142,6 +211,20 @@ double orc_model_logpot(const orc_model* M, const double* x, const double* y) {
     case ORC_BIN: return (x[0] == y[0]) ? 0.0 : -M->log3;
   }
   return NAN;
+}
+
+/* fixed-point weights of one island: mx = max lw, q_i = floor(2^40 exp(lw_i - mx))
+ * (binary32 runs: the difference and the exponential in binary32) */
+void orc_model_quantise(const orc_model* M, const double* lw, int32_t N, uint64_t* q, double* mx_out) {
+  if (!M->f32) { orc_quantise(lw, N, q, mx_out); return; }
+  float mx = -INFINITY;
+  for (int32_t i = 0; i < N; ++i) if ((float)lw[i] > mx) mx = (float)lw[i];
+  *mx_out = (double)mx;
+  for (int32_t i = 0; i < N; ++i) {
+    if (mx == -INFINITY) { q[i] = 0; continue; }
+    const float e = orc_expf((float)lw[i] - mx);
+    q[i] = (uint64_t)(e * 0x1p40f);
+  }
 }
 
 /* ---------------- derivatives (score), plain double arithmetic ---------------- */

@@ -90,3 +90,16 @@ void orc_island_normals(uint64_t seed, int64_t n, int32_t k, int64_t count,
     for (int r = 0; r < 4 && 4 * g + r < count; ++r) z[4 * g + r] = t[r];
   }
 }
+
+/* the same normals in binary32 arithmetic (orc_boxmullerf), stored widened */
+void orc_island_normalsf(uint64_t seed, int64_t n, int32_t k, int64_t count,
+                         double* z) {
+  for (int64_t g = 0; 4 * g < count; ++g) {
+    uint32_t w[4];
+    orc_draw(seed, (uint32_t)g, (uint32_t)k, (uint32_t)n, TAG_NORMAL, 0, w);
+    float t[4];
+    orc_boxmullerf(w[0], w[1], &t[0], &t[1]);
+    orc_boxmullerf(w[2], w[3], &t[2], &t[3]);
+    for (int r = 0; r < 4 && 4 * g + r < count; ++r) z[4 * g + r] = (double)t[r];
+  }
+}

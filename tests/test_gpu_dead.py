@@ -40,13 +40,13 @@ def test_run_with_every_island_dead(ctx, orc, monkeypatch, pipeline, dead_at, m,
     monkeypatch.setenv("AIRPF_PIPELINE", pipeline)
     y = _lg1(50, dead_at)
     print(f"dead run m={m} N={N} fp64={fp64} dead_at={dead_at} pipeline={pipeline}", flush=True)
-    ref = orc.run(orc.Problem(orc.LG1, list(W.LG1_THETA), y, m, N, 5), tau=0.5, store_f32=not fp64)
+    ref = orc.run(orc.Problem(orc.LG1, list(W.LG1_THETA), y, m, N, 5), tau=0.5, f32=not fp64)
     assert ref == -np.inf
     st, v = ctx.run(0, W.LG1_THETA, y, m, N, 5, tau=0.5, fp64=fp64)
     assert st == airpf.OK and v == -np.inf
     # the next call on the context is unaffected
     y2 = _lg1(50, None)
-    ref2 = orc.run(orc.Problem(orc.LG1, list(W.LG1_THETA), y2, m, N, 6), tau=0.5, store_f32=not fp64)
+    ref2 = orc.run(orc.Problem(orc.LG1, list(W.LG1_THETA), y2, m, N, 6), tau=0.5, f32=not fp64)
     st, v2 = ctx.run(0, W.LG1_THETA, y2, m, N, 6, tau=0.5, fp64=fp64)
     assert st == airpf.OK and np.isclose(v2, ref2, rtol=1e-12, atol=0.0)
 
@@ -57,7 +57,7 @@ def test_sv_and_multinomial_dead(ctx, orc, dead_at):
     y = W.sv_data(40).copy()
     y[dead_at] = HUGE
     print(f"dead sv run dead_at={dead_at}", flush=True)
-    assert orc.run(orc.Problem(orc.SV, list(W.SV_THETA), y, 256, 64, 3), tau=0.5, store_f32=True) == -np.inf
+    assert orc.run(orc.Problem(orc.SV, list(W.SV_THETA), y, 256, 64, 3), tau=0.5, f32=True) == -np.inf
     st, v = ctx.run(1, W.SV_THETA, y, 256, 64, 3, tau=0.5)
     assert st == airpf.OK and v == -np.inf
     yl = _lg1(40, dead_at)
@@ -71,13 +71,13 @@ def test_score_with_every_island_dead(ctx, orc, ckpt, dead_at):
     from paper_2312_06484_amd import airpf
     y = _lg1(40, dead_at)
     print(f"dead score ckpt={ckpt} dead_at={dead_at}", flush=True)
-    ref_lz, _, ref_g = orc.score(orc.Problem(orc.LG1, list(W.LG1_THETA), y, 64, 128, 7), tau=0.5, store_f32=True)
+    ref_lz, _, ref_g = orc.score(orc.Problem(orc.LG1, list(W.LG1_THETA), y, 64, 128, 7), tau=0.5, f32=True)
     assert ref_lz == -np.inf and np.array_equal(ref_g, np.zeros(3))
     st, lz, g = ctx.score(0, W.LG1_THETA, y, 64, 128, 7, tau=0.5, ckpt_every=ckpt)
     assert st == airpf.OK and lz == -np.inf and np.array_equal(g, np.zeros(3))
     # a live score right after is unaffected
     y2 = _lg1(40, None)
-    r_lz, _, r_g = orc.score(orc.Problem(orc.LG1, list(W.LG1_THETA), y2, 64, 128, 8), tau=0.5, store_f32=True)
+    r_lz, _, r_g = orc.score(orc.Problem(orc.LG1, list(W.LG1_THETA), y2, 64, 128, 8), tau=0.5, f32=True)
     st, lz, g = ctx.score(0, W.LG1_THETA, y2, 64, 128, 8, tau=0.5, ckpt_every=ckpt)
     assert st == airpf.OK and np.isclose(lz, r_lz, rtol=1e-12, atol=0.0)
     assert np.all(np.abs(g - r_g) <= 1e-5 * np.abs(r_g).max() + 1e-12), (g, r_g)

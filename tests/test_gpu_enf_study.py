@@ -21,7 +21,7 @@ def test_ibpf_vs_airpf_enf(orc):
     for name, t in (("ibpf", 0.0), ("airpf", tau)):
         P = orc.Problem(orc.LG1, list(W.LG1_THETA), y, m, N, seed)
         tr = orc.Trace(P, anc=False, pi=False, lpost=False, digest=False)
-        lz = orc.run(P, tau=t, store_f32=True, trace=tr)
+        lz = orc.run(P, tau=t, f32=True, trace=tr)
         r = res[name]
         assert abs(r["log_z"] - lz) <= 1e-12 * abs(lz)
         np.testing.assert_array_equal(r["sstar"], tr.sstar[: T - 1])

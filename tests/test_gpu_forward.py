@@ -56,7 +56,7 @@ def run_both(ctx, orc, model, m, N, T, tau, f64, seed=1, dx=None):
     st, lz = ctx.run(g["kind"], g["theta"], g["y"], m, N, seed, tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"],
                      consts=g["consts"], trace=gt)
     ot = orc.Trace(P)
-    lo = orc.run(P, tau=tau, store_f32=not f64, trace=ot)
+    lo = orc.run(P, tau=tau, f32=not f64, trace=ot)
     return lz, gt, lo, ot, P
 
 
@@ -222,7 +222,7 @@ def test_untraced_run_without_interactions(ctx, orc, model, m, N, T, tau, f64, d
                     consts=g["consts"])
     assert lz == lz_traced
     assert (gt.sstar == 0).all()
-    lo = orc.run(P, tau=tau, store_f32=not f64)
+    lo = orc.run(P, tau=tau, f32=not f64)
     assert abs(lz - lo) <= 1e-12 * max(1.0, abs(lo)), (lz, lo)
 
 
@@ -255,7 +255,7 @@ def test_untraced_run_matches_traced(ctx, orc, model, m, N, T, tau, f64, dx):
                     consts=g["consts"])
     print("steps with interactions:", int((gt.sstar[:-1] > 0).sum()), "of", T - 1, flush=True)
     assert lz == lz_traced
-    lo = orc.run(P, tau=tau, store_f32=not f64)
+    lo = orc.run(P, tau=tau, f32=not f64)
     assert abs(lz - lo) <= 1e-12 * max(1.0, abs(lo)), (lz, lo)
 
 
@@ -306,7 +306,7 @@ def test_multinomial_parity(ctx, orc, model, m, N, T, tau, f64, dx):
     kw = dict(tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"], consts=g["consts"], resampling=airpf.MULTINOMIAL)
     _, lz = ctx.run(g["kind"], g["theta"], g["y"], m, N, 4, trace=gt, **kw)
     ot = orc.Trace(P)
-    lo = orc.run(P, tau=tau, scheme=1, store_f32=not f64, trace=ot)
+    lo = orc.run(P, tau=tau, scheme=1, f32=not f64, trace=ot)
     assert_parity(lz, gt, lo, ot, P)
     _, lz2 = ctx.run(g["kind"], g["theta"], g["y"], m, N, 4, **kw)
     assert lz2 == lz

@@ -20,7 +20,7 @@ def test_long_record(orc):
     y = W.lg1_data(T)
     P = orc.Problem(orc.LG1, list(W.LG1_THETA), y, m, N, seed)
     ot = orc.Trace(P, anc=False, pi=False, lpost=False, enf=False, digest=True, logz_inc=False)
-    lo = orc.run(P, tau=tau, store_f32=True, trace=ot)
+    lo = orc.run(P, tau=tau, f32=True, trace=ot)
     ctx = airpf.Context(0)
     print("long record", T, m, N, flush=True)
     gt = airpf.Trace(T, m, N, sstar=True, enf=False, lpost=False, anc=False, pi=False, digest=True)

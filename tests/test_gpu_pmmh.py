@@ -24,7 +24,7 @@ def test_pmmh_chains_match_the_oracle_fed_sampler(ctx, orc):
     gpu = pmmh.BatchedLogLik(ctx, 1, y, m, N, tau=tau)
 
     def oracle_ll(thetas, seeds):
-        return np.array([orc.run(orc.Problem(orc.SV, list(th), y, m, N, int(s)), tau=tau, store_f32=True)
+        return np.array([orc.run(orc.Problem(orc.SV, list(th), y, m, N, int(s)), tau=tau, f32=True)
                          for th, s in zip(thetas, seeds)])
 
     th0 = np.tile(np.array(W.SV_THETA), (8, 1))
@@ -45,7 +45,7 @@ def test_mala_chains_match_the_oracle_fed_sampler(ctx, orc):
     gpu = pmmh.BatchedScore(ctx, 1, y, m, N, tau=tau, fp64=True, ckpt_every=8)
 
     def oracle_score(thetas, seeds):
-        out = [orc.score(orc.Problem(orc.SV, list(th), y, m, N, int(s)), tau=tau, store_f32=False)
+        out = [orc.score(orc.Problem(orc.SV, list(th), y, m, N, int(s)), tau=tau, f32=False)
                for th, s in zip(thetas, seeds)]
         return np.array([o[0] for o in out]), np.array([o[2] for o in out])
 

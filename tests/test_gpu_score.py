@@ -76,7 +76,7 @@ def test_score_parity(ctx, orc, model, m, N, T, tau, f64, dx, K):
                         consts=g["consts"])
     assert lz == lz_run == lz_pw                          # the score's forward is the plain forward
     ot = orc.Trace(P)
-    lo, gpw, gps = orc.score(P, tau=tau, store_f32=not f64, trace=ot)
+    lo, gpw, gps = orc.score(P, tau=tau, f32=not f64, trace=ot)
     assert abs(lz - lo) <= 1e-12 * max(1.0, abs(lo))
     if T > 1:
         np.testing.assert_array_equal(gt.pi, ot.pi[: (T - 1) * m])

@@ -114,8 +114,8 @@ def test_single_island_is_bootstrap_filter(orc, maker, f32):
          "sv": lambda: sv_problem(orc, 30, 1, 37, 5),
          "lgd": lambda: lgd_problem(orc, 20, 1, 19, 5)}[maker]()
     tr = orc.Trace(P)
-    lz = orc.run(P, tau=0.3, store_f32=f32, trace=tr)
-    ll, anc = orc.bpf(P, k=0, store_f32=f32, want_anc=True)
+    lz = orc.run(P, tau=0.3, f32=f32, trace=tr)
+    ll, anc = orc.bpf(P, k=0, f32=f32, want_anc=True)
     assert lz == ll
     T, N = P.T, P.N
     assert (tr.anc.reshape(T, N)[:T - 1] == anc.reshape(T, N)[:T - 1]).all()
@@ -235,7 +235,7 @@ def test_float32_storage_accuracy_along_same_genealogy(orc):
     T, m, N = 200, 16, 32
     P = sv_problem(orc, T, m, N, 2)
     tr = orc.Trace(P)
-    orc.run(P, store_f32=True, trace=tr)
-    F32, _, _ = orc.frozen(P, tr, store_f32=True)
-    F64, _, _ = orc.frozen(P, tr, store_f32=False)
+    orc.run(P, f32=True, trace=tr)
+    F32, _, _ = orc.frozen(P, tr, f32=True)
+    F64, _, _ = orc.frozen(P, tr, f32=False)
     assert abs(F32 - F64) < 1e-4 * T

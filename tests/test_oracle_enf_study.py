@@ -11,7 +11,7 @@ from paper_2312_06484_amd import workloads as W
 def _trace(orc, tau, T=400, m=256, N=8, seed=3):
     P = orc.Problem(orc.LG1, list(W.LG1_THETA), W.lg1_data(T), m, N, seed)
     tr = orc.Trace(P, anc=False, pi=False, lpost=False, digest=False)
-    lz = orc.run(P, tau=tau, store_f32=True, trace=tr)
+    lz = orc.run(P, tau=tau, f32=True, trace=tr)
     return lz, tr.enf.reshape(T, tr.S + 1)[: T - 1], tr.sstar[: T - 1].astype(int), tr.S
 
 
