@@ -94,8 +94,11 @@ typedef struct {
                          airpf_score and a batch with want_score return
                          AIRPF_E_UNSUPPORTED for it; any other value is
                          AIRPF_E_INVALID_ARG */
-  int32_t precision;  /* storage precision of the particle state; all particle
-                         arithmetic is double precision either way */
+  int32_t precision;  /* precision of the particles: AIRPF_FP64 everything in
+                         double; AIRPF_FP32 binary32 state, normals, model
+                         and fixed-point weights (own single-precision exp,
+                         log, sin/cos, Box-Muller on the same draws), island
+                         log-weights and log Zhat in double either way */
   int32_t score_mode; /* airpf_score_mode (airpf_score, airpf_run_batch with scores) */
   int32_t ckpt_every; /* checkpoint interval of the score's recomputation (0: auto) */
   uint32_t flags;     /* AIRPF_FLAG_* */
@@ -213,7 +216,9 @@ airpf_status airpf_ctx_last_kernel_ms(airpf_ctx* ctx, double* ms);
  * implementations of exp, log, (cos, sin)(2 pi v), Box-Muller and Philox on
  * host arrays of length n (outputs host).  `which`: 0 exp, 1 log, 2 cossin
  * (out2 gets sin), 3 Box-Muller of word pairs (in_u32 pairs, out/out2),
- * 4 Philox (in_u32 = 6 words per item: key0, key1, c0..c3; out_u32 4 per item). */
+ * 4 Philox (in_u32 = 6 words per item: key0, key1, c0..c3; out_u32 4 per
+ * item); 5, 6, 7, 8: the binary32 exp, log, cossin and Box-Muller (inputs
+ * rounded to binary32, results widened to double). */
 airpf_status airpf_debug_eval(airpf_ctx* ctx, int32_t which, int64_t n, const double* in,
                               const uint32_t* in_u32, double* out, double* out2,
                               uint32_t* out_u32);

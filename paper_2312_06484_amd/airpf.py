@@ -298,21 +298,22 @@ class Context:
 
     def debug_eval(self, which, values=None, words=None):
         """Evaluate the device's own exp (0), log (1), cossin 2 pi (2),
-        Box-Muller (3) or Philox (4) on host arrays."""
+        Box-Muller (3) or Philox (4) on host arrays; 5-8 are the binary32
+        exp, log, cossin and Box-Muller."""
         L = lib()
-        if which in (0, 1, 2):
+        if which in (0, 1, 2, 5, 6, 7):
             v = np.ascontiguousarray(values, dtype=np.float64)
             n = v.size
             out, out2 = np.zeros(n), np.zeros(n)
             st = L.airpf_debug_eval(self._h, which, n, _p(v, _dp), None, _p(out, _dp), _p(out2, _dp), None)
             if st != OK:
                 raise AirpfError(st, "airpf_debug_eval")
-            return (out, out2) if which == 2 else out
+            return (out, out2) if which in (2, 7) else out
         w = np.ascontiguousarray(words, dtype=np.uint32)
-        if which == 3:
+        if which in (3, 8):
             n = w.size // 2
             out, out2 = np.zeros(n), np.zeros(n)
-            st = L.airpf_debug_eval(self._h, 3, n, None, _p(w, _u32p), _p(out, _dp), _p(out2, _dp), None)
+            st = L.airpf_debug_eval(self._h, which, n, None, _p(w, _u32p), _p(out, _dp), _p(out2, _dp), None)
             if st != OK:
                 raise AirpfError(st, "airpf_debug_eval")
             return out, out2

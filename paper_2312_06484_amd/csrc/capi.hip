@@ -193,6 +193,14 @@ airpf_status prepare_model(const airpf_model* model, const double* theta, int32_
       return AIRPF_E_INVALID_ARG;
   }
   for (int i = 0; i < d_theta; ++i) mp->th[i] = theta[i];
+  // binary32 particles: every parameter and derived constant rounded once
+  for (int i = 0; i < d_theta; ++i) mp->thf[i] = static_cast<float>(theta[i]);
+  for (int i = 0; i < airpf::kMaxDy * 8; ++i) mp->Hf[i] = static_cast<float>(mp->H[i]);
+  mp->s0f = static_cast<float>(mp->s0);
+  mp->sqf = static_cast<float>(mp->sq);
+  mp->sp0f = static_cast<float>(mp->sp0);
+  mp->hrf = static_cast<float>(mp->hr);
+  mp->isyf = model->kind == AIRPF_LG1 ? static_cast<float>(1.0 / theta[2]) : 0.0f;
   mp->dy = dy;
   *cst_q = c_log - 40.0 * std::log(2.0) - std::log(static_cast<double>(N));
   *dx_out = dx;
@@ -603,15 +611,17 @@ extern "C" airpf_status airpf_ctx_last_kernel_ms(airpf_ctx* ctx, double* ms) {
 
 extern "C" airpf_status airpf_debug_eval(airpf_ctx* ctx, int32_t which, int64_t n, const double* in,
                                          const uint32_t* in_u32, double* out, double* out2, uint32_t* out_u32) {
-  if (!ctx || n < 0 || which < 0 || which > 4) return AIRPF_E_INVALID_ARG;
+  if (!ctx || n < 0 || which < 0 || which > 8) return AIRPF_E_INVALID_ARG;
   if (n == 0) return AIRPF_OK;
-  const bool uses_in = which <= 2, uses_in32 = which >= 3, uses_out2 = which == 2 || which == 3;
-  if ((uses_in && !in) || (uses_in32 && !in_u32) || (which <= 3 && !out) || (uses_out2 && !out2) ||
+  // 0-2, 5-7 read doubles; 3, 8 read word pairs; 4 reads Philox blocks
+  const bool uses_in = which <= 2 || (which >= 5 && which <= 7), uses_in32 = which == 3 || which == 4 || which == 8;
+  const bool uses_out2 = which == 2 || which == 3 || which == 7 || which == 8;
+  if ((uses_in && !in) || (uses_in32 && !in_u32) || (which != 4 && !out) || (uses_out2 && !out2) ||
       (which == 4 && !out_u32))
     return AIRPF_E_INVALID_ARG;
   HIP_OK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
-  const size_t n32 = which == 3 ? 2 * size_t(n) : 6 * size_t(n);
+  const size_t n32 = (which == 3 || which == 8) ? 2 * size_t(n) : 6 * size_t(n);
   ST_OK(ctx->dbg_in.ensure(8 * size_t(n)));
   ST_OK(ctx->dbg_in32.ensure(4 * n32));
   ST_OK(ctx->dbg_out.ensure(8 * size_t(n)));
@@ -622,7 +632,7 @@ extern "C" airpf_status airpf_debug_eval(airpf_ctx* ctx, int32_t which, int64_t 
   HIP_OK(airpf::launch_debug_eval(which, n, static_cast<const double*>(ctx->dbg_in.p),
                                   static_cast<const uint32_t*>(ctx->dbg_in32.p), static_cast<double*>(ctx->dbg_out.p),
                                   static_cast<double*>(ctx->dbg_out2.p), static_cast<uint32_t*>(ctx->dbg_out32.p), s));
-  if (which <= 3) HIP_OK(hipMemcpyAsync(out, ctx->dbg_out.p, 8 * size_t(n), hipMemcpyDeviceToHost, s));
+  if (which != 4) HIP_OK(hipMemcpyAsync(out, ctx->dbg_out.p, 8 * size_t(n), hipMemcpyDeviceToHost, s));
   if (uses_out2) HIP_OK(hipMemcpyAsync(out2, ctx->dbg_out2.p, 8 * size_t(n), hipMemcpyDeviceToHost, s));
   if (which == 4) HIP_OK(hipMemcpyAsync(out_u32, ctx->dbg_out32.p, 16 * size_t(n), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));

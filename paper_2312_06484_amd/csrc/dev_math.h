@@ -2,7 +2,8 @@
 //
 // Contract shared (as a written specification, not as code) with the CPU
 // checker, so that every integer decision of the filter -- fixed-point
-// weights, ancestors, island selections -- comes out identical:
+// weights, ancestors, island selections -- comes out identical (runs with
+// binary32 particles use the binary32 set further below):
 //  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (seed lo, seed
 //    hi), counter = (c0, island, step, tag << 24 | sub).
 //  * exp, log and (cos, sin)(2 pi v) evaluated with correctly rounded IEEE
@@ -227,6 +228,104 @@ __device__ __forceinline__ void normals4(Key key, uint32_t g, uint32_t island, u
   box_muller(w[0], w[1], z[0], z[1]);
   box_muller(w[2], w[3], z[2], z[3]);
 }
+
+// ---------------------------------------------------------------- binary32
+// The same functions for binary32 particles, every operation a correctly
+// rounded single-precision one (fmaf, +, *, /, sqrtf, rintf): Cody-Waite
+// with a 15-bit ln 2 head (k ln2_head exact) and e^r = 1 + (r + r^2 Q(r)),
+// Q of degree 5 (1/2! .. 1/7!); results below 2^-126 are 0 and the scaling
+// 2^k is exact (k in [-125, 127]); log by 2 atanh(s) to s^9; sin to th^9 and
+// cos to th^10 after the quarter-turn reduction.  Coefficients are the
+// double tables above rounded once to binary32 (each equals the correctly
+// rounded binary32 value of its rational).
+
+constexpr float kLn2HeadF = 0x1.62e400p-1f;    // 15 significant bits
+constexpr float kLn2TailF = 0x1.7f7d1cp-20f;   // ln 2 - head, rounded
+constexpr float kInvLn2F = 0x1.715476p+0f;
+constexpr float kTwoPiF = 0x1.921fb6p+2f;
+template <int K> struct InvFactF { static constexpr float value = static_cast<float>(kCoeff.inv_fact[K]); };
+template <int I> struct InvOddF { static constexpr float value = static_cast<float>(kCoeff.inv_odd[I]); };
+
+__device__ inline float fexp(float x) {
+  const float kf = rintf(x * kInvLn2F);
+  const float r = fmaf(-kf, kLn2TailF, fmaf(-kf, kLn2HeadF, x));
+  const float r2 = r * r, r4 = r2 * r2;
+  const float q0 = fmaf(InvFactF<3>::value, r, InvFactF<2>::value);
+  const float q1 = fmaf(InvFactF<5>::value, r, InvFactF<4>::value);
+  const float q2 = fmaf(InvFactF<7>::value, r, InvFactF<6>::value);
+  const float Q = fmaf(q2, r4, fmaf(q1, r2, q0));
+  const float p = 1.0f + fmaf(r2, Q, r);
+  const int k = static_cast<int>(fminf(fmaxf(kf, -200.0f), 200.0f));
+  float res = __builtin_ldexpf(p, k);              // exact where it is kept
+  res = kf > 127.0f ? __uint_as_float(0x7f800000u) : res;
+  res = kf < -125.0f ? 0.0f : res;
+  return x == x ? res : x;
+}
+
+__device__ inline float flog(float x0) {
+  const bool sub = x0 < 0x1p-126f;
+  const float x = sub ? x0 * 0x1p+24f : x0;
+  const uint32_t bits = __float_as_uint(x);
+  int e = static_cast<int>((bits >> 23) & 0xff) - 127 - (sub ? 24 : 0);
+  float f = __uint_as_float((bits & 0x007fffffu) | 0x3f800000u);
+  const bool big = f > 0x1.6a09e6p+0f;
+  f = big ? f * 0.5f : f;
+  e += big ? 1 : 0;
+  const float s = (f - 1.0f) / (f + 1.0f);
+  const float z = s * s;
+  // 2 atanh(s) = 2 (s + s z P(z)), P(z) = 1/3 + z/5 + z^2/7 + z^3/9
+  const float P = fmaf(fmaf(InvOddF<4>::value, z, InvOddF<3>::value), z * z,
+                       fmaf(InvOddF<2>::value, z, InvOddF<1>::value));
+  float t = fmaf(s * z, P, s);
+  t = t + t;
+  const float ef = static_cast<float>(e);
+  float res = ef * kLn2HeadF + (ef * kLn2TailF + t);
+  res = x0 == __uint_as_float(0x7f800000u) ? x0 : res;
+  res = x0 == 0.0f ? __uint_as_float(0xff800000u) : res;
+  return (x0 == x0 && x0 >= 0.0f) ? res : __uint_as_float(0x7fc00000u);
+}
+
+__device__ inline void fcossin_2pi(float v, float& c, float& s) {
+  const float q = rintf(v * 4.0f);
+  const float th = (v - q * 0.25f) * kTwoPiF;
+  const float z = th * th, z2 = z * z;
+  const float a0 = fmaf(-InvFactF<3>::value, z, 1.0f);
+  const float a1 = fmaf(-InvFactF<7>::value, z, InvFactF<5>::value);
+  const float sn = th * fmaf(fmaf(InvFactF<9>::value, z2, a1), z2, a0);
+  const float g0 = fmaf(-InvFactF<2>::value, z, 1.0f);
+  const float g1 = fmaf(-InvFactF<6>::value, z, InvFactF<4>::value);
+  const float g2 = fmaf(-InvFactF<10>::value, z, InvFactF<8>::value);
+  const float pc = fmaf(fmaf(g2, z2, g1), z2, g0);
+  const int quad = static_cast<int>(q) & 3;
+  const float a = (quad & 1) ? -sn : pc;
+  const float b = (quad & 1) ? pc : sn;
+  c = (quad & 2) ? -a : a;
+  s = (quad & 2) ? -b : b;
+}
+
+// Box-Muller in binary32 on the same two words: u1 = fmaf((float)wa, 2^-32,
+// 2^-33) in [2^-33, 1], v = (float)wb 2^-32 (the conversions round to
+// nearest even)
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z0, float& z1) {
+  const float u1 = fmaf(static_cast<float>(wa), 0x1p-32f, 0x1p-33f);
+  const float r = sqrtf(-2.0f * flog(u1));
+  float c, s;
+  fcossin_2pi(static_cast<float>(wb) * 0x1p-32f, c, s);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+// normals 4g .. 4g+3 of (step, island) in binary32 arithmetic
+__device__ __forceinline__ void normals4(Key key, uint32_t g, uint32_t island, uint32_t step, float z[4]) {
+  uint32_t w[4];
+  draw4(key, g, island, step, kTagNormal, 0, w);
+  box_muller(w[0], w[1], z[0], z[1]);
+  box_muller(w[2], w[3], z[2], z[3]);
+}
+
+// exp in the particles' precision
+__device__ __forceinline__ double rexp(double x) { return dexp(x); }
+__device__ __forceinline__ float rexp(float x) { return fexp(x); }
 
 __device__ __forceinline__ uint64_t fmix64(uint64_t h) {
   h ^= h >> 33; h *= 0xff51afd7ed558ccdULL;

@@ -1,10 +1,12 @@
 // State-space models on the device: initial draw, mutation kernel K and the
 // per-particle part of log g_n (Section 1.2's HMM; the concrete models are
-// listed in include/airpf.h).  Arithmetic is double precision; a state kept
-// in binary32 is rounded once when produced, and every later use reads the
-// rounded value.  Operation order is part of the contract with the CPU
-// checker (explicit fma only):
-//   LG1  x_0 = z;  x' = fma(a, x, sx*z);  lw = -0.5*(r*r), r = (y - x)/sy
+// listed in include/airpf.h).  The particle arithmetic is done in the
+// particles' own precision R (double, or binary32 with every parameter and
+// derived constant rounded once to binary32 on the host and the observation
+// rounded to binary32).  Operation order is part of the contract with the
+// CPU checker (explicit fma only):
+//   LG1  x_0 = z;  x' = fma(a, x, sx*z);  lw = -0.5*(r*r),
+//        r = (y - x)/sy (double) or (y - x)*isy, isy = 1/sy (binary32)
 //   SV   x_0 = fma(s0, z, mu);  x' = fma(phi, x - mu, fma(sigma, z, mu));
 //        lw = fma(-(0.5*(y*y)), exp(-x), -0.5*x)
 //   LGD  x_0[d] = sqrt(p0)*z_d;  x'[i] = sqrt(q)*z_i then fma(A[i][c], x[c], .)
@@ -16,6 +18,8 @@
 // and vector-Jacobian products of the mutation x' = F(x, z; theta) and of
 // the initial draw.
 #pragma once
+#include <type_traits>
+
 #include "dev_math.h"
 
 namespace airpf {
@@ -29,26 +33,43 @@ struct ModelArgs {
   double H[kMaxDy * 8];
   double s0, sq, sp0, hr;
   double ds0_dphi, ds0_dsig;  // SV: derivatives of the stationary sd
+  // binary32 particles: the same parameters and constants rounded once
+  float thf[kMaxTheta];
+  float Hf[kMaxDy * 8];
+  float s0f, sqf, sp0f, hrf, isyf;
   int dy;
 };
 
-template <typename Store>
-__device__ __forceinline__ double round_store(double v) {
-  return static_cast<double>(static_cast<Store>(v));
+template <typename R> __device__ __forceinline__ constexpr bool is_f32() { return std::is_same<R, float>::value; }
+template <typename R> __device__ __forceinline__ R rfma(R a, R b, R c) {
+  if constexpr (is_f32<R>()) return fmaf(a, b, c); else return fma(a, b, c);
+}
+// parameter i, and entry i of H, in the particles' precision
+template <typename R> __device__ __forceinline__ R par(const ModelArgs& p, int i) {
+  if constexpr (is_f32<R>()) return p.thf[i]; else return p.th[i];
+}
+template <typename R> __device__ __forceinline__ R hpar(const ModelArgs& p, int i) {
+  if constexpr (is_f32<R>()) return p.Hf[i]; else return p.H[i];
 }
 
 struct LG1 {
   static constexpr int DX = 1;
   static constexpr bool kThetaOuter = false;   // see LGD
-  template <typename Store>
-  __device__ static void init(const ModelArgs&, const double* z, double* x) { x[0] = round_store<Store>(z[0]); }
-  template <typename Store>
-  __device__ static void prop(const ModelArgs& p, const double* xp, const double* z, double* x) {
-    x[0] = round_store<Store>(fma(p.th[0], xp[0], p.th[1] * z[0]));
+  template <typename R>
+  __device__ static void init(const ModelArgs&, const R* z, R* x) { x[0] = z[0]; }
+  template <typename R>
+  __device__ static void prop(const ModelArgs& p, const R* xp, const R* z, R* x) {
+    x[0] = rfma<R>(par<R>(p, 0), xp[0], par<R>(p, 1) * z[0]);
   }
-  __device__ static double logpot(const ModelArgs& p, const double* x, const double* y) {
-    const double r = (y[0] - x[0]) / p.th[2];
-    return -0.5 * (r * r);
+  template <typename R>
+  __device__ static R logpot(const ModelArgs& p, const R* x, const double* y) {
+    if constexpr (is_f32<R>()) {
+      const float r = (static_cast<float>(y[0]) - x[0]) * p.isyf;
+      return -0.5f * (r * r);
+    } else {
+      const double r = (y[0] - x[0]) / p.th[2];
+      return -0.5 * (r * r);
+    }
   }
   static constexpr int P = 3;
   __device__ static void dlogpot_dx(const ModelArgs& p, const double* x, const double* y, double* g) {
@@ -71,18 +92,21 @@ struct LG1 {
 struct SV {
   static constexpr int DX = 1;
   static constexpr bool kThetaOuter = false;   // see LGD
-  template <typename Store>
-  __device__ static void init(const ModelArgs& p, const double* z, double* x) {
-    x[0] = round_store<Store>(fma(p.s0, z[0], p.th[0]));
+  template <typename R>
+  __device__ static void init(const ModelArgs& p, const R* z, R* x) {
+    if constexpr (is_f32<R>()) x[0] = fmaf(p.s0f, z[0], p.thf[0]);
+    else x[0] = fma(p.s0, z[0], p.th[0]);
   }
-  template <typename Store>
-  __device__ static void prop(const ModelArgs& p, const double* xp, const double* z, double* x) {
-    const double mu = p.th[0];
-    x[0] = round_store<Store>(fma(p.th[1], xp[0] - mu, fma(p.th[2], z[0], mu)));
+  template <typename R>
+  __device__ static void prop(const ModelArgs& p, const R* xp, const R* z, R* x) {
+    const R mu = par<R>(p, 0);
+    x[0] = rfma<R>(par<R>(p, 1), xp[0] - mu, rfma<R>(par<R>(p, 2), z[0], mu));
   }
-  __device__ static double logpot(const ModelArgs&, const double* x, const double* y) {
-    const double h = 0.5 * (y[0] * y[0]);
-    return fma(-h, dexp(-x[0]), -0.5 * x[0]);
+  template <typename R>
+  __device__ static R logpot(const ModelArgs&, const R* x, const double* y) {
+    const R yr = static_cast<R>(y[0]);
+    const R h = R(0.5) * (yr * yr);
+    return rfma<R>(-h, rexp(-x[0]), R(-0.5) * x[0]);
   }
   static constexpr int P = 3;
   __device__ static void dlogpot_dx(const ModelArgs&, const double* x, const double* y, double* g) {
@@ -106,30 +130,34 @@ struct SV {
 template <int D>
 struct LGD {
   static constexpr int DX = D;
-  template <typename Store>
-  __device__ static void init(const ModelArgs& p, const double* z, double* x) {
+  template <typename R>
+  __device__ static void init(const ModelArgs& p, const R* z, R* x) {
+    const R sp0 = is_f32<R>() ? R(p.sp0f) : R(p.sp0);
 #pragma unroll
-    for (int d = 0; d < D; ++d) x[d] = round_store<Store>(p.sp0 * z[d]);
+    for (int d = 0; d < D; ++d) x[d] = sp0 * z[d];
   }
-  template <typename Store>
-  __device__ static void prop(const ModelArgs& p, const double* xp, const double* z, double* x) {
+  template <typename R>
+  __device__ static void prop(const ModelArgs& p, const R* xp, const R* z, R* x) {
+    const R sq = is_f32<R>() ? R(p.sqf) : R(p.sq);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      double acc = p.sq * z[i];
+      R acc = sq * z[i];
 #pragma unroll
-      for (int c = 0; c < D; ++c) acc = fma(p.th[i * D + c], xp[c], acc);
-      x[i] = round_store<Store>(acc);
+      for (int c = 0; c < D; ++c) acc = rfma<R>(par<R>(p, i * D + c), xp[c], acc);
+      x[i] = acc;
     }
   }
-  __device__ static double logpot(const ModelArgs& p, const double* x, const double* y) {
-    double ss = 0.0;
+  template <typename R>
+  __device__ static R logpot(const ModelArgs& p, const R* x, const double* y) {
+    R ss = R(0);
     for (int i = 0; i < p.dy; ++i) {
-      double e = y[i];
+      R e = static_cast<R>(y[i]);
 #pragma unroll
-      for (int c = 0; c < D; ++c) e = fma(-p.H[i * D + c], x[c], e);
-      ss = fma(e, e, ss);
+      for (int c = 0; c < D; ++c) e = rfma<R>(-hpar<R>(p, i * D + c), x[c], e);
+      ss = rfma<R>(e, e, ss);
     }
-    return -(ss * p.hr);
+    const R hr = is_f32<R>() ? R(p.hrf) : R(p.hr);
+    return -(ss * hr);
   }
   // theta = A: the transition's theta-tangent contracted with the child's
   // adjoint is lam xp^T (an outer product), and g and x_0 do not depend on

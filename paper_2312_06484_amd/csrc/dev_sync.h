@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "dev_math.h"
 
 namespace airpf {
@@ -20,6 +22,11 @@ __device__ __forceinline__ int64_t tree_off(int m, int level) {  // level >= 1
 }
 
 __device__ __forceinline__ double ninf() { return -__longlong_as_double(0x7ff0000000000000LL); }
+template <typename R> __device__ __forceinline__ R neg_inf() {
+  if constexpr (std::is_same<R, float>::value) return __uint_as_float(0xff800000u); else return ninf();
+}
+__device__ __forceinline__ double rmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float rmax(float a, float b) { return fmaxf(a, b); }
 
 // log((exp(a) + exp(b)) / 2), symmetric in (a, b)
 __device__ __forceinline__ double pair_mean(double a, double b) {
@@ -187,6 +194,38 @@ __device__ __forceinline__ double team_max(double v, int TP, double* red) {
   }
   return v;
 }
+
+// the same tree for binary32 values (32-bit lane moves); `red` holds kWaves floats
+__device__ __forceinline__ float readlane_f32(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+  return __uint_as_float(dpp32<CTRL>(__float_as_uint(v)));
+}
+__device__ __forceinline__ float team_max(float v, int TP, float* red) {
+  if (TP >= 2) v = fmaxf(v, dppf<0xB1>(v));
+  if (TP >= 4) v = fmaxf(v, dppf<0x4E>(v));
+  if (TP >= 8) v = fmaxf(v, dppf<0x141>(v));
+  if (TP >= 16) v = fmaxf(v, dppf<0x140>(v));
+  if (TP >= 64) {
+    v = fmaxf(fmaxf(readlane_f32(v, 0), readlane_f32(v, 16)), fmaxf(readlane_f32(v, 32), readlane_f32(v, 48)));
+  } else if (TP >= 32) {
+    v = fmaxf(v, __shfl_xor(v, 16, 64));
+  }
+  if (TP > 64) {
+    const int tid = threadIdx.x;
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    const int w0 = (tid / TP) * (TP >> 6);
+    float r = red[w0];
+    for (int i = 1; i < (TP >> 6); ++i) r = fmaxf(r, red[w0 + i]);
+    __syncthreads();
+    v = r;
+  }
+  return v;
+}
+__device__ __forceinline__ float team_max(float v, int TP, double* red) { return team_max(v, TP, reinterpret_cast<float*>(red)); }
 
 __device__ __forceinline__ uint64_t team_sum_u64(uint64_t v, int TP, uint64_t* red) {
   if (TP >= 2) v += dpp64<0xB1>(v);

@@ -94,6 +94,11 @@ __global__ void debug_eval_kernel(int which, int64_t n, const double* in, const 
       for (int r = 0; r < 4; ++r) out_u32[4 * i + r] = w[r];
       break;
     }
+    // binary32 counterparts (inputs and outputs widened to double)
+    case 5: out[i] = fexp(static_cast<float>(in[i])); break;
+    case 6: out[i] = flog(static_cast<float>(in[i])); break;
+    case 7: { float c, s; fcossin_2pi(static_cast<float>(in[i]), c, s); out[i] = c; out2[i] = s; break; }
+    case 8: { float z0, z1; box_muller(in_u32[2 * i], in_u32[2 * i + 1], z0, z1); out[i] = z0; out2[i] = z1; break; }
   }
 }
 

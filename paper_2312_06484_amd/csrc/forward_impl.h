@@ -15,6 +15,8 @@
 //                (or x_0 ~ pi_0), normals at (step n, island k);
 //   weighting    lw = log g_n(x) per particle, q = floor(2^40 exp(lw - max)),
 //                Q = sum q (exact), L_k = Lpre_k + ((max + log Q) + cst);
+//                the particle arithmetic (normals, model, lw, exp) is done in
+//                the state's precision Store, island weights in double;
 //   resampling   systematic on the integer cumulative weights: slot j takes
 //                min{i : N C_i > U + j Q}, U uniform on [0, Q);
 //   island tree  pair means log((W_a + W_b)/2) of aligned blocks, level by
@@ -150,9 +152,9 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 
   const bool replay = !Plain && a.replay_pi != 0;
   // normals of (step, island, particle) for this lane's particles
-  auto draw_normals = [&](int64_t n, int k, int j0, double* z) {
+  auto draw_normals = [&](int64_t n, int k, int j0, Store* z) {
     for (int g = 0; g < NZ / 4; ++g) {
-      double t[4];
+      Store t[4];
       normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
 #pragma unroll
       for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
@@ -178,7 +180,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     // the first pass's draws (its normals and the systematic offset's first
     // block) do not depend on the other blocks: they are taken between
     // publishing this block's flag and waiting for the others
-    double z_first[NZ];
+    Store z_first[NZ];
     uint32_t wsys_first[4] = {0u, 0u, 0u, 0u};
     bool first_drawn = false;
     bool skip_passes = false;
@@ -315,7 +317,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       // sub-block 0 of the systematic offset's draw (it does not depend on Q)
       uint32_t wsys[4] = {wsys_first[0], wsys_first[1], wsys_first[2], wsys_first[3]};
       if (!pre && n < a.T - 1 && lane == 0) draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
-      double x[PPT][DX];
+      Store x[PPT][DX];
       double Lpre = 0.0;
       if (n == n0 && ck_in) {
         // restart from the checkpoint taken entering this step
@@ -324,10 +326,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 #pragma unroll
         for (int r = 0; r < PPT; ++r)
 #pragma unroll
-          for (int d = 0; d < DX; ++d) x[r][d] = (j0 + r < N) ? static_cast<double>(xc[(j0 + r) * DX + d]) : 0.0;
+          for (int d = 0; d < DX; ++d) x[r][d] = (j0 + r < N) ? xc[(j0 + r) * DX + d] : Store(0);
         if (lane == 0) Lpre = ck_L[(n / ck_every) * m + k];
       } else if (n == 0) {
-        double z[NZ];
+        Store z[NZ];
         draw_normals(n, k, j0, z);
 #pragma unroll
         for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * DX, x[r]);
@@ -350,7 +352,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 #pragma unroll
             for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? get(xin + (j0 + r) * DX + d) : Store(0);
         }
-        double z[NZ];
+        Store z[NZ];
         if (pre) {
 #pragma unroll
           for (int i = 0; i < NZ; ++i) z[i] = z_first[i];
@@ -359,9 +361,9 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         }
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
-          double xp[DX];
+          Store xp[DX];
 #pragma unroll
-          for (int d = 0; d < DX; ++d) xp[d] = static_cast<double>(xr[r][d]);
+          for (int d = 0; d < DX; ++d) xp[d] = xr[r][d];
           Model::template prop<Store>(a.mp, xp, z + r * DX, x[r]);
         }
       }
@@ -391,22 +393,22 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 
       // ---- weighting ----
       const double* yn = a.y + n * a.dy;
-      double lw[PPT];
-      double mx = ninf();
+      Store lw[PPT];
+      Store mx = neg_inf<Store>();
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
         const bool valid = active && (j0 + r < N);
-        double v = valid ? Model::logpot(a.mp, x[r], yn) : ninf();
-        if (!(v == v)) v = ninf();
+        Store v = valid ? Model::template logpot<Store>(a.mp, x[r], yn) : neg_inf<Store>();
+        if (!(v == v)) v = neg_inf<Store>();
         lw[r] = v;
-        mx = fmax(mx, v);
+        mx = rmax(mx, v);
       }
       mx = team_max(mx, TP, red_d);
       uint64_t q[PPT];
       uint64_t tsum = 0;
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
-        q[r] = (mx == ninf()) ? 0 : static_cast<uint64_t>(dexp(lw[r] - mx) * 0x1p40);
+        q[r] = (mx == neg_inf<Store>()) ? 0 : static_cast<uint64_t>(rexp(lw[r] - mx) * Store(0x1p40));
         tsum += q[r];
       }
       const uint64_t incl = team_scan_u64(tsum, TP, red_u);
@@ -414,7 +416,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       const uint64_t Qk = TP == 64 ? readlane_u64(incl, 63)
                           : (TP < 64 ? __shfl(incl, (tid & 63) | (TP - 1), 64) : team_sum_u64(tsum, TP, red_u));
       if (lane == 0 && active && !replay) {
-        const double L = (Qk == 0) ? ninf() : Lpre + ((mx + dlog(static_cast<double>(Qk))) + a.cst_q);
+        const double L = (Qk == 0) ? ninf() : Lpre + ((static_cast<double>(mx) + dlog(static_cast<double>(Qk))) + a.cst_q);
         lvp(par)[li] = L;
         if (tr_lpost) tr_lpost[n * m + k] = L;
       }
@@ -705,12 +707,12 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       const int j0 = lane * PPT;
       uint32_t wsys[4] = {0u, 0u, 0u, 0u};
       if (n < T - 1 && lane == 0) draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
-      double x[PPT][DX];
+      Store x[PPT][DX];
       double Lpre = 0.0;
       if (n == 0) {
-        double z[NZ];
+        Store z[NZ];
         for (int g = 0; g < NZ / 4; ++g) {
-          double t[4];
+          Store t[4];
           normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
 #pragma unroll
           for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
@@ -734,18 +736,18 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
 #pragma unroll
             for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? get(xin + (j0 + r) * DX + d) : Store(0);
         }
-        double z[NZ];
+        Store z[NZ];
         for (int g = 0; g < NZ / 4; ++g) {
-          double t[4];
+          Store t[4];
           normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
 #pragma unroll
           for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
         }
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
-          double xp[DX];
+          Store xp[DX];
 #pragma unroll
-          for (int d = 0; d < DX; ++d) xp[d] = static_cast<double>(xr[r][d]);
+          for (int d = 0; d < DX; ++d) xp[d] = xr[r][d];
           Model::template prop<Store>(a.mp, xp, z + r * DX, x[r]);
         }
       }
@@ -769,28 +771,28 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
 
       // ---- weighting ----
       const double* yn = a.y + n * a.dy;
-      double lw[PPT];
-      double mx = ninf();
+      Store lw[PPT];
+      Store mx = neg_inf<Store>();
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
         const bool valid = active && (j0 + r < N);
-        double v = valid ? Model::logpot(a.mp, x[r], yn) : ninf();
-        if (!(v == v)) v = ninf();
+        Store v = valid ? Model::template logpot<Store>(a.mp, x[r], yn) : neg_inf<Store>();
+        if (!(v == v)) v = neg_inf<Store>();
         lw[r] = v;
-        mx = fmax(mx, v);
+        mx = rmax(mx, v);
       }
       mx = team_max(mx, TP, red_d);
       uint64_t q[PPT];
       uint64_t tsum = 0;
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
-        q[r] = (mx == ninf()) ? 0 : static_cast<uint64_t>(dexp(lw[r] - mx) * 0x1p40);
+        q[r] = (mx == neg_inf<Store>()) ? 0 : static_cast<uint64_t>(rexp(lw[r] - mx) * Store(0x1p40));
         tsum += q[r];
       }
       const uint64_t incl = team_scan_u64(tsum, TP, red_u);
       const uint64_t Qk = TP == 64 ? readlane_u64(incl, 63) : __shfl(incl, (tid & 63) | (TP - 1), 64);
       if (lane == 0 && active) {
-        const double L = (Qk == 0) ? ninf() : Lpre + ((mx + dlog(static_cast<double>(Qk))) + a.cst_q);
+        const double L = (Qk == 0) ? ninf() : Lpre + ((static_cast<double>(mx) + dlog(static_cast<double>(Qk))) + a.cst_q);
         lvp(par)[li] = L;
       }
 

@@ -205,15 +205,18 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
         const bool valid = active && (j0 + r < N);
+        Store xr[DX];
 #pragma unroll
         for (int d = 0; d < DX; ++d) {
           const Store v = valid ? xs[(j0 + r) * DX + d] : Store(0);
+          xr[d] = v;
           x[r][d] = static_cast<double>(v);
           sxt[(j0 + r) * DX + d] = v;
         }
-        double v = valid ? Model::logpot(a.mp, x[r], yn) : ninf();
-        if (!(v == v)) v = ninf();
-        lw[r] = v;
+        // log g in the particles' precision, as the forward pass weighted them
+        Store v = valid ? Model::template logpot<Store>(a.mp, xr, yn) : neg_inf<Store>();
+        if (!(v == v)) v = neg_inf<Store>();
+        lw[r] = static_cast<double>(v);
       }
 
       double lam[PPT][DX], D[PPT];
@@ -273,7 +276,7 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
             const int child = blo + it + b;
             double z[NZ];
             for (int g = 0; g < NZ / 4; ++g) {
-              double t[4];
+              Store t[4];
               normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(child),
                        static_cast<uint32_t>(n + 1), t);
 #pragma unroll
@@ -375,7 +378,7 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
       if (n == 0) {
         double z[NZ];
         for (int g = 0; g < NZ / 4; ++g) {
-          double t[4];
+          Store t[4];
           normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), 0u, t);
 #pragma unroll
           for (int q = 0; q < 4; ++q) z[4 * g + q] = t[q];

@@ -170,6 +170,34 @@ def test_math_bit_identical(ctx, orc):
         assert tuple(int(v) for v in gp[i]) == orc.philox((c0, c1, c2, c3), (k0, k1))
 
 
+def test_math_f32_bit_identical(ctx, orc):
+    """The binary32 functions of runs with binary32 particles: device and
+    oracle bit for bit, including special and extreme inputs."""
+    g = np.random.default_rng(1)
+    f = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)    # binary32 inputs
+    xs = f(np.concatenate([g.uniform(-104, 89, 40000), g.uniform(-30, 0, 40000), g.uniform(-1e-3, 1e-3, 2000),
+                           [0.0, -0.0, -87.3, -87.4, 88.72, 88.73, -125.0, -200.0, 1e-30, np.inf, -np.inf]]))
+    ge = ctx.debug_eval(5, xs)
+    oe = np.array([orc.expf(v) for v in xs])
+    np.testing.assert_array_equal(ge, oe)
+    ls = f(np.concatenate([np.exp(g.uniform(-87, 88, 40000)), g.uniform(0.5, 2, 40000),
+                           g.integers(1, 2**24, 5000) * 2.0**-24, [1e-40, 1e-45, 1.0, 0.0, np.inf, 2.0**-33]]))
+    gl = ctx.debug_eval(6, ls)
+    ol = np.array([orc.logf(v) for v in ls])
+    np.testing.assert_array_equal(gl, ol)
+    vs = f(g.integers(0, 2**32, 40000).astype(np.float32) * np.float32(2.0**-32))
+    gc, gs = ctx.debug_eval(7, vs)
+    oc = np.array([orc.cossin2pif(v) for v in vs])
+    np.testing.assert_array_equal(gc, oc[:, 0])
+    np.testing.assert_array_equal(gs, oc[:, 1])
+    words = np.concatenate([g.integers(0, 2**32, 80000, dtype=np.uint64).astype(np.uint32),
+                            np.array([0, 0, 2**32 - 1, 2**32 - 1, 255, 2**31, 2**32 - 128, 1], dtype=np.uint32)])
+    z0, z1 = ctx.debug_eval(8, words=words)
+    ob = np.array([orc.boxmullerf(int(words[2 * i]), int(words[2 * i + 1])) for i in range(words.size // 2)])
+    np.testing.assert_array_equal(z0, ob[:, 0])
+    np.testing.assert_array_equal(z1, ob[:, 1])
+
+
 def test_invalid_arguments(ctx):
     from paper_2312_06484_amd import airpf
     y = W.lg1_data(10)
