@@ -8,7 +8,9 @@ arithmetic, and returns the exact law of the estimate Zhat_T = gamma^N_T(1).
 Model: x in {0,1}, x_0 uniform, stay with probability 3/4, y = x with
 probability 3/4.  Systematic internal resampling with exact weights: the
 offset is continuous uniform on [0, G), G = sum_i g_i; slot j takes
-min{i : N C_i > U + j G}.  Stage s pairs k with k xor 2^(s-1); interaction
+min{i : N C_i > U + j G}.  Multinomial internal resampling (the i.i.d.
+draws of Algorithm 1 as written): slot j takes i with probability g_i / G,
+independently.  Stage s pairs k with k xor 2^(s-1); interaction
 iff ENF < tau; a block is taken from the partner with probability
 W_p/(W_k + W_p); the island weights become the pair mean.
 """
@@ -54,6 +56,19 @@ def systematic_outcomes(g, N):
     return list(out.items())
 
 
+def multinomial_outcomes(g, N):
+    """[(ancestors tuple, probability)]: N independent draws with P(i) = g_i / G."""
+    G = sum(g)
+    out = []
+    for anc in product(range(N), repeat=N):
+        pr = Fr(1)
+        for a in anc:
+            pr *= g[a] / G
+        if pr:
+            out.append((anc, pr))
+    return out
+
+
 def enf(W):
     m = len(W)
     s1, s2 = sum(W), sum(w * w for w in W)
@@ -62,8 +77,9 @@ def enf(W):
     return (s1 / m) ** 2 / (s2 / m)
 
 
-def law_of_zhat(y, m, N, tau):
+def law_of_zhat(y, m, N, tau, scheme="systematic"):
     """Exact law {Zhat: probability} of the AIRPF estimate after len(y) weightings."""
+    outcomes = systematic_outcomes if scheme == "systematic" else multinomial_outcomes
     tau = Fr(tau)
     S = m.bit_length() - 1
     T = len(y)
@@ -86,7 +102,7 @@ def law_of_zhat(y, m, N, tau):
         # internal resampling
         nd = defaultdict(Fr)
         for (xs, W), p in dist.items():
-            per_island = [systematic_outcomes([g_of(xs[k * N + i], y[n]) for i in range(N)], N)
+            per_island = [outcomes([g_of(xs[k * N + i], y[n]) for i in range(N)], N)
                           for k in range(m)]
             for combo in product(*per_island):
                 pr = p
