@@ -75,3 +75,19 @@ def lgd(A, H, q, r, p0, y, grad=True):
         return float(ll), None
     ll.backward()
     return float(ll.detach()), At.grad.numpy().reshape(-1).copy()
+
+
+def lg1_filter_means(theta, y):
+    """E[x_n | y_0..y_n] for n = 0..T-1 of the 1-D linear-Gaussian model (the
+    Kalman filter's updated means), float64 numpy."""
+    a, sx, sy = (float(v) for v in theta)
+    m, P = 0.0, 1.0
+    out = np.empty(len(y))
+    for t, yt in enumerate(np.asarray(y, dtype=np.float64)):
+        if t > 0:
+            m, P = a * m, a * a * P + sx * sx
+        S = P + sy * sy
+        K = P / S
+        m, P = m + K * (yt - m), (1.0 - K) * P
+        out[t] = m
+    return out

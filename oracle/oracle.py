@@ -41,7 +41,7 @@ class _Opts(C.Structure):
 
 class _Trace(C.Structure):
     _fields_ = [("sstar", _i32p), ("enf", _dp), ("lpost", _dp), ("anc", _i32p),
-                ("pi", _i32p), ("digest", _u64p), ("x", _dp), ("logz_inc", _dp)]
+                ("pi", _i32p), ("digest", _u64p), ("x", _dp), ("logz_inc", _dp), ("fmean", _dp)]
 
 
 _lib = None
@@ -210,7 +210,7 @@ class Trace:
     """Host arrays the oracle fills (or, in replay mode, reads)."""
 
     def __init__(self, prob, anc=True, pi=True, lpost=True, enf=True, digest=True,
-                 x=False, logz_inc=True):
+                 x=False, logz_inc=True, fmean=False):
         T, m, N = prob.T, prob.m, prob.N
         S = m.bit_length() - 1
         self.sstar = np.zeros(T, dtype=np.int32)
@@ -221,6 +221,7 @@ class Trace:
         self.digest = np.zeros(2 * T, dtype=np.uint64) if digest else None
         self.x = np.zeros(T * m * N * prob.dx) if x else None
         self.logz_inc = np.zeros(T) if logz_inc else None
+        self.fmean = np.zeros(T * m) if fmean else None
         self.S = S
 
     def _c(self):
@@ -233,6 +234,7 @@ class Trace:
         t.digest = _ptr(self.digest, _u64p)
         t.x = _ptr(self.x, _dp)
         t.logz_inc = _ptr(self.logz_inc, _dp)
+        t.fmean = _ptr(self.fmean, _dp)
         return t
 
 

@@ -53,6 +53,9 @@ typedef struct {
   uint64_t* digest;      /* [2*T]        ancestor / island-map digests       */
   double* x;             /* [T*m*N*dx]   state entering each weighting       */
   double* logz_inc;      /* [T]          log Zhat_{n+1} - log Zhat_n         */
+  double* fmean;         /* [T*m]        island k's weighted mean of the first
+                            state coordinate after the weighting:
+                            sum_i q_i x_i / Q, summed in particle order     */
 } orc_trace;
 
 /* ---- counter-based RNG (orc_rng.c) ---- */

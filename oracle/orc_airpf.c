@@ -242,6 +242,12 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
         if (mx != -INFINITY) se += orc_exp(lwk[j] - mx);
       }
       Qk[k] = Q;
+      if (tr && tr->fmean) {
+        /* the island's estimate of the filtering mean of x (first coordinate) */
+        double num = 0.0;
+        for (int32_t j = 0; j < N; ++j) num += (double)q[(int64_t)k * N + j] * x[((int64_t)k * N + j) * dx];
+        tr->fmean[n * m + k] = (Q == 0) ? NAN : num / (double)Q;
+      }
       L[k] = (Q == 0) ? -INFINITY : L[k] + ((mx + orc_log((double)Q)) + cst_q);
       Lx[k] = (mx == -INFINITY) ? -INFINITY : Lx[k] + ((mx + orc_log(se)) + cst_x);
       if (want_score) {

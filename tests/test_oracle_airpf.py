@@ -239,3 +239,35 @@ def test_float32_storage_accuracy_along_same_genealogy(orc):
     F32, _, _ = orc.frozen(P, tr, f32=True)
     F64, _, _ = orc.frozen(P, tr, f32=False)
     assert abs(F32 - F64) < 1e-4 * T
+
+
+def test_island_filter_means_track_the_kalman_filter(orc):
+    """The oracle's per-island weighted means of x after each weighting,
+    mixed by the island weights, estimate the filtering mean E[x_n | y_0..n]
+    (Section 3.2's pi^N_n): consistent with the Kalman filter's means within
+    their Monte Carlo error, and closer with more particles."""
+    from oracle import kalman
+    T = 12
+    y = W.lg1_data(T)
+    km = kalman.lg1_filter_means(W.LG1_THETA, y)
+
+    def est(m, N, seed):
+        P = lg1_problem(orc, T, m, N, seed, y=y)
+        tr = orc.Trace(P, anc=False, pi=False, enf=False, digest=False, fmean=True)
+        orc.run(P, tau=0.3, trace=tr)
+        L = tr.lpost.reshape(T, m)
+        F = tr.fmean.reshape(T, m)
+        w = np.exp(L - L.max(axis=1, keepdims=True))
+        return (w * F).sum(axis=1) / w.sum(axis=1)
+
+    e = np.array([est(16, 64, s) - km for s in range(1, 41)])
+    se = e.std(axis=0, ddof=1) / math.sqrt(e.shape[0])
+    assert np.all(np.abs(e.mean(axis=0)) < 4 * se + 1e-3)
+    small = np.sqrt(np.mean([(est(2, 4, s) - km) ** 2 for s in range(1, 41)]))
+    big = np.sqrt(np.mean(e ** 2))
+    assert big < small / 4, (small, big)
+    # one particle: the island's mean is that particle's state
+    P = lg1_problem(orc, T, 1, 1, 3, y=y)
+    tr = orc.Trace(P, x=True, fmean=True)
+    orc.run(P, tau=0.3, trace=tr)
+    np.testing.assert_array_equal(tr.fmean, tr.x)

@@ -78,3 +78,23 @@ def test_lgd_model_spectral_radius():
     A, H = W.lgd_model()
     assert A.shape == (8, 8) and H.shape == (4, 8)
     assert abs(np.max(np.abs(np.linalg.eigvals(A))) - 0.95) < 1e-12
+
+
+def test_lg1_filter_means_vs_dense_conditioning():
+    """The Kalman updated means equal E[x_n | y_0..y_n] from the joint
+    Gaussian of (x_n, y_0..y_n) built from the model's covariances."""
+    from oracle import kalman
+    th = (0.9, 0.8, 1.1)
+    a, sx, sy = th
+    T = 15
+    y = W.lg1_data(T, theta=th)
+    got = kalman.lg1_filter_means(th, y)
+    var = np.empty(T)
+    var[0] = 1.0
+    for t in range(1, T):
+        var[t] = a * a * var[t - 1] + sx * sx
+    for n in range(T):
+        Sx = np.array([[a ** abs(s - t) * var[min(s, t)] for t in range(n + 1)] for s in range(n + 1)])
+        Syy = Sx + sy * sy * np.eye(n + 1)
+        Sxy = Sx[n]                                  # Cov(x_n, y_t) = Cov(x_n, x_t)
+        assert abs(got[n] - Sxy @ np.linalg.solve(Syy, y[:n + 1])) < 1e-10
