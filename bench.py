@@ -59,10 +59,33 @@ def workload_inputs(name):
     return wl, y
 
 
+def _oracle_sample(args):
+    """One oracle run on the sample (a pool worker: imports only the oracle)."""
+    kind, theta, ys, m, N, seed, dx, dy, consts, f32 = args
+    from oracle import oracle as orc
+    P = orc.Problem(kind, theta, ys, m, N, seed, dx=dx, dy=dy, consts=consts)
+    t0 = time.perf_counter()
+    orc.run(P, tau=0.3, f32=f32)
+    return time.perf_counter() - t0
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, y, gpu_ctx, budget_steps):
-    """The CPU oracle, single-threaded, on the first `budget_steps`
-    observations of the same workload; also the GPU's log Zhat on that same
-    sample for the stated error."""
+    """The CPU oracle on the first `budget_steps` observations of the same
+    workload: single-threaded, then one process per usable host core running
+    the same sample with different seeds (the oracle as it stands, no
+    threading of its own); also the GPU's log Zhat on that sample for the
+    stated error."""
+    import multiprocessing as mp
     from oracle import oracle as orc
     kinds = {0: orc.LG1, 1: orc.SV, 2: orc.LGD}
     Ts = min(budget_steps, wl["T"])
@@ -75,9 +98,18 @@ def cpu_baseline(wl, y, gpu_ctx, budget_steps):
     _, lg = gpu_ctx.run(wl["kind"], wl["theta"], ys, wl["m"], wl["N"], 1, tau=0.3, fp64=not wl["f32"],
                         dx=wl["dx"], dy=wl["dy"], consts=wl["consts"])
     ps = wl["m"] * wl["N"] * Ts
-    return dict(value=ps / dt, unit="particle-steps/s", cores=1, kind="oracle",
-                sample="%s, first %d of %d observations, seed 1, single thread" % (wl["name"], Ts, wl["T"])), \
-        abs(lg - lo)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(cores, 16))
+    args = [(kinds[wl["kind"]], wl["theta"], ys, wl["m"], wl["N"], 1 + i, wl["dx"], wl["dy"], wl["consts"],
+             wl["f32"]) for i in range(cores)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        pool.map(_oracle_sample, args)
+    dt_all = time.perf_counter() - t0
+    return dict(value=cores * ps / dt_all, unit="particle-steps/s", cores=cores, kind="oracle",
+                sample="%s, first %d of %d observations; %d processes (one per usable core), seeds 1..%d, "
+                       "pool start-up included" % (wl["name"], Ts, wl["T"], cores, cores),
+                single_core_value=ps / dt, cpu_model=_cpu_model(), nproc=os.cpu_count()), abs(lg - lo)
 
 
 def fwd_bytes(dx, store_bytes):
@@ -106,13 +138,24 @@ def mode_record(particle_steps, seconds, bpp, **extra):
     return rec
 
 
-def timed(torch, fn):
-    fn(True)                                          # warm-up (also sizes the workspaces)
+REPEATS = 3          # timed calls per mode; the record gives the median and the spread
+
+
+def timed(torch, fn, spread=None):
+    """Median wall time of REPEATS calls after one warm-up call (which also
+    sizes the workspaces); `spread`, if given, receives min and max (ms)."""
+    fn(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = fn(False)
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0, r
+    ts, r = [], None
+    for _ in range(REPEATS):
+        t0 = time.perf_counter()
+        r = fn(False)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    if spread is not None:
+        spread.update(ms_min=ts[0] * 1e3, ms_max=ts[-1] * 1e3, repeats=REPEATS)
+    return ts[len(ts) // 2], r
 
 
 def measure_modes(ctx, torch):
@@ -126,28 +169,50 @@ def measure_modes(ctx, torch):
     against AIRPF, traced runs), and the 8-D LG workload forward and
     forward + score."""
     from paper_2312_06484_amd import workloads as W
+    from oracle import kalman
     out = {}
     dev = "cuda"
 
+    # the latency configuration: 1-D LG, T = 100, 8 islands of 32, FP64 state;
+    # log Zhat against the oracle's on the same seed and against Kalman
+    T, m, N = 100, 8, 32
+    y1 = W.lg1_data(T)
+    yd = torch.tensor(y1, dtype=torch.float64, device=dev)
+    sp = {}
+    dt, lz = timed(torch, lambda w: ctx.run(0, W.LG1_THETA, None, m, N, 77 if w else 1, tau=0.3, fp64=True,
+                                            y_device_ptr=yd.data_ptr(), T=T)[1], sp)
+    from oracle import oracle as orc
+    lo = orc.run(orc.Problem(orc.LG1, W.LG1_THETA, y1, m, N, 1), tau=0.3)
+    out["fwd_lg1_t100_m8_n32_f64"] = mode_record(m * N * T, dt, fwd_bytes(1, 8), log_z=lz,
+                                                 device_ms=ctx.last_kernel_ms(), logz_abs_vs_oracle=abs(lz - lo),
+                                                 logz_minus_kalman=lz - kalman.lg1(W.LG1_THETA, y1, grad=False)[0],
+                                                 **sp)
+
     # interactions off (tau = 0: independent bootstrap filters), 1-D LG, T=1000, 1024 x 256
     T, m, N = 1000, 1024, 256
-    yd = torch.tensor(W.lg1_data(T), dtype=torch.float64, device=dev)
+    y1 = W.lg1_data(T)
+    yd = torch.tensor(y1, dtype=torch.float64, device=dev)
+    sp = {}
     dt, lz = timed(torch, lambda w: ctx.run(0, W.LG1_THETA, None, m, N, 77 if w else 1, tau=0.0,
-                                            y_device_ptr=yd.data_ptr(), T=T)[1])
+                                            y_device_ptr=yd.data_ptr(), T=T)[1], sp)
     out["fwd_lg1_t1000_m1024_n256_f32_tau0"] = mode_record(m * N * T, dt, fwd_bytes(1, 4), log_z=lz,
-                                                          device_ms=ctx.last_kernel_ms())
+                                                          device_ms=ctx.last_kernel_ms(),
+                                                          logz_minus_kalman=lz - kalman.lg1(W.LG1_THETA, y1,
+                                                                                            grad=False)[0], **sp)
 
     # SV, T = 2000, 4096 x 128: forward, and forward + path-space score with checkpoints every 100 steps
     T, m, N = 2000, 4096, 128
     yd = torch.tensor(W.sv_data(T), dtype=torch.float64, device=dev)
+    sp = {}
     dt, lz = timed(torch, lambda w: ctx.run(1, W.SV_THETA, None, m, N, 99 if w else 1, tau=0.3,
-                                            y_device_ptr=yd.data_ptr(), T=T)[1])
+                                            y_device_ptr=yd.data_ptr(), T=T)[1], sp)
     out["fwd_sv_t2000_m4096_n128_f32"] = mode_record(m * N * T, dt, fwd_bytes(1, 4), log_z=lz,
-                                                     device_ms=ctx.last_kernel_ms())
+                                                     device_ms=ctx.last_kernel_ms(), **sp)
+    sp = {}
     dt, (_, lz, g) = timed(torch, lambda w: ctx.score(1, W.SV_THETA, None, m, N, 99 if w else 1, tau=0.3,
-                                                      ckpt_every=100, y_device_ptr=yd.data_ptr(), T=T))
+                                                      ckpt_every=100, y_device_ptr=yd.data_ptr(), T=T), sp)
     out["fwd_score_sv_t2000_m4096_n128_f32_k100"] = mode_record(m * N * T, dt, fwd_score_bytes(1, 4), log_z=lz,
-                                                                grad=list(g))
+                                                                grad=list(g), **sp)
 
     # 64 chains' proposals, uneven T, m, N: forward + score, batched and one at a time
     items = W.batch_c4(64)
@@ -162,15 +227,17 @@ def measure_modes(ctx, torch):
     bpp = fwd_score_bytes(1, 4)
     # the warm-up call has the timed call's shape, so it also measures and
     # caches the tiling (AIRPF_FLAG_AUTOTUNE) outside the timed region
+    spb = {}
     tb, (st, lzb, grb, ist) = timed(torch, lambda w: ctx.run_batch(1, probs, tau=0.3, want_score=True,
                                                                    ckpt_every=100, y_on_device=True,
-                                                                   autotune=True))
+                                                                   autotune=True), spb)
     # the forward alone (what a PMMH step calls), batched: the warm-up call
     # measures and caches its tiling too
+    sp = {}
     tf, (stf, lzf, _, istf) = timed(torch, lambda w: ctx.run_batch(1, probs, tau=0.3, want_score=False,
-                                                                    y_on_device=True, autotune=True))
+                                                                    y_on_device=True, autotune=True), sp)
     out["batched_fwd_sv_64_chains"] = mode_record(total, tf, fwd_bytes(1, 4), total_particle_steps=total,
-                                                  items_ok=int((istf == 0).sum()), tiling="autotuned")
+                                                  items_ok=int((istf == 0).sum()), tiling="autotuned", **sp)
     # PMMH on the SV posterior: 64 chains, each iteration's 64 proposals
     # scored by one batched forward (T = 500, 256 islands of 128 particles);
     # then particle MALA, each iteration one batched forward + score.  The
@@ -210,7 +277,7 @@ def measure_modes(ctx, torch):
                                          "ibpf": enf["ibpf"]["summary"], "airpf": enf["airpf"]["summary"],
                                          "log_z": {"ibpf": enf["ibpf"]["log_z"], "airpf": enf["airpf"]["log_z"]}}
     out["batched_fwd_score_sv_64_chains"] = mode_record(total, tb, bpp, total_particle_steps=total,
-                                                        items_ok=int((ist == 0).sum()), tiling="autotuned")
+                                                        items_ok=int((ist == 0).sum()), tiling="autotuned", **spb)
     t0 = time.perf_counter()
     same = True
     for p, lzv, gv in zip(probs, lzb, grb):
@@ -228,15 +295,78 @@ def measure_modes(ctx, torch):
     yd = torch.tensor(W.lgd_data(A, H, T).reshape(-1), dtype=torch.float64, device=dev)
     cst = W.lgd_consts(H)
     th = A.reshape(-1).tolist()
+    lzk8 = kalman.lgd(A, H, cst[0], cst[1], cst[2], W.lgd_data(A, H, T), grad=False)[0]
+    sp = {}
     dt, lz = timed(torch, lambda w: ctx.run(2, th, None, m, N, 99 if w else 1, tau=0.3, dx=8, dy=4, consts=cst,
-                                            y_device_ptr=yd.data_ptr(), T=T)[1])
+                                            y_device_ptr=yd.data_ptr(), T=T)[1], sp)
     out["fwd_lgd8_t500_m16384_n64_f32"] = mode_record(m * N * T, dt, fwd_bytes(8, 4), log_z=lz,
-                                                      device_ms=ctx.last_kernel_ms())
+                                                      device_ms=ctx.last_kernel_ms(), logz_minus_kalman=lz - lzk8,
+                                                      **sp)
+    sp = {}
     dt, (_, lz, g) = timed(torch, lambda w: ctx.score(2, th, None, m, N, 99 if w else 1, tau=0.3, dx=8, dy=4,
                                                       consts=cst, ckpt_every=50, y_device_ptr=yd.data_ptr(),
-                                                      T=T))
-    out["fwd_score_lgd8_t500_m16384_n64_f32_k50"] = mode_record(m * N * T, dt, fwd_score_bytes(8, 4), log_z=lz)
+                                                      T=T), sp)
+    out["fwd_score_lgd8_t500_m16384_n64_f32_k50"] = mode_record(m * N * T, dt, fwd_score_bytes(8, 4), log_z=lz,
+                                                                logz_minus_kalman=lz - lzk8, **sp)
     return out
+
+
+PROFILE_MODES = ("headline", "c1", "batch_fwd", "batch_fwd_score", "lgd8_fwd", "sv_fwd_score", "all")
+
+
+def profile_mode(name, ctx, torch, runs):
+    """One configuration alone, `runs` calls after one warm-up call, for the
+    counter passes of a profiler (each pass a run of its own): c1 (1-D LG,
+    T = 100, 8 x 32, FP64), batch_fwd / batch_fwd_score (the 64-chain SV
+    proposal batch, forward alone or with scores, K = 100), lgd8_fwd (8-D LG,
+    T = 500, 16384 x 64), sv_fwd_score (SV, T = 2000, 4096 x 128, K = 100),
+    headline (the benchmark workload), all (each of these in turn, so that
+    one profiler pass covers every kernel: their names differ)."""
+    from paper_2312_06484_amd import workloads as W
+    dev = "cuda"
+    if name == "all":
+        for n in PROFILE_MODES[:-1]:
+            profile_mode(n, ctx, torch, runs)
+        return
+    if name == "headline":
+        wl, y = workload_inputs("lg1_t1000_m1024_n256_f32")
+        yd = torch.tensor(y.reshape(-1), dtype=torch.float64, device=dev)
+        fn = lambda s: ctx.run(0, wl["theta"], None, wl["m"], wl["N"], s, tau=0.3, y_device_ptr=yd.data_ptr(),
+                               T=wl["T"])
+    elif name == "c1":
+        yd = torch.tensor(W.lg1_data(100), dtype=torch.float64, device=dev)
+        fn = lambda s: ctx.run(0, W.LG1_THETA, None, 8, 32, s, tau=0.3, fp64=True, y_device_ptr=yd.data_ptr(),
+                               T=100)
+    elif name in ("batch_fwd", "batch_fwd_score"):
+        probs, keep = [], {}
+        for it in W.batch_c4(64):
+            if it["T"] not in keep:
+                keep[it["T"]] = torch.tensor(W.sv_data(it["T"]), dtype=torch.float64, device=dev)
+            probs.append(dict(theta=it["theta"], y=keep[it["T"]].data_ptr(), T=it["T"], m=it["m"], N=it["N"],
+                              seed=it["seed"]))
+        score = name == "batch_fwd_score"
+        fn = lambda s: ctx.run_batch(1, probs, tau=0.3, want_score=score, ckpt_every=100 if score else 0,
+                                     y_on_device=True, autotune=True)
+    elif name == "lgd8_fwd":
+        A, H = W.lgd_model()
+        yd = torch.tensor(W.lgd_data(A, H, 500).reshape(-1), dtype=torch.float64, device=dev)
+        cst = W.lgd_consts(H)
+        fn = lambda s: ctx.run(2, A.reshape(-1).tolist(), None, 16384, 64, s, tau=0.3, dx=8, dy=4, consts=cst,
+                               y_device_ptr=yd.data_ptr(), T=500)
+    elif name == "sv_fwd_score":
+        yd = torch.tensor(W.sv_data(2000), dtype=torch.float64, device=dev)
+        fn = lambda s: ctx.score(1, W.SV_THETA, None, 4096, 128, s, tau=0.3, ckpt_every=100,
+                                 y_device_ptr=yd.data_ptr(), T=2000)
+    else:
+        raise SystemExit("unknown profile mode %r (one of %s)" % (name, ", ".join(PROFILE_MODES)))
+    fn(99)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(runs):
+        fn(k + 1)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_mode": name, "runs": runs, "ms_per_run": (time.perf_counter() - t0) / runs * 1e3}),
+          flush=True)
 
 
 def main():
@@ -250,6 +380,9 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the forward+score and batched-vs-plain measurements")
+    ap.add_argument("--profile-mode", choices=PROFILE_MODES, default=None,
+                    help="run only this configuration (a warm-up call and --steps calls) and exit: "
+                         "for profiler counter passes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the "
                          "reference reading for the HBM byte counters) and exit")
@@ -271,6 +404,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_per_copy": 4 * n, "copies": 5}))
+        return
+
+    if args.profile_mode:
+        ctx = airpf.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+        profile_mode(args.profile_mode, ctx, torch, args.steps)
+        ctx.close()
         return
 
     wl, y = workload_inputs(args.workload)

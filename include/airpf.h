@@ -32,11 +32,18 @@
  *     AIRPF_E_DOMAIN (theta outside its support) *log_z_out is -inf; on other
  *     errors outputs are set to NaN where they exist.  A run in which every
  *     island's weight vanishes is a valid estimate: AIRPF_OK, log Zhat = -inf.
+ *   - Observations are checked for NaN and infinities: host arrays before
+ *     anything is launched, device-resident ones (AIRPF_FLAG_Y_ON_DEVICE)
+ *     by the kernels as they read them; either way such a call returns
+ *     AIRPF_E_INVALID_ARG with NaN outputs (per item in a batch).
  *   - Tiling never changes a result.  Environment switches, read at each
  *     call, only change how the work is laid out: AIRPF_MAX_BLOCKS=<n> caps
  *     the blocks of a single-problem launch, AIRPF_PIPELINE=0 switches off
  *     the pipelined forward kernel (worker waves beside a control wave),
  *     AIRPF_TILER="alpha,beta" sets the batch tiler's cost ratio beta/alpha.
+ *     AIRPF_WORKSPACE_CAP=<bytes> caps every device buffer a context grows
+ *     (a call that needs more returns AIRPF_E_NOMEM, as a failed allocation
+ *     does).
  */
 #ifndef AIRPF_H
 #define AIRPF_H
@@ -64,8 +71,16 @@ typedef enum {
  *  AIRPF_LGD  x_0 ~ N(0, p0 I), x' = A x + sqrt(q) e, y = H x + sqrt(r) v;
  *             theta = vec(A) row-major (d_x^2 entries); consts =
  *             (q, r, p0, H row-major d_y x d_x), q, r, p0 > 0;
- *             d_x in {2, 3, 4, 8}, 1 <= d_y <= 8. */
-typedef enum { AIRPF_LG1 = 0, AIRPF_SV = 1, AIRPF_LGD = 2 } airpf_model_kind;
+ *             d_x in {2, 3, 4, 8}, 1 <= d_y <= 8.
+ *  AIRPF_BIN  the binary toy HMM of the exact-variance example (Section 4.1):
+ *             x_0 uniform on {0, 1}, x' = 1 - x with probability 1/4,
+ *             g(y | x) = 3/4 if y == x else 1/4 (observations 0 or 1; any
+ *             other value never matches);  no parameters (d_theta = 0, theta
+ *             may be NULL), d_x = d_y = 1.  Forward only (airpf_run,
+ *             airpf_run_noalloc); its states are 0/1 and always kept in
+ *             double (the precision option has no effect).  airpf_score and
+ *             airpf_run_batch return AIRPF_E_UNSUPPORTED. */
+typedef enum { AIRPF_LG1 = 0, AIRPF_SV = 1, AIRPF_LGD = 2, AIRPF_BIN = 3 } airpf_model_kind;
 
 typedef struct {
   int32_t kind;          /* airpf_model_kind */
@@ -112,6 +127,10 @@ typedef struct {
   int32_t* anc;      /* [(T-1)*m*N] within-island ancestors */
   int32_t* pi;       /* [(T-1)*m] island source map after the stages */
   uint64_t* digest;  /* [2*T] order-free digests of ancestors and island maps */
+  double* fmean;     /* [T*m] island k's estimate of the filtering mean of the first
+                        state coordinate after step n's weighting, sum_i q_i x_i / Q
+                        with the fixed-point weights q (the filter's estimate of
+                        E[x_n | y_0..y_n] is sum_k exp(lpost_k) fmean_k / sum_k exp(lpost_k)) */
 } airpf_trace;
 
 typedef struct airpf_ctx airpf_ctx;

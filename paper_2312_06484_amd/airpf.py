@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libairpf.so")
 
-LG1, SV, LGD = 0, 1, 2
+LG1, SV, LGD, BIN = 0, 1, 2, 3
 SYSTEMATIC, MULTINOMIAL = 0, 1
 FP32, FP64 = 0, 1
 PATHSPACE, PATHWISE = 0, 1
@@ -59,7 +59,7 @@ class _Problem(C.Structure):
 
 class _Trace(C.Structure):
     _fields_ = [("sstar", _i32p), ("enf", _dp), ("lpost", _dp), ("anc", _i32p),
-                ("pi", _i32p), ("digest", _u64p)]
+                ("pi", _i32p), ("digest", _u64p), ("fmean", _dp)]
 
 
 _lib = None
@@ -129,7 +129,7 @@ def _p(a, t):
 class Trace:
     """Host arrays a run fills (see airpf_trace in include/airpf.h)."""
 
-    def __init__(self, T, m, N, sstar=True, enf=True, lpost=True, anc=True, pi=True, digest=True):
+    def __init__(self, T, m, N, sstar=True, enf=True, lpost=True, anc=True, pi=True, digest=True, fmean=False):
         S = int(m).bit_length() - 1
         self.sstar = np.zeros(T, np.int32) if sstar else None
         self.enf = np.zeros(T * (S + 1)) if enf else None
@@ -137,11 +137,13 @@ class Trace:
         self.anc = np.zeros(max(T - 1, 0) * m * N, np.int32) if anc else None
         self.pi = np.zeros(max(T - 1, 0) * m, np.int32) if pi else None
         self.digest = np.zeros(2 * T, np.uint64) if digest else None
+        self.fmean = np.zeros(T * m) if fmean else None
 
     def _c(self):
         t = _Trace()
         t.sstar, t.enf, t.lpost = _p(self.sstar, _i32p), _p(self.enf, _dp), _p(self.lpost, _dp)
         t.anc, t.pi, t.digest = _p(self.anc, _i32p), _p(self.pi, _i32p), _p(self.digest, _u64p)
+        t.fmean = _p(self.fmean, _dp)
         return t
 
 
@@ -278,7 +280,7 @@ class Context:
                 keep.append(yy)
                 arr[i].y, arr[i].T = yy.ctypes.data_as(C.c_void_p), yy.size // int(dy)
             arr[i].m, arr[i].N, arr[i].seed = int(pr["m"]), int(pr["N"]), int(pr["seed"])
-        P = int(dx) * int(dx) if kind == LGD else 3
+        P = int(dx) * int(dx) if kind == LGD else (0 if kind == BIN else 3)
         lz = np.full(max(B, 1), np.nan)
         gr = np.full((max(B, 1), P), np.nan) if want_score else None
         ist = (C.c_int * max(B, 1))()

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libairpf.so")
 SOURCES = ["forward.hip", "forward_models_1d.hip", "forward_models_lgd23.hip", "forward_models_lgd4.hip",
-           "forward_models_lgd8.hip", "score.hip", "capi.hip"]
+           "forward_models_lgd8.hip", "forward_models_bin.hip", "score.hip", "capi.hip"]
 ARCH = "gfx950"
 
 

@@ -18,12 +18,23 @@
 
 namespace {
 
+// AIRPF_WORKSPACE_CAP=<bytes>: no context buffer may grow beyond this size
+// (a request that needs more reports AIRPF_E_NOMEM, as a failed allocation
+// would); read at each growth
+size_t workspace_cap() {
+  const char* e = std::getenv("AIRPF_WORKSPACE_CAP");
+  if (!e) return ~size_t(0);
+  const long long v = std::atoll(e);
+  return v > 0 ? static_cast<size_t>(v) : ~size_t(0);
+}
+
 // Grow-only device buffer owned by a context.
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
   airpf_status ensure(size_t bytes) {
     if (bytes <= cap) return AIRPF_OK;
+    if (bytes > workspace_cap()) return AIRPF_E_NOMEM;
     if (p) { (void)hipFree(p); p = nullptr; cap = 0; }
     size_t want = bytes < 256 ? 256 : bytes;
     if (hipMalloc(&p, want) != hipSuccess) { p = nullptr; return AIRPF_E_NOMEM; }
@@ -80,7 +91,7 @@ struct airpf_ctx {
   hipEvent_t ev[2] = {nullptr, nullptr};
   double last_kernel_ms = 0.0;
   DevBuf x1[2], tree[2], part[2], misc, ybuf;
-  DevBuf t_sstar, t_enf, t_lpost, t_anc, t_pi, t_dig;
+  DevBuf t_sstar, t_enf, t_lpost, t_anc, t_pi, t_dig, t_fmean;
   DevBuf s_pi, s_sstar, s_lpre, s_ckx, s_ckL, s_recx, s_reca, s_lam[2], s_del[2], s_grad, s_nu;
   DevBuf dbg_in, dbg_in32, dbg_out, dbg_out2, dbg_out32;
   DevBuf batch;
@@ -130,7 +141,7 @@ extern "C" airpf_status airpf_ctx_destroy(airpf_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
   for (DevBuf* b : {&c->x1[0], &c->x1[1], &c->tree[0], &c->tree[1], &c->part[0], &c->part[1], &c->misc,
-                    &c->ybuf, &c->t_sstar, &c->t_enf, &c->t_lpost, &c->t_anc, &c->t_pi, &c->t_dig,
+                    &c->ybuf, &c->t_sstar, &c->t_enf, &c->t_lpost, &c->t_anc, &c->t_pi, &c->t_dig, &c->t_fmean,
                     &c->dbg_in, &c->dbg_in32, &c->dbg_out, &c->dbg_out2, &c->dbg_out32, &c->s_pi,
                     &c->s_sstar, &c->s_lpre, &c->s_ckx, &c->s_ckL, &c->s_recx, &c->s_reca, &c->s_lam[0],
                     &c->s_lam[1], &c->s_del[0], &c->s_del[1], &c->s_grad, &c->s_nu, &c->batch})
@@ -149,7 +160,7 @@ namespace {
 airpf_status prepare_model(const airpf_model* model, const double* theta, int32_t d_theta, int32_t N,
                            airpf::ModelArgs* mp, double* cst_q, int* dx_out, int* dy_out) {
   std::memset(mp, 0, sizeof(*mp));
-  if (!model || !theta) return AIRPF_E_INVALID_ARG;
+  if (!model || (!theta && d_theta != 0)) return AIRPF_E_INVALID_ARG;
   const double LOG2PI = std::log(2.0 * M_PI);
   double c_log = 0.0;
   int dx = 1, dy = 1;
@@ -187,6 +198,12 @@ airpf_status prepare_model(const airpf_model* model, const double* theta, int32_
       mp->hr = 1.0 / (2.0 * r);
       for (int i = 0; i < dx * dy; ++i) mp->H[i] = model->consts[3 + i];
       c_log = -(0.5 * static_cast<double>(dy)) * std::log(2.0 * M_PI * r);
+      break;
+    }
+    case AIRPF_BIN: {
+      if (d_theta != 0 || model->dx != 1 || model->dy != 1) return AIRPF_E_INVALID_ARG;
+      mp->log3 = std::log(3.0);
+      c_log = std::log(0.75);
       break;
     }
     default:
@@ -245,10 +262,11 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
                      const airpf_options* opt_in, double* log_z_out, int max_blocks, Prepared* P,
                      unsigned char* fixed = nullptr) {
   set_nan(log_z_out);
-  if (!ctx || !model || !theta || !y || !log_z_out) return AIRPF_E_INVALID_ARG;
+  if (!ctx || !model || (!theta && d_theta != 0) || !y || !log_z_out) return AIRPF_E_INVALID_ARG;
   if (T < 1 || T > (int64_t(1) << 30) || !is_pow2(m) || N < 1 || N > 2048) return AIRPF_E_INVALID_ARG;
   if (m > kMaxIslands) return AIRPF_E_UNSUPPORTED;
   P->opt = opt_in ? *opt_in : default_options();
+  if (model->kind == AIRPF_BIN && P->opt.precision == AIRPF_FP32) P->opt.precision = AIRPF_FP64;   // 0/1 states
   const airpf_options& opt = P->opt;
   if (!(opt.tau == opt.tau)) return AIRPF_E_INVALID_ARG;
   if (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) return AIRPF_E_INVALID_ARG;
@@ -330,6 +348,8 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   }
   a.out_logz = reinterpret_cast<double*>(misc);
   a.status = reinterpret_cast<int*>(misc + 8);
+  a.bad_y = reinterpret_cast<int*>(misc + 12);
+  a.check_y = y_dev ? 1 : 0;
   a.bar = reinterpret_cast<unsigned*>(misc + 64);
   a.ring = reinterpret_cast<double*>(misc + ring_off);
   if (y_dev) {
@@ -365,6 +385,7 @@ airpf_status attach_trace(airpf_ctx* ctx, Prepared& P, airpf_trace* trace) {
   if (trace->pi && T > 1) { ST_OK(ctx->t_pi.ensure(4 * size_t(T - 1) * m)); a.tr_pi = static_cast<int32_t*>(ctx->t_pi.p); }
   if (trace->digest) { ST_OK(ctx->t_dig.ensure(16 * size_t(T))); a.tr_digest = static_cast<unsigned long long*>(ctx->t_dig.p);
                        HIP_OK(airpf::fill_u32(a.tr_digest, 0u, 4 * int64_t(T), s)); }
+  if (trace->fmean) { ST_OK(ctx->t_fmean.ensure(8 * size_t(T) * m)); a.tr_fmean = static_cast<double*>(ctx->t_fmean.p); }
   return AIRPF_OK;
 }
 
@@ -380,17 +401,19 @@ airpf_status copy_trace(airpf_ctx* ctx, const Prepared& P, airpf_trace* trace) {
   if (trace->anc && a.tr_anc) HIP_OK(hipMemcpyAsync(trace->anc, a.tr_anc, 4 * size_t(T - 1) * m * N, hipMemcpyDeviceToHost, s));
   if (trace->pi && a.tr_pi) HIP_OK(hipMemcpyAsync(trace->pi, a.tr_pi, 4 * size_t(T - 1) * m, hipMemcpyDeviceToHost, s));
   if (trace->digest && a.tr_digest) HIP_OK(hipMemcpyAsync(trace->digest, a.tr_digest, 16 * size_t(T), hipMemcpyDeviceToHost, s));
+  if (trace->fmean && a.tr_fmean) HIP_OK(hipMemcpyAsync(trace->fmean, a.tr_fmean, 8 * size_t(T) * m, hipMemcpyDeviceToHost, s));
   return AIRPF_OK;
 }
 
 airpf_status finish(airpf_ctx* ctx, const Prepared& P, double* log_z_out) {
   double lz = 0.0;
-  int kstatus = 0;
+  int kstatus[2] = {0, 0};                     // the status word and the bad-observation flag
   hipStream_t s = ctx->stream;
   HIP_OK(hipMemcpyAsync(&lz, P.a.out_logz, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(&kstatus, P.a.status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(kstatus, P.a.status, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  if (kstatus != 0) return AIRPF_E_DEVICE;
+  if (kstatus[1] != 0) return AIRPF_E_INVALID_ARG;     // a device-resident observation was not finite
+  if (kstatus[0] != 0) return AIRPF_E_DEVICE;
   float ms = 0.0f;
   HIP_OK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
   ctx->last_kernel_ms = ms;
@@ -443,6 +466,8 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   }
   // the reverse pass finds a particle's children as a run of sorted ancestors
   if (opt.resampling == AIRPF_MULTINOMIAL) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
+  // the binary model has no parameters and no differentiable mutation
+  if (model && model->kind == AIRPF_BIN) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
   if (model && ((model->kind == AIRPF_LGD && N > 512) || (model->kind != AIRPF_LGD && N > 1024))) {
     set_nan(log_z_out);
     return AIRPF_E_UNSUPPORTED;
@@ -528,11 +553,11 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   // reverse sweep.  A forward pass that failed skips the sweep too.
   {
     double lz_fwd = 0.0;
-    int st_fwd = 0;
+    int st_fwd[2] = {0, 0};
     HIP_OK(hipMemcpyAsync(&lz_fwd, a.out_logz, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(&st_fwd, a.status, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(st_fwd, a.status, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    if (st_fwd != 0 || lz_fwd == -INFINITY) {
+    if (st_fwd[0] != 0 || st_fwd[1] != 0 || lz_fwd == -INFINITY) {
       HIP_OK(hipEventRecord(ctx->ev[1], s));
       a.tr_pi = keep_pi;
       a.tr_sstar = keep_sstar;
@@ -719,6 +744,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
                                         int32_t want_score, double* log_z_out, double* grad_out,
                                         airpf_status* item_status) {
   if (!ctx || !model || B < 0 || (B > 0 && (!probs || !log_z_out || !item_status))) return AIRPF_E_INVALID_ARG;
+  if (model->kind == AIRPF_BIN) return AIRPF_E_UNSUPPORTED;        // single problems only
   const airpf_options opt = opt_in ? *opt_in : default_options();
   if (want_score && !grad_out) return AIRPF_E_INVALID_ARG;
   if (!(opt.tau == opt.tau) || (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) || opt.ckpt_every < 0)
@@ -814,6 +840,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   Arena ar;
   const size_t o_logz = ar.take(8 * items.size());
   const size_t o_status = ar.take(64);
+  const size_t o_bad = ar.take(4 * items.size());        // per problem: a device-resident observation not finite
   const size_t o_args = ar.take(sizeof(airpf::FwdArgs) * items.size() + sizeof(airpf::BwdArgs) * items.size());
   size_t o_bmap = 0;
   {
@@ -852,6 +879,8 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   auto at = [&](size_t o) { return static_cast<void*>(base + o); };
   int* d_status = static_cast<int*>(at(o_status));
   HIP_OK(airpf::fill_u32(d_status, 0u, 16, s));
+  int* d_bad = static_cast<int*>(at(o_bad));
+  HIP_OK(airpf::fill_u32(d_bad, 0u, int64_t(items.size()), s));
   for (Item& it : items)
     if (!y_dev)
       HIP_OK(hipMemcpyAsync(at(it.o_y), probs[it.idx].y, 8 * size_t(it.T) * dy, hipMemcpyHostToDevice, s));
@@ -901,6 +930,8 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
         }
         a.bar = static_cast<unsigned*>(at(it.o_flags));
         a.status = d_status;
+        a.bad_y = d_bad + (&it - items.data());
+        a.check_y = y_dev ? 1 : 0;
         a.out_logz = static_cast<double*>(at(o_logz)) + (&it - items.data());
         a.n0 = 0; a.n1 = it.T;
         fwd_fill(it, a);
@@ -1012,11 +1043,16 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
     // there): no reverse sweep, its score is zero; a failed forward launch
     // skips every sweep (reported below)
     std::vector<double> lz_fwd(items.size());
+    std::vector<int> bad_fwd(items.size());
     int st_fwd = 0;
     HIP_OK(hipMemcpyAsync(lz_fwd.data(), at(o_logz), 8 * lz_fwd.size(), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(bad_fwd.data(), d_bad, 4 * bad_fwd.size(), hipMemcpyDeviceToHost, s));
     HIP_OK(hipMemcpyAsync(&st_fwd, d_status, 4, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    auto swept = [&](const Item& it) { return st_fwd == 0 && lz_fwd[&it - items.data()] != -INFINITY; };
+    auto swept = [&](const Item& it) {
+      const size_t i = &it - items.data();
+      return st_fwd == 0 && bad_fwd[i] == 0 && lz_fwd[i] != -INFINITY;
+    };
     for (Item& it : items) HIP_OK(airpf::fill_u32(at(it.o_gisl), 0u, 2 * int64_t(it.m) * Pn, s));
     int64_t Cmax = 0;
     for (const Item& it : items) Cmax = std::max(Cmax, it.C);
@@ -1055,8 +1091,10 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   if (st != AIRPF_OK) { for (const Item& it : items) item_status[it.idx] = st; return st; }
 
   std::vector<double> lz(items.size());
+  std::vector<int> bad(items.size());
   int kstatus = 0;
   HIP_OK(hipMemcpyAsync(lz.data(), at(o_logz), 8 * lz.size(), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(bad.data(), d_bad, 4 * bad.size(), hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(&kstatus, d_status, 4, hipMemcpyDeviceToHost, s));
   if (want_score)
     for (const Item& it : items)
@@ -1069,6 +1107,13 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   float ms = 0.0f;
   HIP_OK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
   ctx->last_kernel_ms = ms;
-  for (size_t i = 0; i < items.size(); ++i) log_z_out[items[i].idx] = lz[i];
+  for (size_t i = 0; i < items.size(); ++i) {
+    if (bad[i]) {                                  // reported per item; the outputs stay NaN
+      item_status[items[i].idx] = AIRPF_E_INVALID_ARG;
+      if (want_score) for (int q = 0; q < Pn; ++q) grad_out[size_t(items[i].idx) * Pn + q] = std::nan("");
+      continue;
+    }
+    log_z_out[items[i].idx] = lz[i];
+  }
   return AIRPF_OK;
 }

@@ -12,6 +12,9 @@
 //   LGD  x_0[d] = sqrt(p0)*z_d;  x'[i] = sqrt(q)*z_i then fma(A[i][c], x[c], .)
 //        over c;  e_i = y_i then fma(-H[i][c], x[c], .) over c;
 //        ss = fma(e_i, e_i, ss) over i;  lw = -(ss*(1/(2r)))
+//   BIN  z is the particle's raw 32-bit word (not a normal variate):
+//        x_0 = bit 31 of z;  x' = 1 - x when bits 31..30 of z are zero,
+//        else x;  lw = 0 when x == y, else -log 3
 //
 // Derivatives for the score (plain double arithmetic, no bit-exactness
 // contract): d lw/dx, d log g/d theta (the constant of log g included),
@@ -37,6 +40,7 @@ struct ModelArgs {
   float thf[kMaxTheta];
   float Hf[kMaxDy * 8];
   float s0f, sqf, sp0f, hrf, isyf;
+  double log3;                // BIN: log 3 from the host
   int dy;
 };
 
@@ -54,6 +58,7 @@ template <typename R> __device__ __forceinline__ R hpar(const ModelArgs& p, int 
 
 struct LG1 {
   static constexpr int DX = 1;
+  static constexpr bool kWordNoise = false;     // N(0,1) noise
   static constexpr bool kThetaOuter = false;   // see LGD
   template <typename R>
   __device__ static void init(const ModelArgs&, const R* z, R* x) { x[0] = z[0]; }
@@ -91,6 +96,7 @@ struct LG1 {
 
 struct SV {
   static constexpr int DX = 1;
+  static constexpr bool kWordNoise = false;     // N(0,1) noise
   static constexpr bool kThetaOuter = false;   // see LGD
   template <typename R>
   __device__ static void init(const ModelArgs& p, const R* z, R* x) {
@@ -124,6 +130,32 @@ struct SV {
     acc[0] += lam[0];
     acc[1] += lam[0] * z[0] * p.ds0_dphi;
     acc[2] += lam[0] * z[0] * p.ds0_dsig;
+  }
+};
+
+// The binary toy HMM of the exact-variance example (Section 4.1): a
+// two-state chain that starts uniform and flips with probability 1/4 per
+// step, observed through a channel that reports the state with probability
+// 3/4.  A particle's noise is one raw 32-bit word per step (drawn with its
+// own tag), so the states stay exactly 0 or 1 and the log-potential takes
+// the two values 0 and -log 3 (the constant log(3/4) is added per island).
+// No parameters; forward only.
+struct BIN {
+  static constexpr int DX = 1;
+  static constexpr bool kWordNoise = true;
+  static constexpr bool kThetaOuter = false;
+  static constexpr int P = 0;
+  template <typename R>
+  __device__ static void init(const ModelArgs&, const R* z, R* x) {
+    x[0] = static_cast<R>(static_cast<uint32_t>(z[0]) >> 31);
+  }
+  template <typename R>
+  __device__ static void prop(const ModelArgs&, const R* xp, const R* z, R* x) {
+    x[0] = (static_cast<uint32_t>(z[0]) >> 30) == 0u ? R(1) - xp[0] : xp[0];
+  }
+  template <typename R>
+  __device__ static R logpot(const ModelArgs& p, const R* x, const double* y) {
+    return static_cast<double>(x[0]) == y[0] ? R(0) : static_cast<R>(-p.log3);
   }
 };
 
@@ -164,6 +196,7 @@ struct LGD {
   // theta, so a step's contribution of a slot is (sum over its children of
   // lam) xp^T, formed once per slot instead of once per child
   static constexpr bool kThetaOuter = true;
+  static constexpr bool kWordNoise = false;
   static constexpr int P = D * D;
   __device__ static void dlogpot_dx(const ModelArgs& p, const double* x, const double* y, double* g) {
     const double inv_r = 2.0 * p.hr;

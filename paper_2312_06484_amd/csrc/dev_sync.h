@@ -383,6 +383,18 @@ __device__ __forceinline__ EnfRec enf_join(const EnfRec& x, const EnfRec& y) {
                 __builtin_ldexp(x.b, 2 * dx) + __builtin_ldexp(y.b, 2 * dy)};
 }
 
+// Whether the stage's ENF am^2 / bm lies below tau, decided as the rounded
+// quotient decides it.  Far from the threshold the product tau * bm settles
+// it (a relative margin of 2^-40 covers the roundings of both sides); only
+// within the margin is the division done.  bm = 0 (NaN or infinite
+// quotient) is never below.
+__device__ __forceinline__ bool enf_below(double am, double bm, double tau) {
+  const double num = am * am, lim = tau * bm;
+  if (num < lim * (1.0 - 0x1p-40)) return true;
+  if (num > lim * (1.0 + 0x1p-40)) return false;
+  return num / bm < tau;
+}
+
 // One wave reduces n <= 1024 ENF records (n a power of two) by the
 // adjacent-pair tree: lane l first joins its aligned run of n/64 records,
 // then lanes join in a butterfly over groups of 2, 4, ..., min(n, 64).  The
@@ -407,6 +419,53 @@ __device__ __forceinline__ EnfRec wave_butterfly_enf(EnfRec r, int n) {
     r = enf_join(r, EnfRec{__shfl_xor(r.E, 16, 64), __shfl_xor(r.a, 16, 64), __shfl_xor(r.b, 16, 64)});
   }
   return r;
+}
+
+// The join of the n records of a wave (n <= 256 a power of two; lane l
+// holds records per*l .. per*l + per - 1, per = max(1, n/64) <= 4, the rest
+// empty) over the adjacent-pair tree, in one rescaling: every record is
+// brought to the largest E of all, then a and b are summed over the same
+// tree as wave_butterfly_enf.  The result equals the pairwise joins bit for
+// bit: scaling by a power of two commutes with each rounded sum while the
+// values stay normal, and a term scaled below 2^-1000 of the largest is
+// lost below rounding either way (up to the rounding of such a subnormal
+// term).  Every lane gets the record.
+__device__ __forceinline__ EnfRec wave_join_flat(const EnfRec* rec, int per, int n) {
+  double e = rec[0].E;
+  if (per >= 2) e = fmax(e, rec[1].E);
+  if (per >= 4) e = fmax(e, fmax(rec[2].E, rec[3].E));
+  e = fmax(e, dppd<0xB1>(e));
+  e = fmax(e, dppd<0x4E>(e));
+  e = fmax(e, dppd<0x141>(e));
+  e = fmax(e, dppd<0x140>(e));
+  e = fmax(fmax(readlane_f64(e, 0), readlane_f64(e, 16)), fmax(readlane_f64(e, 32), readlane_f64(e, 48)));
+  double A[4], B[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int g = static_cast<int>(fmax(rec[j].E - e, -4000.0));     // an empty record's gap is -inf or NaN
+    A[j] = __builtin_ldexp(rec[j].a, g);
+    B[j] = __builtin_ldexp(rec[j].b, 2 * g);
+  }
+  double a = per == 4 ? (A[0] + A[1]) + (A[2] + A[3]) : (per == 2 ? A[0] + A[1] : A[0]);
+  double b = per == 4 ? (B[0] + B[1]) + (B[2] + B[3]) : (per == 2 ? B[0] + B[1] : B[0]);
+  const int nl = n >= 64 ? 64 : n;                                  // lanes holding records
+  if (nl >= 2) { a += dppd<0xB1>(a); b += dppd<0xB1>(b); }
+  if (nl >= 4) { a += dppd<0x4E>(a); b += dppd<0x4E>(b); }
+  if (nl >= 8) { a += dppd<0x141>(a); b += dppd<0x141>(b); }
+  if (nl >= 16) { a += dppd<0x140>(a); b += dppd<0x140>(b); }
+  if (nl >= 64) {
+    a = (readlane_f64(a, 0) + readlane_f64(a, 16)) + (readlane_f64(a, 32) + readlane_f64(a, 48));
+    b = (readlane_f64(b, 0) + readlane_f64(b, 16)) + (readlane_f64(b, 32) + readlane_f64(b, 48));
+  } else if (nl >= 32) {
+    a += __shfl_xor(a, 16, 64);
+    b += __shfl_xor(b, 16, 64);
+    a = readlane_f64(a, 0);
+    b = readlane_f64(b, 0);
+  } else {
+    a = readlane_f64(a, 0);
+    b = readlane_f64(b, 0);
+  }
+  return EnfRec{e, a, b};
 }
 
 template <class F>

@@ -40,6 +40,7 @@
 #include <hip/hip_cooperative_groups.h>
 #include <stdint.h>
 #include <cstdlib>
+#include <type_traits>
 
 #include "dev_models.h"
 #include "dev_sync.h"
@@ -48,6 +49,31 @@
 namespace airpf {
 
 // ------------------------------------------------------------ the kernel
+
+// The mutation noise of one lane's particles j0 .. j0 + PPT - 1 at (step n,
+// island k): PPT * DX normal variates from the lane's blocks of four, or,
+// for a model driven by raw words (the binary model), the first word of
+// each particle's own Philox block (counter j, tag kTagBin), exact in double.
+template <class Model, typename Store, int PPT>
+__device__ __forceinline__ void draw_noise(const Key& key, int64_t n, int k, int j0, Store* z) {
+  constexpr int NZ = PPT * Model::DX;
+  if constexpr (Model::kWordNoise) {
+    static_assert(std::is_same<Store, double>::value, "raw words are kept exactly in double");
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      uint32_t w[4];
+      draw4(key, static_cast<uint32_t>(j0 + r), static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagBin, 0, w);
+      z[r] = static_cast<Store>(w[0]);
+    }
+  } else {
+    for (int g = 0; g < NZ / 4; ++g) {
+      Store t[4];
+      normals4(key, static_cast<uint32_t>((j0 * Model::DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
+    }
+  }
+}
 
 // One problem's filter, run by the G blocks of its sub-grid; `bid` is this
 // block's index within them.
@@ -85,6 +111,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   int32_t* const tr_anc = Plain ? nullptr : a.tr_anc;
   int32_t* const tr_pi = Plain ? nullptr : a.tr_pi;
   unsigned long long* const tr_digest = Plain ? nullptr : a.tr_digest;
+  double* const tr_fmean = Plain ? nullptr : a.tr_fmean;
   double* const tr_lpre = Plain ? nullptr : a.tr_lpre;
   void* const rec_x = Plain ? nullptr : a.rec_x;
   uint16_t* const rec_anc = Plain ? nullptr : a.rec_anc;
@@ -115,7 +142,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   // tau so small that no stage can ever interact, and nothing traced or
   // recorded: the blocks are independent until the final log Zhat
   const bool never = a.no_interaction && !tr_enf && !tr_sstar && !tr_pi && !tr_lpost && !tr_anc &&
-                     !tr_digest && !tr_lpre && !rec_x && !rec_anc && !ck_x && !ck_in;
+                     !tr_digest && !tr_fmean && !tr_lpre && !rec_x && !rec_anc && !ck_x && !ck_in;
 
   // levels lc+1 .. `level` of the island tree in `up`, built on demand from
   // the G published block roots (identical in every block); up_top is the
@@ -152,14 +179,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 
   const bool replay = !Plain && a.replay_pi != 0;
   // normals of (step, island, particle) for this lane's particles
-  auto draw_normals = [&](int64_t n, int k, int j0, Store* z) {
-    for (int g = 0; g < NZ / 4; ++g) {
-      Store t[4];
-      normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
-    }
-  };
+  auto draw_normals = [&](int64_t n, int k, int j0, Store* z) { draw_noise<Model, Store, PPT>(key, n, k, j0, z); };
   // Speculation: the stages of most steps do not interact (s* = 0), and then
   // every island continues from its own resampled block with its own weight,
   // all of which this block holds.  With the resampled states resident in
@@ -169,7 +189,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   // blocks written out) or the step is run again as usual.  The results are
   // the same either way.
   const bool spec_on = a.res_lds && !never && !replay && !a.shortcut_all && !tr_enf && !tr_sstar && !tr_pi &&
-                       !tr_lpost && !tr_anc && !tr_digest && !tr_lpre && !rec_x && !rec_anc && !ck_x &&
+                       !tr_lpost && !tr_anc && !tr_digest && !tr_fmean && !tr_lpre && !rec_x && !rec_anc && !ck_x &&
                        !ck_in;
   bool pending = false;     // step n-1 is published and its cascade not yet taken
   bool spec_done = false;   // step n's passes have run speculatively
@@ -231,7 +251,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
             // after s-1 interacting stages every island holds its 2^{s-1}-block
             // mean: sum_k W_k = 2^{s-1} sum_b w_b, sum_k W_k^2 = 2^{s-1} sum_b w_b^2
             const double blk = static_cast<double>(1 << (sw - 1));
-            const double am = (blk * r.a) / static_cast<double>(m), bm = (blk * r.b) / static_cast<double>(m);
+            const double am = (blk * r.a) * __builtin_ldexp(1.0, -S), bm = (blk * r.b) * __builtin_ldexp(1.0, -S);   // m = 2^S: scaling by the exact reciprocal is the division
             if ((tid & 63) == 0) { s_enf[wave] = (am * am) / bm; s_encmax[wave] = r.E; }
           }
           __syncthreads();
@@ -393,6 +413,11 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 
       // ---- weighting ----
       const double* yn = a.y + n * a.dy;
+      if (a.check_y && lane == 0 && active) {           // observations the host could not check
+        bool fin = true;
+        for (int i = 0; i < a.dy; ++i) fin = fin && isfinite(yn[i]);
+        if (!fin) put(a.bad_y, 1);
+      }
       Store lw[PPT];
       Store mx = neg_inf<Store>();
 #pragma unroll
@@ -419,6 +444,14 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         const double L = (Qk == 0) ? ninf() : Lpre + ((static_cast<double>(mx) + dlog(static_cast<double>(Qk))) + a.cst_q);
         lvp(par)[li] = L;
         if (tr_lpost) tr_lpost[n * m + k] = L;
+      }
+      if (tr_fmean) {
+        // the island's estimate of the filtering mean of x[0]: sum_i q_i x_i / Q
+        double num = 0.0;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) num += (active && j0 + r < N) ? static_cast<double>(q[r]) * static_cast<double>(x[r][0]) : 0.0;
+        num = team_sum_f64(num, TP, red_d);
+        if (lane == 0 && active) tr_fmean[n * m + k] = Qk == 0 ? __longlong_as_double(0x7ff8000000000000LL) : num / static_cast<double>(Qk);
       }
 
       // ---- internal resampling ----
@@ -648,11 +681,15 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 // passes: a step whose stage 1 does not interact moves no state through
 // HBM at all.
 constexpr int kPipeBlock = kBlock + 64;
+constexpr int kYChunk = 64;                 // observation steps per LDS chunk
 
 // Rec: the forward run of the score, which also keeps each step's island
 // maps, s*, entering weights, and checkpoints every ck_every steps (no
 // other trace, no replay).
-template <class Model, typename Store, int PPT, bool Rec>
+// TPC > 0: compiled for teams of TPC lanes and full islands (N = TPC * PPT),
+// so that the team reductions, scans and bounds are resolved at compile
+// time (no branch on the team width); 0: any width, read from the arguments.
+template <class Model, typename Store, int PPT, bool Rec, int TPC = 0>
 __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;
@@ -665,13 +702,21 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   __shared__ int s_src[kMaxIslandsPerBlock];
   __shared__ double s_lpre[kMaxIslandsPerBlock];
   __shared__ int s_ctl[2];                    // s* of the step just decided; 1: leave
+  // the observations of 64 steps at a time, two chunks: the control wave
+  // loads chunk j + 1 while the workers use chunk j, so that no worker pass
+  // waits on a memory load for its observation
+  __shared__ double s_y[2][kYChunk * kMaxDy];
+  // each island's level-1 ENF leaf (E, a, b) by step parity, formed by the
+  // island's team right after its weighting (the control wave only joins
+  // the block's leaves)
+  __shared__ EnfRec s_leaf[2][kMaxIslandsPerBlock];
 
   const int tid = threadIdx.x;
   const bool ctl = tid >= kBlock;             // the control wave
   const int lane64 = tid & 63;
-  const int TP = a.TP, tpb = kBlock / TP;
+  const int TP = TPC ? TPC : a.TP, tpb = kBlock / TP;
   const int team = tid / TP, lane = tid & (TP - 1);
-  const int m = a.m, N = a.N, S = a.S, c = a.c, lc = a.lc, G = a.G;
+  const int m = a.m, N = TPC ? TPC * PPT : a.N, S = a.S, c = a.c, lc = a.lc, G = a.G;
   const int64_t T = a.T;
   const int kbase = bid * c;
   const Key key = make_key(a.seed);
@@ -698,6 +743,11 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
 
   // ================= worker waves: the island passes of step n =================
   // spec: sources and entering weights under s*_{n-1} = 0
+  // a team with one island per step (one pass) draws the first block of
+  // the systematic-resampling words of its next TP steps at once, lane l
+  // the block of step base + l; the words are the same either way
+  const bool sys_batch = passes == 1 && TP >= 16;
+  uint32_t sysw[4] = {0u, 0u, 0u, 0u};
   auto run_passes = [&](int64_t n, bool spec) {
     const int par = static_cast<int>(n & 1), ppar = par ^ 1;
     for (int p = 0; p < passes; ++p) {
@@ -706,17 +756,21 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       const int k = kbase + (active ? li : 0);
       const int j0 = lane * PPT;
       uint32_t wsys[4] = {0u, 0u, 0u, 0u};
-      if (n < T - 1 && lane == 0) draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
+      if (sys_batch) {
+        const int64_t base = n - n % TP;
+        if (n == base && base + lane < T - 1)
+          draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(base + lane), kTagSys, 0, sysw);
+        const int src_lane = (tid & 63 & ~(TP - 1)) | static_cast<int>(n - base);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wsys[i] = static_cast<uint32_t>(__shfl(static_cast<int>(sysw[i]), src_lane, 64));
+      } else if (n < T - 1 && lane == 0) {
+        draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
+      }
       Store x[PPT][DX];
       double Lpre = 0.0;
       if (n == 0) {
         Store z[NZ];
-        for (int g = 0; g < NZ / 4; ++g) {
-          Store t[4];
-          normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
-        }
+        draw_noise<Model, Store, PPT>(key, n, k, j0, z);
 #pragma unroll
         for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * DX, x[r]);
       } else {
@@ -737,12 +791,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
             for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? get(xin + (j0 + r) * DX + d) : Store(0);
         }
         Store z[NZ];
-        for (int g = 0; g < NZ / 4; ++g) {
-          Store t[4];
-          normals4(key, static_cast<uint32_t>((j0 * DX) / 4 + g), static_cast<uint32_t>(k), static_cast<uint32_t>(n), t);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) z[4 * g + r] = t[r];
-        }
+        draw_noise<Model, Store, PPT>(key, n, k, j0, z);
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           Store xp[DX];
@@ -770,7 +819,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       }
 
       // ---- weighting ----
-      const double* yn = a.y + n * a.dy;
+      const double* yn = s_y[(n / kYChunk) & 1] + (n % kYChunk) * a.dy;
       Store lw[PPT];
       Store mx = neg_inf<Store>();
 #pragma unroll
@@ -794,6 +843,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       if (lane == 0 && active) {
         const double L = (Qk == 0) ? ninf() : Lpre + ((static_cast<double>(mx) + dlog(static_cast<double>(Qk))) + a.cst_q);
         lvp(par)[li] = L;
+        s_leaf[par][li] = enf_leaf(L);
       }
 
       // ---- internal resampling (systematic, by offspring counts) ----
@@ -932,16 +982,20 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     __builtin_amdgcn_s_waitcnt(0);
     ++epoch;
     if (lane64 == 0) put(&a.bar[bid], epoch);
+    // a lane watches the flags of blocks lane, lane + 64, ... (G <= 256):
+    // all of them are loaded before any is tested, one round trip per poll
     int ok = 1;
-    for (int i = lane64; i < G && ok; i += 64) {
-      unsigned spins = 0;
-      while (get(&a.bar[i]) < epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if ((++spins & 1023u) == 0 && (spins > (1u << 24) || get(a.status) != 0)) {
-          put(a.status, 1);
-          ok = 0;
-          break;
-        }
+    unsigned spins = 0;
+    while (true) {
+      unsigned f[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) f[j] = lane64 + 64 * j < G ? get(&a.bar[lane64 + 64 * j]) : epoch;
+      if (f[0] >= epoch && f[1] >= epoch && f[2] >= epoch && f[3] >= epoch) break;
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 1023u) == 0 && (spins > (1u << 24) || get(a.status) != 0)) {
+        put(a.status, 1);
+        ok = 0;
+        break;
       }
     }
     return __all(ok) != 0;
@@ -961,8 +1015,8 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   // record sees the cleared slot.
   auto level1 = [&](int64_t t, EnfRec& out) -> bool {
     const int slot = static_cast<int>(t % 3), prev = static_cast<int>((t + 2) % 3);
-    const double* lv = lvp(static_cast<int>(t & 1));
-    const EnfRec own = wave_reduce_enf(c, [&](int i) { return enf_leaf(lv[i]); });
+    const EnfRec* lf = s_leaf[t & 1];
+    const EnfRec own = wave_reduce_enf(c, [&](int i) { return lf[i]; });
     const EnfRec mine{readlane_f64(own.E, 0), readlane_f64(own.a, 0), readlane_f64(own.b, 0)};
     const int64_t copy_stride = 9 * static_cast<int64_t>(G);
     __builtin_amdgcn_s_waitcnt(0);
@@ -1000,10 +1054,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
         break;
       }
     }
-    EnfRec r = per == 4 ? enf_join(enf_join(rec[0], rec[1]), enf_join(rec[2], rec[3]))
-                        : (per == 2 ? enf_join(rec[0], rec[1]) : rec[0]);
-    r = wave_butterfly_enf(r, G);
-    out = EnfRec{readlane_f64(r.E, 0), readlane_f64(r.a, 0), readlane_f64(r.b, 0)};
+    out = wave_join_flat(rec, per, G);
     const bool done = __all(ok) != 0;
     if (done && lane64 < kRingCopies) {
       double* rp = a.ring + lane64 * copy_stride + static_cast<int64_t>(prev) * 3 * G;
@@ -1013,6 +1064,20 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       put(rp + 2 * G + bid, nan);
     }
     return done;
+  };
+  // the observations of chunk j (steps j * kYChunk onwards) into s_y[j & 1];
+  // observations the host could not check are checked here
+  auto load_y = [&](int64_t j) {
+    const int dy = a.dy;
+    const int64_t n0 = j * kYChunk;
+    double* dst = s_y[j & 1];
+    bool fin = true;
+    for (int i = lane64; i < kYChunk * dy; i += 64) {
+      const double v = n0 + i / dy < T ? a.y[n0 * dy + i] : 0.0;
+      fin = fin && isfinite(v);
+      dst[i] = v;
+    }
+    if (a.check_y && !fin) put(a.bad_y, 1);
   };
   // resampled blocks of step t from LDS to HBM
   auto write_out = [&](int64_t t) {
@@ -1060,8 +1125,8 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
         return;
       }
       const double blk = static_cast<double>(1 << (s - 1));
-      const double am = (blk * r.a) / static_cast<double>(m), bm = (blk * r.b) / static_cast<double>(m);
-      if (!((am * am) / bm < a.tau)) break;
+      const double am = (blk * r.a) * __builtin_ldexp(1.0, -S), bm = (blk * r.b) * __builtin_ldexp(1.0, -S);   // m = 2^S: scaling by the exact reciprocal is the division
+      if (!enf_below(am, bm, a.tau)) break;
       sstar = s;
       if (s == 1) {
         write_out(t);
@@ -1096,12 +1161,23 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   };
 
   // ================= the step loop =================
-  if (ctl && lane64 == 0) { s_ctl[0] = 0; s_ctl[1] = 0; }
+  if (ctl) {
+    if (lane64 == 0) { s_ctl[0] = 0; s_ctl[1] = 0; }
+    load_y(0);
+  }
+  __syncthreads();
   if (!ctl) run_passes(0, false);
+  else if (T > kYChunk) load_y(1);
   __syncthreads();
   for (int64_t n = 1; n < T; ++n) {
-    if (ctl) control_step(n - 1);
-    else run_passes(n, true);
+    if (ctl) {
+      control_step(n - 1);
+      // chunk n/64 + 1 into the buffer of chunk n/64 - 1, whose last step
+      // (n - 1) is done
+      if (n % kYChunk == 0 && n + kYChunk < T) load_y(n / kYChunk + 1);
+    } else {
+      run_passes(n, true);
+    }
     __syncthreads();
     if (s_ctl[1]) return;
     if (s_ctl[0] > 0) {
@@ -1125,9 +1201,9 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   }
 }
 
-template <class Model, typename Store, int PPT, bool Rec>
+template <class Model, typename Store, int PPT, bool Rec, int TPC = 0>
 __global__ __launch_bounds__(kPipeBlock) void forward_pipe_kernel(FwdArgs a) {
-  forward_pipe_body<Model, Store, PPT, Rec>(a, static_cast<int>(blockIdx.x));
+  forward_pipe_body<Model, Store, PPT, Rec, TPC>(a, static_cast<int>(blockIdx.x));
 }
 
 template <class Model, typename Store, int PPT, bool Plain>
@@ -1167,7 +1243,7 @@ inline int ilog2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
 
 // nothing traced, recorded, replayed or checkpointed: the Plain kernel runs it
 inline bool fwd_is_plain(const FwdArgs& a) {
-  return !a.tr_sstar && !a.tr_enf && !a.tr_lpost && !a.tr_anc && !a.tr_pi && !a.tr_digest && !a.tr_lpre && !a.rec_x &&
+  return !a.tr_sstar && !a.tr_enf && !a.tr_lpost && !a.tr_anc && !a.tr_pi && !a.tr_digest && !a.tr_fmean && !a.tr_lpre && !a.rec_x &&
          !a.rec_anc && !a.ck_x && !a.ck_L && !a.ck_in && a.ck_every == 0 && !a.replay_pi && a.n0 == 0 && a.n1 == a.T;
 }
 
@@ -1178,7 +1254,7 @@ inline bool fwd_is_plain(const FwdArgs& a) {
 // the score's forward: island maps, s*, entering weights and checkpoints
 // kept, nothing else traced or replayed
 inline bool fwd_is_score_forward(const FwdArgs& a) {
-  return !a.tr_enf && !a.tr_lpost && !a.tr_anc && !a.tr_digest && !a.rec_x && !a.rec_anc && !a.ck_in &&
+  return !a.tr_enf && !a.tr_lpost && !a.tr_anc && !a.tr_digest && !a.tr_fmean && !a.rec_x && !a.rec_anc && !a.ck_in &&
          !a.replay_pi && a.n0 == 0 && a.n1 == a.T;
 }
 
@@ -1241,8 +1317,19 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
   // level-1 record wait reads at most four blocks per lane), and the
   // resampled states resident in LDS
   if (fwd_pipe_candidate(a, TP)) {
-    const void* pk = fwd_is_plain(a) ? reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false>)
-                                     : reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, true>);
+    const bool plain = fwd_is_plain(a);
+    const void* pk = plain ? reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false>)
+                           : reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, true>);
+    // binary32 1-D islands that fill 64- or 32-lane teams: the kernel
+    // compiled for that width (same results)
+    if constexpr (std::is_same<Store, float>::value && PPT == 4 && Model::DX == 1) {
+      if (a.N == 64 * PPT)
+        pk = plain ? reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false, 64>)
+                   : reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, true, 64>);
+      else if (a.N == 32 * PPT)
+        pk = plain ? reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false, 32>)
+                   : reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, true, 32>);
+    }
     const int G = fit_blocks(pk, kPipeBlock, L, a.m, tpb, L.max_blocks < 256 ? L.max_blocks : 256, smem_of, &smem);
     if (G >= 1 && a.m / G <= kMaxIslandsPerBlock && fwd_res_bytes(sizeof(Store), Model::DX, a.m / G, a.N) > 0) {
       set_plan(G, smem);
@@ -1308,7 +1395,8 @@ static hipError_t batch_fwd_ppt(const BatchLaunch& L, int* cap) {
 // compiled in a translation unit of their own)
 template <class Model>
 hipError_t fwd_launch_model(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan) {
-  return L.fp64 ? dispatch_ppt<Model, double>(L, a, plan) : dispatch_ppt<Model, float>(L, a, plan);
+  if constexpr (Model::kWordNoise) return dispatch_ppt<Model, double>(L, a, plan);   // 0/1 states, kept in double
+  else return L.fp64 ? dispatch_ppt<Model, double>(L, a, plan) : dispatch_ppt<Model, float>(L, a, plan);
 }
 template <class Model>
 hipError_t fwd_batch_model(const BatchLaunch& L, int* cap) {
@@ -1318,6 +1406,7 @@ hipError_t fwd_batch_model(const BatchLaunch& L, int* cap) {
 hipError_t fwd_launch_lg1(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
 hipError_t fwd_batch_lg1(const BatchLaunch& L, int* cap);
 hipError_t fwd_launch_sv(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
+hipError_t fwd_launch_bin(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
 hipError_t fwd_batch_sv(const BatchLaunch& L, int* cap);
 hipError_t fwd_launch_lgd2(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
 hipError_t fwd_batch_lgd2(const BatchLaunch& L, int* cap);

@@ -31,6 +31,8 @@ struct FwdArgs {
   unsigned* bar;              // [G] grid-barrier flags, zero before the launch
   int* status;                // [1] 0 ok, 1 barrier timed out
   double* ring;               // pipelined kernel: [kRingCopies][3 slots][E, a, b][G] level-1 ENF records, NaN before the launch
+  int check_y;                // 1: the observations came from the caller's device memory unchecked
+  int* bad_y;                 // [1] set to 1 when such an observation is NaN or infinite
   double* out_logz;           // [1]
   int32_t* tr_sstar;
   double* tr_enf;
@@ -38,6 +40,7 @@ struct FwdArgs {
   int32_t* tr_anc;
   int32_t* tr_pi;
   unsigned long long* tr_digest;
+  double* tr_fmean;           // [T*m] island weighted means of x[0] after each weighting
   // ---- what the score needs (all optional) ----
   int64_t n0, n1;             // steps [n0, n1) of this launch (0, T for a plain run)
   int replay_pi;              // 1: island maps from tr_pi, no cascade, no island weights

@@ -1,4 +1,6 @@
-"""Effective number of filters along a run: independent island filters
+"""Studies of the filter on the GPU.
+
+Effective number of filters along a run: independent island filters
 (IBPF) against AIRPF, the comparison of the paper's Section 4.2.
 
 The ENF of the m island weights, (sum W)^2 / (m sum W^2) in the normalised
@@ -52,4 +54,48 @@ def ibpf_vs_airpf(ctx, kind, theta, y, m, N, seed, tau=0.3, **kw):
                             else float("nan"),
                             mean_stages=float(np.mean(r["sstar"])))
         out[name] = r
+    return out
+
+
+def filter_means(lpost, fmean, T, m):
+    """The filter's estimate of E[x_n | y_0..y_n] per step from the traced
+    island log-weights after each weighting and the islands' weighted means
+    (the filtering measure of Algorithm 1 is the island-weighted mixture of
+    the islands' weighted particle sets)."""
+    L = np.asarray(lpost, dtype=np.float64).reshape(T, m)
+    F = np.asarray(fmean, dtype=np.float64).reshape(T, m)
+    w = np.exp(L - L.max(axis=1, keepdims=True))
+    w = np.where(np.isfinite(F), w, 0.0)
+    return (w * np.where(np.isfinite(F), F, 0.0)).sum(axis=1) / w.sum(axis=1)
+
+
+def error_vs_islands(ctx, theta, y, total, ms, seeds, tau=0.3, exact_means=None):
+    """Filtering error against the number of islands at a fixed total number
+    of particles (Theorem 2 of Section 3.2: for AIRPF whose ENF stays above
+    tau, the L_r error of the filtering estimates is at most
+    C sqrt(log2(m) / (m M tau))).  The 1-D linear-Gaussian model, whose
+    exact filtering means (``exact_means``, e.g. the Kalman filter's) are
+    the reference.  For each m in ``ms`` (N = total / m particles per
+    island) and each seed: one traced GPU run; the error is the root mean
+    square over steps and seeds of the filter's estimate of E[x_n | y_0..n]
+    minus the exact mean.  Returns dict(m=[...], N=[...], rmse=[...],
+    rate=[...]) with rate = sqrt(log2(m) / (m N tau)) (log2 m taken as at
+    least 1; NaN for tau = 0, independent filters, which the theorem does
+    not cover)."""
+    y = np.asarray(y, dtype=np.float64)
+    T = y.size
+    out = dict(m=[], N=[], rmse=[], rate=[])
+    for m in ms:
+        N = total // m
+        sq = []
+        for seed in seeds:
+            tr = airpf.Trace(T, m, N, sstar=False, enf=False, lpost=True, anc=False, pi=False, digest=False,
+                             fmean=True)
+            ctx.run(airpf.LG1, theta, y, m, N, seed, tau=tau, trace=tr)
+            est = filter_means(tr.lpost, tr.fmean, T, m)
+            sq.append(np.mean((est - exact_means) ** 2))
+        out["m"].append(m)
+        out["N"].append(N)
+        out["rmse"].append(float(np.sqrt(np.mean(sq))))
+        out["rate"].append(float(np.sqrt(max(1.0, np.log2(m)) / (m * N * tau))) if tau > 0 else float("nan"))
     return out

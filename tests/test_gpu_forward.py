@@ -52,10 +52,10 @@ def run_both(ctx, orc, model, m, N, T, tau, f64, seed=1, dx=None):
     from paper_2312_06484_amd import airpf
     g, P = make_case(orc, model, m, N, T, seed, dx)
     print("case", model, dx, m, N, T, tau, "f64" if f64 else "f32", flush=True)
-    gt = airpf.Trace(T, m, N)
+    gt = airpf.Trace(T, m, N, fmean=True)
     st, lz = ctx.run(g["kind"], g["theta"], g["y"], m, N, seed, tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"],
                      consts=g["consts"], trace=gt)
-    ot = orc.Trace(P)
+    ot = orc.Trace(P, fmean=True)
     lo = orc.run(P, tau=tau, f32=not f64, trace=ot)
     return lz, gt, lo, ot, P
 
@@ -73,6 +73,9 @@ def assert_parity(lz, gt, lo, ot, P):
     ge = gt.enf.reshape(T, S + 1)[: T - 1, 1:]
     oe = ot.enf.reshape(T, S + 1)[: T - 1, 1:]
     np.testing.assert_allclose(ge, oe, rtol=1e-12, atol=0)
+    if gt.fmean is not None and ot.fmean is not None:
+        # island weighted means: the same terms summed in another order
+        np.testing.assert_allclose(gt.fmean, ot.fmean, rtol=1e-12, atol=1e-12)
 
 
 CASES = [
@@ -219,6 +222,66 @@ def test_invalid_arguments(ctx):
     # a valid call still works after the failures
     st, v = ctx.run(0, th, y, 4, 4, 1)
     assert st == airpf.OK and np.isfinite(v)
+
+
+@pytest.mark.parametrize("where", [0, 7, 29])
+def test_device_observations_are_checked(ctx, where):
+    """A NaN or infinite observation in device memory, which the host cannot
+    look at, is caught by the kernels: INVALID_ARG with NaN outputs from
+    airpf_run (pipelined, serial and no-allocation paths), airpf_score and per
+    item in a batch; the other items and the next calls are unaffected."""
+    import torch
+    from paper_2312_06484_amd import airpf
+    T = 30
+    y = W.lg1_data(T)
+    for badv in (np.nan, np.inf):
+        yb = y.copy()
+        yb[where] = badv
+        yd = torch.tensor(yb, dtype=torch.float64, device="cuda")
+        good = torch.tensor(y, dtype=torch.float64, device="cuda")
+        for tau in (0.3, 2.0, 0.0):
+            st, v = ctx.run(0, W.LG1_THETA, None, 256, 64, 1, tau=tau, y_device_ptr=yd.data_ptr(), T=T,
+                            raise_on_error=False)
+            assert st == airpf.E_INVALID_ARG and math.isnan(v), (tau, st, v)
+        st, v = ctx.run_noalloc(0, W.LG1_THETA, None, 64, 32, 1, y_device_ptr=yd.data_ptr(), T=T,
+                                raise_on_error=False)
+        assert st == airpf.E_INVALID_ARG and math.isnan(v)
+        st, v, g = ctx.score(0, W.LG1_THETA, None, 16, 32, 1, y_device_ptr=yd.data_ptr(), T=T,
+                             raise_on_error=False)
+        assert st == airpf.E_INVALID_ARG and math.isnan(v) and np.isnan(g).all()
+        probs = [dict(theta=W.LG1_THETA, y=good.data_ptr(), T=T, m=16, N=32, seed=1),
+                 dict(theta=W.LG1_THETA, y=yd.data_ptr(), T=T, m=16, N=32, seed=2)]
+        for want in (False, True):
+            st, lz, gr, ist = ctx.run_batch(0, probs, want_score=want, y_on_device=True)
+            assert st == airpf.OK and ist[0] == airpf.OK and ist[1] == airpf.E_INVALID_ARG
+            assert np.isfinite(lz[0]) and np.isnan(lz[1])
+            _, ref = ctx.run(0, W.LG1_THETA, y, 16, 32, 1)
+            assert lz[0] == ref
+        torch.cuda.synchronize()
+    st, v = ctx.run(0, W.LG1_THETA, y, 4, 4, 1)
+    assert st == airpf.OK and np.isfinite(v)
+
+
+def test_workspace_cap_reports_nomem(ctx, monkeypatch):
+    """AIRPF_WORKSPACE_CAP makes a buffer that would have to grow past it fail
+    as an allocation failure does: AIRPF_E_NOMEM, NaN outputs, and the
+    context usable again once the cap is lifted."""
+    from paper_2312_06484_amd import airpf
+    y = W.lg1_data(20)
+    fresh = airpf.Context(0)
+    try:
+        monkeypatch.setenv("AIRPF_WORKSPACE_CAP", str(1 << 20))
+        st, v = fresh.run(0, W.LG1_THETA, y, 4096, 256, 1, raise_on_error=False)     # 4 MiB of states
+        assert st == airpf.E_NOMEM and math.isnan(v)
+        st, v, g = fresh.score(0, W.LG1_THETA, y, 1024, 256, 1, raise_on_error=False)
+        assert st == airpf.E_NOMEM and math.isnan(v) and np.isnan(g).all()
+        st, v = fresh.run(0, W.LG1_THETA, y, 16, 32, 1, raise_on_error=False)         # fits
+        assert st == airpf.OK
+        monkeypatch.delenv("AIRPF_WORKSPACE_CAP")
+        st, v = fresh.run(0, W.LG1_THETA, y, 4096, 256, 1)
+        assert st == airpf.OK and np.isfinite(v)
+    finally:
+        fresh.close()
 
 
 @pytest.mark.parametrize("tau", [0.5, 0.25, 0.125])
