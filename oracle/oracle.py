@@ -7,7 +7,9 @@ the HIP library.
 Model kinds and parameters (Section 1.2's HMM; concrete models as stated in
 orc_models.c):
     LG1 theta = (a, sx, sy);  SV theta = (mu, phi, sigma);
-    LGD theta = vec(A), consts = (q, r, p0, H.ravel());  BIN (toy HMM).
+    LGD theta = vec(A), consts = (q, r, p0, H.ravel());  BIN (toy HMM);
+    BCP theta = (p,), consts = (alpha, beta) integers, alpha + beta <= 7,
+    dx = dy = 2, y rows (k_n, n_n).
 Argument ``N`` is the number of particles PER ISLAND (the paper's M).
 """
 import ctypes as C
@@ -18,8 +20,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "liborc.so")
 
-LG1, SV, LGD, BIN = 0, 1, 2, 3
-TAG_NORMAL, TAG_SYS, TAG_MULT, TAG_ISL, TAG_BIN = 1, 2, 3, 4, 5
+LG1, SV, LGD, BIN, BCP = 0, 1, 2, 3, 4
+TAG_NORMAL, TAG_SYS, TAG_MULT, TAG_ISL, TAG_BIN, TAG_BCP = 1, 2, 3, 4, 5, 6
 
 _dp = C.POINTER(C.c_double)
 _i32p = C.POINTER(C.c_int32)

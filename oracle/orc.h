@@ -17,8 +17,8 @@
 #define ORC_H
 #include <stdint.h>
 
-enum { ORC_LG1 = 0, ORC_SV = 1, ORC_LGD = 2, ORC_BIN = 3 };
-enum { TAG_NORMAL = 1, TAG_SYS = 2, TAG_MULT = 3, TAG_ISL = 4, TAG_BIN = 5 };
+enum { ORC_LG1 = 0, ORC_SV = 1, ORC_LGD = 2, ORC_BIN = 3, ORC_BCP = 4 };
+enum { TAG_NORMAL = 1, TAG_SYS = 2, TAG_MULT = 3, TAG_ISL = 4, TAG_BIN = 5, TAG_BCP = 6 };
 #define ORC_MAX_DX 8
 #define ORC_MAX_DY 8
 #define ORC_MAX_P 64

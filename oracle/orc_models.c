@@ -30,6 +30,22 @@
  *        x in {0,1}, x_0 = w >> 31, flip iff (w >> 30) == 0 (prob 1/4),
  *        g = 3/4 if y == x else 1/4, written as log g = l + log(3/4) with
  *        l = 0 (match) or l = -log 3.
+ *   BCP  the Beta change-point model of the change-point experiment (Section
+ *        4.2): a rate x in (0,1), x_0 ~ Beta(alpha, beta), x' = x with
+ *        probability 1 - p, else a fresh Beta(alpha, beta) draw; theta = (p),
+ *        consts = (alpha, beta), positive integers with alpha + beta <= 7;
+ *        y_n = (k_n, n_n) counts, g = x^k (1-x)^(n-k) (the binomial
+ *        likelihood without its data-only coefficient).  The state is
+ *        (log x, log(1-x)).  A particle's step uses the eight words of two
+ *        Philox blocks (counters 2j and 2j+1, tag 6): word 0 decides the
+ *        change (u0 = w0 2^-32 < p), words 1..alpha+beta give the uniforms
+ *        u_i = (w_i + 1/2) 2^-32 of the draw
+ *          ga = 0, ga -= log(u_i) for i = 1..alpha;
+ *          gb = 0, gb -= log(u_i) for i = alpha+1..alpha+beta;
+ *          ls = log(ga + gb);  x = (log(ga) - ls, log(gb) - ls)
+ *        (a sum of k unit exponentials is Gamma(k, 1), and Ga / (Ga + Gb) is
+ *        Beta(alpha, beta)); log is the oracle's own orc_log.
+ *        lw = y_0 * x_0 + (y_1 - y_0) * x_1, no constant.
  * The per-particle part (without c) is what gets quantised; c is added once
  * per island and step.  Constants c, s0, sqrt(q), sqrt(p0), 1/(2r) and log 3
  * come from the host libm.
@@ -41,7 +57,7 @@
 
 void orc_model_setup(orc_model* M, const orc_problem* P, int f32) {
   M->kind = P->kind; M->dx = P->dx; M->dy = P->dy; M->P = P->d_theta;
-  M->f32 = f32;
+  M->f32 = (P->kind == ORC_BIN || P->kind == ORC_BCP) ? 0 : f32;   /* word-driven models: double only */
   for (int i = 0; i < P->d_theta && i < ORC_MAX_P; ++i) {
     M->th[i] = P->theta[i];
     M->thf[i] = (float)P->theta[i];
@@ -73,11 +89,28 @@ void orc_model_setup(orc_model* M, const orc_problem* P, int f32) {
       M->c_log = log(0.75);
       M->log3 = log(3.0);
       break;
+    case ORC_BCP:
+      M->c_log = 0.0;
+      M->ab[0] = (int)P->consts[0];
+      M->ab[1] = (int)P->consts[1];
+      break;
   }
 }
 
+/* a Beta(alpha, beta) draw from words w[1..alpha+beta] as (log x, log(1-x)) */
+static void bcp_beta(const orc_model* M, const double* w, double* x) {
+  double ga = 0.0, gb = 0.0;
+  for (int i = 1; i <= M->ab[0]; ++i) ga -= orc_log((w[i] + 0.5) * 0x1p-32);
+  for (int i = M->ab[0] + 1; i <= M->ab[0] + M->ab[1]; ++i) gb -= orc_log((w[i] + 0.5) * 0x1p-32);
+  const double ls = orc_log(ga + gb);
+  x[0] = orc_log(ga) - ls;
+  x[1] = orc_log(gb) - ls;
+}
+
 /* number of N(0,1) (or BIN words) one particle consumes per step */
-int orc_model_noise_dim(const orc_model* M) { return M->kind == ORC_BIN ? 1 : M->dx; }
+int orc_model_noise_dim(const orc_model* M) {
+  return M->kind == ORC_BIN ? 1 : (M->kind == ORC_BCP ? 8 : M->dx);
+}
 
 /* noise for particles 0..N-1 of (step n, island k): z[j*dim + d] */
 void orc_model_noise(const orc_model* M, uint64_t seed, int64_t n, int32_t k,
@@ -88,6 +121,14 @@ void orc_model_noise(const orc_model* M, uint64_t seed, int64_t n, int32_t k,
       orc_draw(seed, (uint32_t)j, (uint32_t)k, (uint32_t)n, TAG_BIN, 0, w);
       z[j] = (double)w[0];
     }
+  } else if (M->kind == ORC_BCP) {
+    for (int32_t j = 0; j < N; ++j) {
+      uint32_t w[4];
+      for (int b = 0; b < 2; ++b) {
+        orc_draw(seed, (uint32_t)(2 * j + b), (uint32_t)k, (uint32_t)n, TAG_BCP, 0, w);
+        for (int i = 0; i < 4; ++i) z[8 * j + 4 * b + i] = (double)w[i];
+      }
+    }
   } else if (M->f32) {
     orc_island_normalsf(seed, n, k, (int64_t)N * M->dx, z);
   } else {
@@ -96,7 +137,7 @@ void orc_model_noise(const orc_model* M, uint64_t seed, int64_t n, int32_t k,
 }
 
 void orc_model_init(const orc_model* M, const double* z, double* x) {
-  if (M->f32 && M->kind != ORC_BIN) {
+  if (M->f32 && M->kind != ORC_BIN && M->kind != ORC_BCP) {
     switch (M->kind) {
       case ORC_LG1: x[0] = (double)(float)z[0]; break;
       case ORC_SV: x[0] = (double)fmaf(M->s0f, (float)z[0], M->thf[0]); break;
@@ -113,11 +154,12 @@ void orc_model_init(const orc_model* M, const double* z, double* x) {
       for (int d = 0; d < M->dx; ++d) x[d] = M->sp0 * z[d];
       break;
     case ORC_BIN: x[0] = (double)(((uint32_t)z[0]) >> 31); break;
+    case ORC_BCP: bcp_beta(M, z, x); break;
   }
 }
 
 void orc_model_prop(const orc_model* M, const double* xp, const double* z, double* x) {
-  if (M->f32 && M->kind != ORC_BIN) {
+  if (M->f32 && M->kind != ORC_BIN && M->kind != ORC_BCP) {
     switch (M->kind) {
       case ORC_LG1:
         x[0] = (double)fmaf(M->thf[0], (float)xp[0], M->thf[1] * (float)z[0]);
@@ -160,12 +202,20 @@ void orc_model_prop(const orc_model* M, const double* xp, const double* z, doubl
       x[0] = ((w >> 30) == 0) ? 1.0 - xp[0] : xp[0];
       break;
     }
+    case ORC_BCP:
+      if (z[0] * 0x1p-32 < M->th[0]) {
+        bcp_beta(M, z, x);
+      } else {
+        x[0] = xp[0];
+        x[1] = xp[1];
+      }
+      break;
   }
 }
 
 /* per-particle part of log g_n(x) (the model constant c is not included) */
 double orc_model_logpot(const orc_model* M, const double* x, const double* y) {
-  if (M->f32 && M->kind != ORC_BIN) {
+  if (M->f32 && M->kind != ORC_BIN && M->kind != ORC_BCP) {
     switch (M->kind) {
       case ORC_LG1: {
         const float r = ((float)y[0] - (float)x[0]) * M->isyf;
@@ -209,6 +259,7 @@ double orc_model_logpot(const orc_model* M, const double* x, const double* y) {
       return -(ss * M->hr);
     }
     case ORC_BIN: return (x[0] == y[0]) ? 0.0 : -M->log3;
+    case ORC_BCP: return y[0] * x[0] + (y[1] - y[0]) * x[1];
   }
   return NAN;
 }

@@ -15,6 +15,7 @@ typedef struct {
   double q, r, p0, sq, sp0, hr; /* LGD noise scales                        */
   double H[ORC_MAX_DX * ORC_MAX_DY];
   double log3;                  /* BIN                                     */
+  int ab[2];                    /* BCP: integer Beta shapes (alpha, beta)  */
 } orc_model;
 
 void orc_model_setup(orc_model* M, const orc_problem* P, int f32);

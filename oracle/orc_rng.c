@@ -18,6 +18,9 @@
  *   SYS    : c0 = 0: the systematic offset of island k at step n.
  *   MULT   : c0 = j: the j-th multinomial draw of island k at step n.
  *   ISL    : c0 = s: the pair-selection uniform of island k, stage s, step n.
+ *   BIN    : c0 = j: word 0 drives particle j of the binary model.
+ *   BCP    : c0 = 2j + b (b = 0, 1): the eight words of particle j of the
+ *            Beta change-point model.
  *   BIN    : c0 = j: the binary toy model's per-particle word.
  *   sub    : 0, 1, ... extra blocks for rejection retries.
  */

@@ -33,6 +33,7 @@ static void case_run(int kind, int dx, int dy, int m, int N, int T, double tau, 
   if (kind == ORC_LG1) { theta[0] = 0.9; theta[1] = 1.0; theta[2] = 1.0; }
   else if (kind == ORC_SV) { theta[0] = -1.0; theta[1] = 0.95; theta[2] = 0.3; }
   else if (kind == ORC_BIN) { theta[0] = 0.0; dth = 1; }
+  else if (kind == ORC_BCP) { theta[0] = 0.1; dth = 1; consts[0] = 2.0; consts[1] = 5.0; }
   else {
     dth = dx * dx;
     for (int i = 0; i < dth; ++i) theta[i] = (i % (dx + 1) == 0) ? 0.5 : 0.05;
@@ -41,6 +42,8 @@ static void case_run(int kind, int dx, int dy, int m, int N, int T, double tau, 
   }
   double* y = malloc(sizeof(double) * (size_t)T * dy);
   for (int i = 0; i < T * dy; ++i) y[i] = kind == ORC_BIN ? (double)(i % 2) : sin(0.7 * i);
+  if (kind == ORC_BCP)
+    for (int i = 0; i < T; ++i) { y[2 * i] = (double)(i % 7); y[2 * i + 1] = 20.0; }
   orc_problem P = {kind, dx, dy, dth, theta, consts, y, T, m, N, 12345};
   orc_opts O = {tau, scheme, f32, 0, 0};
   const int S = (int)round(log2((double)m));
@@ -57,7 +60,7 @@ static void case_run(int kind, int dx, int dy, int m, int N, int T, double tau, 
   tr.fmean = calloc((size_t)T * m, sizeof(double));
   const double lz = orc_airpf_run(&P, &O, &tr);
   check(lz == lz, "run returned NaN");
-  if (kind != ORC_BIN) {
+  if (kind != ORC_BIN && kind != ORC_BCP) {
     double gpw[64], gps[64];
     const double lz2 = orc_airpf_score(&P, &O, NULL, gpw, gps);
     check(lz2 == lz, "score's log Zhat differs from the run's");
@@ -100,6 +103,8 @@ int main(void) {
   case_run(ORC_LGD, 8, 8, 2, 3, 2, 2.0, 1, 0);
   case_run(ORC_BIN, 1, 1, 4, 2, 5, 2.0, 1, 0);        /* the exact-variance toy */
   case_run(ORC_BIN, 1, 1, 1, 8, 5, 0.3, 0, 0);
+  case_run(ORC_BCP, 2, 2, 8, 16, 12, 0.5, 0, 0);      /* Beta change points */
+  case_run(ORC_BCP, 2, 2, 4, 5, 9, 2.0, 1, 0);
   if (fails) return 1;
   printf("sanitised oracle run: ok\n");
   return 0;

@@ -10,6 +10,11 @@ Models (the HMM of Section 1.2 with concrete kernels):
     SV   x_0 ~ N(mu, sigma^2/(1-phi^2)), x_t = mu + phi(x_{t-1}-mu) + sigma e_t,
          y_t = exp(x_t/2) v_t
     LGD  x_0 ~ N(0, p0 I), x_t = A x_{t-1} + sqrt(q) e_t, y_t = H x_t + sqrt(r) v_t
+    BCP  a rate x_0 ~ Beta(alpha, beta); x_t = x_{t-1} with probability 1 - p,
+         else a fresh Beta(alpha, beta) draw; y_t = (k_t, n_t), n_t daily
+         totals, k_t ~ Binomial(n_t, x_t) (the change-point experiment's
+         shape: counts of articles with a keyword among the day's articles;
+         its news data are not available, these stand in for them)
 """
 import numpy as np
 
@@ -94,6 +99,24 @@ def batch_c4(n_chains=64):
         items.append(dict(theta=thetas[c], T=Ts[c % 3], N=Ns[(c // 3) % 4],
                           m=ms[(c // 12) % 2], seed=c + 1))
     return items
+
+
+BCP_AB = (2, 5)          # Beta shapes of the rate chain (integers, alpha + beta <= 7)
+BCP_P = 0.01             # change probability per step
+
+
+def bcp_data(T, p=BCP_P, ab=BCP_AB, mean_total=300, seed=DATA_SEED):
+    """(T, 2) array of (k_t, n_t): n_t ~ 1 + Poisson(mean_total - 1), k_t ~
+    Binomial(n_t, x_t) along a simulated rate chain."""
+    g = np.random.default_rng(seed)
+    x = g.beta(*ab)
+    y = np.empty((T, 2))
+    for t in range(T):
+        if t > 0 and g.random() < p:
+            x = g.beta(*ab)
+        n = 1 + g.poisson(mean_total - 1)
+        y[t] = (g.binomial(n, x), n)
+    return y
 
 
 # Named workloads (sizes as the configurations state them; N is per island)
