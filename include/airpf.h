@@ -79,13 +79,22 @@ typedef enum {
  *             may be NULL), d_x = d_y = 1.  Forward only (airpf_run,
  *             airpf_run_noalloc); its states are 0/1 and always kept in
  *             double (the precision option has no effect).  airpf_score and
- *             airpf_run_batch return AIRPF_E_UNSUPPORTED. */
-typedef enum { AIRPF_LG1 = 0, AIRPF_SV = 1, AIRPF_LGD = 2, AIRPF_BIN = 3 } airpf_model_kind;
+ *             airpf_run_batch return AIRPF_E_UNSUPPORTED.
+ *  AIRPF_BCP  the Beta change-point model of the change-point experiment
+ *             (Section 4.2): a rate r_0 ~ Beta(alpha, beta); r' = r with
+ *             probability 1 - p, else a fresh Beta(alpha, beta) draw;
+ *             y_n = (k_n, n_n) counts (row-major, d_y = 2) with
+ *             g = r^k (1 - r)^(n - k) (no binomial coefficient: a constant of
+ *             the data).  theta = (p), 0 <= p <= 1 (else AIRPF_E_DOMAIN);
+ *             consts = (alpha, beta), integers >= 1 with alpha + beta <= 7;
+ *             d_x = 2 (the state is (log r, log(1 - r))).  Forward only, as
+ *             AIRPF_BIN (states in double; score and batch UNSUPPORTED). */
+typedef enum { AIRPF_LG1 = 0, AIRPF_SV = 1, AIRPF_LGD = 2, AIRPF_BIN = 3, AIRPF_BCP = 4 } airpf_model_kind;
 
 typedef struct {
   int32_t kind;          /* airpf_model_kind */
   int32_t dx, dy;        /* state and observation dimensions */
-  const double* consts;  /* model constants (AIRPF_LGD), host memory */
+  const double* consts;  /* model constants (AIRPF_LGD, AIRPF_BCP), host memory */
   int32_t n_consts;
 } airpf_model;
 

@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libairpf.so")
 
-LG1, SV, LGD, BIN = 0, 1, 2, 3
+LG1, SV, LGD, BIN, BCP = 0, 1, 2, 3, 4
 SYSTEMATIC, MULTINOMIAL = 0, 1
 FP32, FP64 = 0, 1
 PATHSPACE, PATHWISE = 0, 1
@@ -280,7 +280,7 @@ class Context:
                 keep.append(yy)
                 arr[i].y, arr[i].T = yy.ctypes.data_as(C.c_void_p), yy.size // int(dy)
             arr[i].m, arr[i].N, arr[i].seed = int(pr["m"]), int(pr["N"]), int(pr["seed"])
-        P = int(dx) * int(dx) if kind == LGD else (0 if kind == BIN else 3)
+        P = int(dx) * int(dx) if kind == LGD else {BIN: 0, BCP: 1}.get(kind, 3)
         lz = np.full(max(B, 1), np.nan)
         gr = np.full((max(B, 1), P), np.nan) if want_score else None
         ist = (C.c_int * max(B, 1))()

@@ -206,6 +206,19 @@ airpf_status prepare_model(const airpf_model* model, const double* theta, int32_
       c_log = std::log(0.75);
       break;
     }
+    case AIRPF_BCP: {
+      if (d_theta != 1 || model->dx != 2 || model->dy != 2 || !model->consts || model->n_consts != 2)
+        return AIRPF_E_INVALID_ARG;
+      const double al = model->consts[0], be = model->consts[1];
+      if (!all_finite(theta, 1) || !all_finite(model->consts, 2)) return AIRPF_E_INVALID_ARG;
+      if (!(al >= 1.0 && be >= 1.0 && al == std::floor(al) && be == std::floor(be) && al + be <= 7.0))
+        return AIRPF_E_INVALID_ARG;
+      if (!(theta[0] >= 0.0 && theta[0] <= 1.0)) return AIRPF_E_DOMAIN;
+      mp->ab[0] = static_cast<int>(al);
+      mp->ab[1] = static_cast<int>(be);
+      dx = dy = 2;
+      break;
+    }
     default:
       return AIRPF_E_INVALID_ARG;
   }
@@ -266,7 +279,8 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   if (T < 1 || T > (int64_t(1) << 30) || !is_pow2(m) || N < 1 || N > 2048) return AIRPF_E_INVALID_ARG;
   if (m > kMaxIslands) return AIRPF_E_UNSUPPORTED;
   P->opt = opt_in ? *opt_in : default_options();
-  if (model->kind == AIRPF_BIN && P->opt.precision == AIRPF_FP32) P->opt.precision = AIRPF_FP64;   // 0/1 states
+  if ((model->kind == AIRPF_BIN || model->kind == AIRPF_BCP) && P->opt.precision == AIRPF_FP32)
+    P->opt.precision = AIRPF_FP64;                  // word-driven models keep their states in double
   const airpf_options& opt = P->opt;
   if (!(opt.tau == opt.tau)) return AIRPF_E_INVALID_ARG;
   if (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) return AIRPF_E_INVALID_ARG;
@@ -466,8 +480,8 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   }
   // the reverse pass finds a particle's children as a run of sorted ancestors
   if (opt.resampling == AIRPF_MULTINOMIAL) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
-  // the binary model has no parameters and no differentiable mutation
-  if (model && model->kind == AIRPF_BIN) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
+  // the word-driven models' mutations are not differentiable in theta
+  if (model && (model->kind == AIRPF_BIN || model->kind == AIRPF_BCP)) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
   if (model && ((model->kind == AIRPF_LGD && N > 512) || (model->kind != AIRPF_LGD && N > 1024))) {
     set_nan(log_z_out);
     return AIRPF_E_UNSUPPORTED;
@@ -744,7 +758,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
                                         int32_t want_score, double* log_z_out, double* grad_out,
                                         airpf_status* item_status) {
   if (!ctx || !model || B < 0 || (B > 0 && (!probs || !log_z_out || !item_status))) return AIRPF_E_INVALID_ARG;
-  if (model->kind == AIRPF_BIN) return AIRPF_E_UNSUPPORTED;        // single problems only
+  if (model->kind == AIRPF_BIN || model->kind == AIRPF_BCP) return AIRPF_E_UNSUPPORTED;   // single problems only
   const airpf_options opt = opt_in ? *opt_in : default_options();
   if (want_score && !grad_out) return AIRPF_E_INVALID_ARG;
   if (!(opt.tau == opt.tau) || (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) || opt.ckpt_every < 0)

@@ -21,7 +21,7 @@
 
 namespace airpf {
 
-enum : uint32_t { kTagNormal = 1, kTagSys = 2, kTagMult = 3, kTagIsl = 4, kTagBin = 5 };
+enum : uint32_t { kTagNormal = 1, kTagSys = 2, kTagMult = 3, kTagIsl = 4, kTagBin = 5, kTagBcp = 6 };
 
 struct Key { uint32_t k0, k1; };
 

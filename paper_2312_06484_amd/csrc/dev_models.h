@@ -15,6 +15,11 @@
 //   BIN  z is the particle's raw 32-bit word (not a normal variate):
 //        x_0 = bit 31 of z;  x' = 1 - x when bits 31..30 of z are zero,
 //        else x;  lw = 0 when x == y, else -log 3
+//   BCP  z is the particle's eight raw words; x = (log r, log(1 - r)) of a
+//        rate r:  x_0 = beta(z);  x' = beta(z) when z_0 2^-32 < p, else x;
+//        beta(z): ga = 0, ga -= log((z_i + 1/2) 2^-32) for i = 1..alpha;
+//        gb likewise over i = alpha+1..alpha+beta;  ls = log(ga + gb);
+//        x = (log ga - ls, log gb - ls);  lw = y_0 x_0 + (y_1 - y_0) x_1
 //
 // Derivatives for the score (plain double arithmetic, no bit-exactness
 // contract): d lw/dx, d log g/d theta (the constant of log g included),
@@ -41,6 +46,7 @@ struct ModelArgs {
   float Hf[kMaxDy * 8];
   float s0f, sqf, sp0f, hrf, isyf;
   double log3;                // BIN: log 3 from the host
+  int ab[2];                  // BCP: the integer Beta shapes (alpha, beta)
   int dy;
 };
 
@@ -143,6 +149,8 @@ struct SV {
 struct BIN {
   static constexpr int DX = 1;
   static constexpr bool kWordNoise = true;
+  static constexpr int kWords = 1;            // raw words per particle and step
+  static constexpr uint32_t kTag = kTagBin;
   static constexpr bool kThetaOuter = false;
   static constexpr int P = 0;
   template <typename R>
@@ -156,6 +164,50 @@ struct BIN {
   template <typename R>
   __device__ static R logpot(const ModelArgs& p, const R* x, const double* y) {
     return static_cast<double>(x[0]) == y[0] ? R(0) : static_cast<R>(-p.log3);
+  }
+};
+
+// The Beta change-point model of the change-point experiment (Section 4.2):
+// a rate r in (0, 1) that keeps its value from one step to the next with
+// probability 1 - p and is otherwise drawn afresh from Beta(alpha, beta)
+// (its initial law too), observed through counts y = (k, n) with g = r^k
+// (1 - r)^(n - k).  The state is (log r, log(1 - r)); a Beta draw is the
+// ratio of two sums of unit exponentials (integer shapes, alpha + beta <= 7),
+// each a -log of a uniform from one of the particle's eight raw words (two
+// Philox blocks, tag 6), word 0 deciding the change.  theta = (p); forward
+// only, states in double.
+struct BCP {
+  static constexpr int DX = 2;
+  static constexpr bool kWordNoise = true;
+  static constexpr int kWords = 8;
+  static constexpr uint32_t kTag = kTagBcp;
+  static constexpr bool kThetaOuter = false;
+  static constexpr int P = 1;
+  __device__ static void beta(const ModelArgs& p, const double* z, double* x) {
+    double ga = 0.0, gb = 0.0;
+    for (int i = 1; i <= p.ab[0]; ++i) ga -= dlog((z[i] + 0.5) * 0x1p-32);
+    for (int i = p.ab[0] + 1; i <= p.ab[0] + p.ab[1]; ++i) gb -= dlog((z[i] + 0.5) * 0x1p-32);
+    const double ls = dlog(ga + gb);
+    x[0] = dlog(ga) - ls;
+    x[1] = dlog(gb) - ls;
+  }
+  template <typename R>
+  __device__ static void init(const ModelArgs& p, const R* z, R* x) {
+    static_assert(std::is_same<R, double>::value, "raw words and log rates are kept in double");
+    beta(p, z, x);
+  }
+  template <typename R>
+  __device__ static void prop(const ModelArgs& p, const R* xp, const R* z, R* x) {
+    if (z[0] * 0x1p-32 < p.th[0]) {
+      beta(p, z, x);
+    } else {
+      x[0] = xp[0];
+      x[1] = xp[1];
+    }
+  }
+  template <typename R>
+  __device__ static R logpot(const ModelArgs&, const R* x, const double* y) {
+    return y[0] * x[0] + (y[1] - y[0]) * x[1];
   }
 };
 

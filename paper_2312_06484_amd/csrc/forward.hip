@@ -10,6 +10,7 @@ hipError_t launch_forward(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan) {
     case 0: return fwd_launch_lg1(L, a, plan);
     case 1: return fwd_launch_sv(L, a, plan);
     case 3: return fwd_launch_bin(L, a, plan);
+    case 4: return fwd_launch_bcp(L, a, plan);
     case 2:
       switch (L.dx) {
         case 2: return fwd_launch_lgd2(L, a, plan);

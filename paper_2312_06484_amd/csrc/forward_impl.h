@@ -50,20 +50,35 @@ namespace airpf {
 
 // ------------------------------------------------------------ the kernel
 
+// Noise values one particle consumes per step: its normals (one per state
+// coordinate), or the raw words of a word-driven model.
+template <class Model>
+__host__ __device__ constexpr int noise_per_particle() {
+  if constexpr (Model::kWordNoise) return Model::kWords; else return Model::DX;
+}
+
 // The mutation noise of one lane's particles j0 .. j0 + PPT - 1 at (step n,
 // island k): PPT * DX normal variates from the lane's blocks of four, or,
-// for a model driven by raw words (the binary model), the first word of
-// each particle's own Philox block (counter j, tag kTagBin), exact in double.
+// for a model driven by raw words, the first kWords words of particle j's
+// own Philox blocks (counters j * B .. j * B + B - 1, B = ceil(kWords / 4),
+// the model's tag), exact in double.
 template <class Model, typename Store, int PPT>
 __device__ __forceinline__ void draw_noise(const Key& key, int64_t n, int k, int j0, Store* z) {
   constexpr int NZ = PPT * Model::DX;
   if constexpr (Model::kWordNoise) {
     static_assert(std::is_same<Store, double>::value, "raw words are kept exactly in double");
+    constexpr int W = Model::kWords, B = (W + 3) / 4;
 #pragma unroll
     for (int r = 0; r < PPT; ++r) {
-      uint32_t w[4];
-      draw4(key, static_cast<uint32_t>(j0 + r), static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagBin, 0, w);
-      z[r] = static_cast<Store>(w[0]);
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        uint32_t w[4];
+        draw4(key, static_cast<uint32_t>((j0 + r) * B + b), static_cast<uint32_t>(k), static_cast<uint32_t>(n),
+              Model::kTag, 0, w);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (4 * b + i < W) z[r * W + 4 * b + i] = static_cast<Store>(w[i]);
+      }
     }
   } else {
     for (int g = 0; g < NZ / 4; ++g) {
@@ -86,6 +101,7 @@ template <class Model, typename Store, int PPT, bool Plain, bool Mult = false>
 __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;                 // normals per lane per step
+  constexpr int NW = noise_per_particle<Model>(), NZW = PPT * NW;   // noise values per particle, per lane
   static_assert(NZ % 4 == 0, "a lane consumes whole Philox blocks");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red_d[kWaves];
@@ -200,7 +216,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
     // the first pass's draws (its normals and the systematic offset's first
     // block) do not depend on the other blocks: they are taken between
     // publishing this block's flag and waiting for the others
-    Store z_first[NZ];
+    Store z_first[NZW];
     uint32_t wsys_first[4] = {0u, 0u, 0u, 0u};
     bool first_drawn = false;
     bool skip_passes = false;
@@ -349,10 +365,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           for (int d = 0; d < DX; ++d) x[r][d] = (j0 + r < N) ? xc[(j0 + r) * DX + d] : Store(0);
         if (lane == 0) Lpre = ck_L[(n / ck_every) * m + k];
       } else if (n == 0) {
-        Store z[NZ];
+        Store z[NZW];
         draw_normals(n, k, j0, z);
 #pragma unroll
-        for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * DX, x[r]);
+        for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * NW, x[r]);
       } else {
         const int src = spec ? k : s_src[active ? li : 0];
         if (lane == 0 && active) Lpre = spec ? lvp(ppar)[li] : s_lpre[li];
@@ -372,10 +388,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 #pragma unroll
             for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? get(xin + (j0 + r) * DX + d) : Store(0);
         }
-        Store z[NZ];
+        Store z[NZW];
         if (pre) {
 #pragma unroll
-          for (int i = 0; i < NZ; ++i) z[i] = z_first[i];
+          for (int i = 0; i < NZW; ++i) z[i] = z_first[i];
         } else {
           draw_normals(n, k, j0, z);
         }
@@ -384,7 +400,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           Store xp[DX];
 #pragma unroll
           for (int d = 0; d < DX; ++d) xp[d] = xr[r][d];
-          Model::template prop<Store>(a.mp, xp, z + r * DX, x[r]);
+          Model::template prop<Store>(a.mp, xp, z + r * NW, x[r]);
         }
       }
 
@@ -693,6 +709,7 @@ template <class Model, typename Store, int PPT, bool Rec, int TPC = 0>
 __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;
+  constexpr int NW = noise_per_particle<Model>(), NZW = PPT * NW;
   static_assert(NZ % 4 == 0, "a lane consumes whole Philox blocks");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red_d[kWaves];            // team helpers' scratch (unused for TP <= 64)
@@ -769,10 +786,10 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       Store x[PPT][DX];
       double Lpre = 0.0;
       if (n == 0) {
-        Store z[NZ];
+        Store z[NZW];
         draw_noise<Model, Store, PPT>(key, n, k, j0, z);
 #pragma unroll
-        for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * DX, x[r]);
+        for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * NW, x[r]);
       } else {
         const int src = spec ? k : s_src[active ? li : 0];
         if (lane == 0 && active) Lpre = spec ? lvp(ppar)[li] : s_lpre[li];
@@ -790,14 +807,14 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
 #pragma unroll
             for (int d = 0; d < DX; ++d) xr[r][d] = (j0 + r < N) ? get(xin + (j0 + r) * DX + d) : Store(0);
         }
-        Store z[NZ];
+        Store z[NZW];
         draw_noise<Model, Store, PPT>(key, n, k, j0, z);
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           Store xp[DX];
 #pragma unroll
           for (int d = 0; d < DX; ++d) xp[d] = xr[r][d];
-          Model::template prop<Store>(a.mp, xp, z + r * DX, x[r]);
+          Model::template prop<Store>(a.mp, xp, z + r * NW, x[r]);
         }
       }
 
@@ -1008,13 +1025,15 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   // records of its blocks (those wave_reduce_enf(G, ...) assigns it) are
   // complete, and they are joined as wave_reduce_enf joins them.  A record
   // is the block's arrival: no flag, and no wait for the record's own
-  // stores.  Once every block's record of step t is here, every block has
-  // read those of step t-1, so this block clears its slot of step t-1
-  // (reused at step t+2); that clearing completes before the block's next
-  // record is stored (the s_waitcnt below), so a block that sees that
-  // record sees the cleared slot.
+  // stores.  Slot t+1 mod 3 held the records of step t-2, which every block
+  // has read (each stored its record of t-1 after taking all of t-2), so it
+  // is cleared beside the record of step t, ahead of its reuse at step t+1;
+  // that clearing completes before the block's next record is stored (the
+  // s_waitcnt below), so a block that sees that record sees the cleared
+  // slot.  (Stored here, the clearing completes within the poll's first
+  // wait instead of holding up the decision after it.)
   auto level1 = [&](int64_t t, EnfRec& out) -> bool {
-    const int slot = static_cast<int>(t % 3), prev = static_cast<int>((t + 2) % 3);
+    const int slot = static_cast<int>(t % 3), next = static_cast<int>((t + 1) % 3);
     const EnfRec* lf = s_leaf[t & 1];
     const EnfRec own = wave_reduce_enf(c, [&](int i) { return lf[i]; });
     const EnfRec mine{readlane_f64(own.E, 0), readlane_f64(own.a, 0), readlane_f64(own.b, 0)};
@@ -1025,6 +1044,11 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       put(w + bid, mine.E);
       put(w + G + bid, mine.a);
       put(w + 2 * G + bid, mine.b);
+      double* rp = a.ring + lane64 * copy_stride + static_cast<int64_t>(next) * 3 * G;
+      const double nan = __longlong_as_double(static_cast<long long>(~0ull));
+      put(rp + bid, nan);
+      put(rp + G + bid, nan);
+      put(rp + 2 * G + bid, nan);
     }
     const double* rs = a.ring + (bid & (kRingCopies - 1)) * copy_stride + static_cast<int64_t>(slot) * 3 * G;
     const int per = G > 64 ? (G >> 6) : 1;                     // blocks per lane: 4, 2 or 1
@@ -1055,15 +1079,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       }
     }
     out = wave_join_flat(rec, per, G);
-    const bool done = __all(ok) != 0;
-    if (done && lane64 < kRingCopies) {
-      double* rp = a.ring + lane64 * copy_stride + static_cast<int64_t>(prev) * 3 * G;
-      const double nan = __longlong_as_double(static_cast<long long>(~0ull));
-      put(rp + bid, nan);
-      put(rp + G + bid, nan);
-      put(rp + 2 * G + bid, nan);
-    }
-    return done;
+    return __all(ok) != 0;
   };
   // the observations of chunk j (steps j * kYChunk onwards) into s_y[j & 1];
   // observations the host could not check are checked here
@@ -1395,7 +1411,7 @@ static hipError_t batch_fwd_ppt(const BatchLaunch& L, int* cap) {
 // compiled in a translation unit of their own)
 template <class Model>
 hipError_t fwd_launch_model(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan) {
-  if constexpr (Model::kWordNoise) return dispatch_ppt<Model, double>(L, a, plan);   // 0/1 states, kept in double
+  if constexpr (Model::kWordNoise) return dispatch_ppt<Model, double>(L, a, plan);   // word-driven models: double states
   else return L.fp64 ? dispatch_ppt<Model, double>(L, a, plan) : dispatch_ppt<Model, float>(L, a, plan);
 }
 template <class Model>
@@ -1407,6 +1423,7 @@ hipError_t fwd_launch_lg1(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
 hipError_t fwd_batch_lg1(const BatchLaunch& L, int* cap);
 hipError_t fwd_launch_sv(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
 hipError_t fwd_launch_bin(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
+hipError_t fwd_launch_bcp(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
 hipError_t fwd_batch_sv(const BatchLaunch& L, int* cap);
 hipError_t fwd_launch_lgd2(const FwdLaunch& L, const FwdArgs& a, FwdPlan* plan);
 hipError_t fwd_batch_lgd2(const BatchLaunch& L, int* cap);
