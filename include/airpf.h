@@ -226,7 +226,10 @@ typedef struct {
  * opt->flags the library times the tilings of several r on the first (up to)
  * 32 steps of every problem, keeps the fastest and caches it in the context
  * for batches of the same shape (model, precision, score, and every
- * problem's T, m, N), so only the first such call pays for the probes.
+ * problem's T, m, N), so only the first such call pays for the probes; with
+ * the environment variable AIRPF_TUNE_CACHE naming a file, measured ratios
+ * are also appended there and read back by later processes (one text line
+ * "<shape key, hex> <ratio>" per measurement).
  * Tiling never changes results. */
 airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model, int32_t B,
                              const airpf_problem* probs, const airpf_options* opt,

@@ -30,6 +30,11 @@ def flags():
             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
+def link_flags():
+    """Libraries of the link: the ROCm tracer's range markers (roctx)."""
+    return ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
+
+
 def build(verbose: bool = False, out: str = OUT) -> str:
     """Compile each source to an object (in parallel), then link."""
     import tempfile
@@ -40,7 +45,7 @@ def build(verbose: bool = False, out: str = OUT) -> str:
     with tempfile.TemporaryDirectory(prefix="airpf_build_") as d:
         objs = [os.path.join(d, os.path.basename(s) + ".o") for s in srcs]
         cmds = [[hipcc(), *compile_flags, "-c", "-o", o, s] for s, o in zip(srcs, objs)]
-        cmds.append([hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp, *objs])
+        cmds.append([hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp, *objs, *link_flags()])
         if verbose:
             for c in cmds:
                 print(" ".join(c), flush=True)

@@ -1,6 +1,7 @@
 // C ABI of the AIRPF library (declared in include/airpf.h): argument
 // validation, model constants, device workspaces and launches.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cmath>
 #include <cstdint>
@@ -238,6 +239,42 @@ airpf_status prepare_model(const airpf_model* model, const double* theta, int32_
   return AIRPF_OK;
 }
 
+// AIRPF_TUNE_CACHE=<file>: the tiler's measured cost ratios persist across
+// processes in that text file, one line "<batch-shape key, hex> <ratio>"
+// per shape; it is read when the context's own cache misses and appended
+// after a measurement (an unreadable or absent file is a miss).
+bool tune_cache_lookup(uint64_t key, double* ratio) {
+  const char* path = std::getenv("AIRPF_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  unsigned long long k = 0;
+  double r = 0.0;
+  bool found = false;
+  while (std::fscanf(f, "%llx %lf", &k, &r) == 2)
+    if (k == key && r > 0.0 && std::isfinite(r)) { *ratio = r; found = true; }   // the last line of a key wins
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_store(uint64_t key, double ratio) {
+  const char* path = std::getenv("AIRPF_TUNE_CACHE");
+  if (!path || !*path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%016llx %.17g\n", static_cast<unsigned long long>(key), ratio);
+    std::fclose(f);
+  }
+}
+
+// A tracer range (roctx) around one call of the ABI, shown by profilers that
+// trace markers (rocprofv3 --marker-trace); a no-op otherwise.
+struct Range {
+  explicit Range(const char* name) { roctxRangePush(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
 airpf_options default_options() {
   airpf_options o;
   o.tau = 0.3;
@@ -328,7 +365,7 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   // 9G doubles, G <= 256)
   const size_t ring_off = (64 + 4 * size_t(P->gmax) + 255) & ~size_t(255);
   const int gring = std::min(P->gmax, 256);
-  const size_t misc_bytes = ring_off + 8 * 9 * size_t(gring) * airpf::kRingCopies;
+  const size_t misc_bytes = ring_off + 8 * 3 * airpf::kRingSlots * size_t(gring) * airpf::kRingCopies;
   const size_t y_bytes = sizeof(double) * size_t(T) * P->dy;
   unsigned char* misc = nullptr;
   void* ybuf = nullptr;
@@ -373,7 +410,8 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
     a.y = static_cast<const double*>(ybuf);
   }
   HIP_OK(airpf::fill_u32(misc, 0u, 16 + int64_t(P->gmax), s));
-  HIP_OK(airpf::fill_u32(misc + ring_off, 0xFFFFFFFFu, 2 * 9 * int64_t(gring) * airpf::kRingCopies, s));   // NaN
+  HIP_OK(airpf::fill_u32(misc + ring_off, 0xFFFFFFFFu, 2 * 3 * airpf::kRingSlots * int64_t(gring) * airpf::kRingCopies,
+                         s));   // NaN
   return AIRPF_OK;
 }
 
@@ -440,6 +478,7 @@ airpf_status finish(airpf_ctx* ctx, const Prepared& P, double* log_z_out) {
 extern "C" airpf_status airpf_run(airpf_ctx* ctx, const airpf_model* model, const double* theta, int32_t d_theta,
                                   const double* y, int64_t T, int32_t m, int32_t N, uint64_t seed,
                                   const airpf_options* opt_in, double* log_z_out, airpf_trace* trace) {
+  const Range range("airpf_run");
   Prepared P;
   ST_OK(prepare(ctx, model, theta, d_theta, y, T, m, N, seed, opt_in, log_z_out, kMaxBlocks, &P));
   ST_OK(attach_trace(ctx, P, trace));
@@ -471,6 +510,7 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
                                     int32_t d_theta, const double* y, int64_t T, int32_t m, int32_t N,
                                     uint64_t seed, const airpf_options* opt_in, double* log_z_out,
                                     double* grad_out, airpf_trace* trace) {
+  const Range range("airpf_score");
   if (grad_out) for (int i = 0; i < d_theta; ++i) grad_out[i] = std::nan("");
   if (!grad_out) { set_nan(log_z_out); return AIRPF_E_INVALID_ARG; }
   const airpf_options opt = opt_in ? *opt_in : default_options();
@@ -757,6 +797,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
                                         const airpf_problem* probs, const airpf_options* opt_in,
                                         int32_t want_score, double* log_z_out, double* grad_out,
                                         airpf_status* item_status) {
+  const Range range("airpf_run_batch");
   if (!ctx || !model || B < 0 || (B > 0 && (!probs || !log_z_out || !item_status))) return AIRPF_E_INVALID_ARG;
   if (model->kind == AIRPF_BIN || model->kind == AIRPF_BCP) return AIRPF_E_UNSUPPORTED;   // single problems only
   const airpf_options opt = opt_in ? *opt_in : default_options();
@@ -1008,6 +1049,8 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
     mix(uint64_t(model->kind)); mix(uint64_t(dx)); mix(uint64_t(fp64)); mix(uint64_t(want_score));
     for (const Item& it : items) { mix(uint64_t(it.T)); mix(uint64_t(it.m)); mix(uint64_t(it.N)); }
     auto hit = ctx->tuned_ratio.find(key);
+    double filed = 0.0;
+    if (hit == ctx->tuned_ratio.end() && tune_cache_lookup(key, &filed)) hit = ctx->tuned_ratio.emplace(key, filed).first;
     if (hit != ctx->tuned_ratio.end()) {
       ratio = hit->second;
     } else {
@@ -1036,6 +1079,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
       }
       ratio = best;
       ctx->tuned_ratio[key] = ratio;
+      tune_cache_store(key, ratio);
     }
   }
   HIP_OK(hipEventRecord(ctx->ev[0], s));

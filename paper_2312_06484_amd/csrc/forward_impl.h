@@ -726,7 +726,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   // each island's level-1 ENF leaf (E, a, b) by step parity, formed by the
   // island's team right after its weighting (the control wave only joins
   // the block's leaves)
-  __shared__ EnfRec s_leaf[2][kMaxIslandsPerBlock];
+  __shared__ EnfRec s_leaf[3][kMaxIslandsPerBlock];
 
   const int tid = threadIdx.x;
   const bool ctl = tid >= kBlock;             // the control wave
@@ -747,11 +747,13 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
 
   Store* sx = reinterpret_cast<Store*>(smem);                                    // [kBlock*NZ]
   int* sA = reinterpret_cast<int*>(smem + ((sizeof(Store) * kBlock * NZ + 15) & ~size_t(15)));   // [kBlock*PPT]
-  double* lvb = reinterpret_cast<double*>(sA + kBlock * PPT);                      // [2][2c]
-  double* up = lvb + 4 * c;                                                       // [2G]
-  Store* res = reinterpret_cast<Store*>(up + 2 * G);                              // [2][c*N*DX]
+  double* lvb = reinterpret_cast<double*>(sA + kBlock * PPT);                      // [3][2c]
+  double* up = lvb + 6 * c;                                                       // [2G]
+  Store* res = reinterpret_cast<Store*>(up + 2 * G);                              // [3][c*N*DX]
   const int64_t res_words = static_cast<int64_t>(c) * N * DX;
-  auto lvp = [&](int par) { return lvb + 2 * c * par; };
+  // a step's island log-weights (and local tree) and resampled states live
+  // in slot step mod 3: the steps being decided, published and run
+  auto lvp = [&](int sl) { return lvb + 2 * c * sl; };
   auto wsync = [] {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -765,8 +767,10 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   // the block of step base + l; the words are the same either way
   const bool sys_batch = passes == 1 && TP >= 16;
   uint32_t sysw[4] = {0u, 0u, 0u, 0u};
+  int64_t sys_base = -1;                      // first step of the batch in sysw
   auto run_passes = [&](int64_t n, bool spec) {
-    const int par = static_cast<int>(n & 1), ppar = par ^ 1;
+    const int ppar = static_cast<int>((n & 1) ^ 1);                // HBM copies of step n-1, by parity
+    const int sl = static_cast<int>(n % 3), psl = static_cast<int>((n + 2) % 3);   // LDS slots of steps n, n-1
     for (int p = 0; p < passes; ++p) {
       const int li = p * tpb + team;
       const bool active = li < c;
@@ -774,9 +778,13 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       const int j0 = lane * PPT;
       uint32_t wsys[4] = {0u, 0u, 0u, 0u};
       if (sys_batch) {
+        // (a step run again may belong to the batch before the one drawn last)
         const int64_t base = n - n % TP;
-        if (n == base && base + lane < T - 1)
-          draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(base + lane), kTagSys, 0, sysw);
+        if (base != sys_base) {
+          if (base + lane < T - 1)
+            draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(base + lane), kTagSys, 0, sysw);
+          sys_base = base;
+        }
         const int src_lane = (tid & 63 & ~(TP - 1)) | static_cast<int>(n - base);
 #pragma unroll
         for (int i = 0; i < 4; ++i) wsys[i] = static_cast<uint32_t>(__shfl(static_cast<int>(sysw[i]), src_lane, 64));
@@ -792,10 +800,10 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
         for (int r = 0; r < PPT; ++r) Model::template init<Store>(a.mp, z + r * NW, x[r]);
       } else {
         const int src = spec ? k : s_src[active ? li : 0];
-        if (lane == 0 && active) Lpre = spec ? lvp(ppar)[li] : s_lpre[li];
+        if (lane == 0 && active) Lpre = spec ? lvp(psl)[li] : s_lpre[li];
         Store xr[PPT][DX];
         if (src >= kbase && src < kbase + c) {
-          const Store* xin = res + ppar * res_words + static_cast<int64_t>(src - kbase) * N * DX;
+          const Store* xin = res + psl * res_words + static_cast<int64_t>(src - kbase) * N * DX;
 #pragma unroll
           for (int r = 0; r < PPT; ++r)
 #pragma unroll
@@ -859,8 +867,8 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       const uint64_t Qk = TP == 64 ? readlane_u64(incl, 63) : __shfl(incl, (tid & 63) | (TP - 1), 64);
       if (lane == 0 && active) {
         const double L = (Qk == 0) ? ninf() : Lpre + ((static_cast<double>(mx) + dlog(static_cast<double>(Qk))) + a.cst_q);
-        lvp(par)[li] = L;
-        s_leaf[par][li] = enf_leaf(L);
+        lvp(sl)[li] = L;
+        s_leaf[sl][li] = enf_leaf(L);
       }
 
       // ---- internal resampling (systematic, by offspring counts) ----
@@ -916,7 +924,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
           for (int r = 0; r < NZ; ++r) {
             const int w = r * TP + lane;
             const int j = w / DX, d = w - j * DX;
-            if (j < N) res[par * res_words + static_cast<int64_t>(li) * N * DX + w] = sxt[sAt[j] * DX + d];
+            if (j < N) res[sl * res_words + static_cast<int64_t>(li) * N * DX + w] = sxt[sAt[j] * DX + d];
           }
         }
         team_sync(TP);
@@ -927,7 +935,8 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   // ================= control wave =================
   unsigned epoch = 0;
   int up_top = 0;
-  auto build_upper_to = [&](int par, int level) {
+  auto build_upper_to = [&](int64_t t, int level) {
+    const int par = static_cast<int>(t & 1);
     if (up_top < lc + 1) {
       for (int b = lane64; b < G; b += 64) up[b] = get(a.tree[par] + tree_off(m, lc + 1) + b);
       wsync();
@@ -941,10 +950,12 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       wsync();
     }
   };
-  auto lt_value = [&](int par, int level, int idx) -> double {
+  auto lt_value = [&](int64_t t, int level, int idx) -> double {
+    const int par = static_cast<int>(t & 1);
     if (level <= lc + 1) {
       const int lo = kbase >> (level - 1);
-      if (idx >= lo && idx < lo + (c >> (level - 1))) return lvp(par)[2 * c - ((2 * c) >> (level - 1)) + (idx - lo)];
+      if (idx >= lo && idx < lo + (c >> (level - 1)))
+        return lvp(static_cast<int>(t % 3))[2 * c - ((2 * c) >> (level - 1)) + (idx - lo)];
       if (level == lc + 1) return up[idx];
       return get(a.tree[par] + tree_off(m, level) + idx);
     }
@@ -956,7 +967,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   // rec_from .. lc+1
   auto publish = [&](int64_t t, int rec_from) {
     const int par = static_cast<int>(t & 1);
-    double* lv = lvp(par);
+    double* lv = lvp(static_cast<int>(t % 3));
     if (c <= 64) {
       double v = (lane64 < c) ? lv[lane64] : ninf();
       for (int l = 2; l <= lc + 1; ++l) {
@@ -1017,40 +1028,63 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     }
     return __all(ok) != 0;
   };
-  // Stage 1 of step t: this block's level-1 ENF record goes to slot t mod 3
-  // of a ring whose words are NaN until written (into each of the ring's
-  // copies, by one lane per copy; the block polls one copy, and what is said
-  // here holds copy by copy, the clearing and the next record of a copy
-  // being stored by the same lane); each lane waits until the
-  // records of its blocks (those wave_reduce_enf(G, ...) assigns it) are
-  // complete, and they are joined as wave_reduce_enf joins them.  A record
-  // is the block's arrival: no flag, and no wait for the record's own
-  // stores.  Slot t+1 mod 3 held the records of step t-2, which every block
-  // has read (each stored its record of t-1 after taking all of t-2), so it
-  // is cleared beside the record of step t, ahead of its reuse at step t+1;
-  // that clearing completes before the block's next record is stored (the
-  // s_waitcnt below), so a block that sees that record sees the cleared
-  // slot.  (Stored here, the clearing completes within the poll's first
-  // wait instead of holding up the decision after it.)
-  auto level1 = [&](int64_t t, EnfRec& out) -> bool {
-    const int slot = static_cast<int>(t % 3), next = static_cast<int>((t + 1) % 3);
-    const EnfRec* lf = s_leaf[t & 1];
+  // Stage 1's records.  This block's level-1 ENF record of step t goes to
+  // slot t mod kRingSlots of a ring whose words are NaN until written (into
+  // each of the ring's copies, by one lane per copy; the block polls one
+  // copy, and what is said here holds copy by copy, a copy's clearings and
+  // records being stored by the same lane).  A record is the block's
+  // arrival: no flag, and no wait for the record's own stores.  The record
+  // of step t goes out one step before its poll (while the decision of step
+  // t-1 is taken), so the exchange's latency overlaps a whole step.
+  //   Reuse of a slot: beside the record of step t the block clears its
+  // entry of slot t+1 mod kRingSlots, last used by step t+1-kRingSlots =
+  // t-4.  Every block has read the records of t-4: this block has taken all
+  // records of t-2 (the decision before this publication), and each block
+  // stored its record of t-2 after its poll of t-4.  The clearing completes
+  // before this block's next record is stored (the s_waitcnt below), and a
+  // block polls step t+1 only after it has taken this block's record of t,
+  // so it sees the cleared slot.
+  //   When a decision finds that step t-1 interacts, the record of step t
+  // has gone out on the assumption that it does not: every block clears its
+  // entry (no block polls step t before deciding t-1) before the barrier of
+  // the interaction, and publishes the record again after step t is run
+  // again.
+  auto ring_entry = [&](int copy, int64_t t) {
+    return a.ring + static_cast<int64_t>(copy) * (3 * kRingSlots) * G + (t % kRingSlots) * 3 * G + bid;
+  };
+  auto publish_rec = [&](int64_t t) {
+    if (S == 0) return;
+    const EnfRec* lf = s_leaf[t % 3];
     const EnfRec own = wave_reduce_enf(c, [&](int i) { return lf[i]; });
     const EnfRec mine{readlane_f64(own.E, 0), readlane_f64(own.a, 0), readlane_f64(own.b, 0)};
-    const int64_t copy_stride = 9 * static_cast<int64_t>(G);
     __builtin_amdgcn_s_waitcnt(0);
     if (lane64 < kRingCopies) {                                 // lane r writes copy r
-      double* w = a.ring + lane64 * copy_stride + static_cast<int64_t>(slot) * 3 * G;
-      put(w + bid, mine.E);
-      put(w + G + bid, mine.a);
-      put(w + 2 * G + bid, mine.b);
-      double* rp = a.ring + lane64 * copy_stride + static_cast<int64_t>(next) * 3 * G;
+      double* w = ring_entry(lane64, t);
+      put(w, mine.E);
+      put(w + G, mine.a);
+      put(w + 2 * G, mine.b);
+      double* rp = ring_entry(lane64, t + 1);
       const double nan = __longlong_as_double(static_cast<long long>(~0ull));
-      put(rp + bid, nan);
-      put(rp + G + bid, nan);
-      put(rp + 2 * G + bid, nan);
+      put(rp, nan);
+      put(rp + G, nan);
+      put(rp + 2 * G, nan);
     }
-    const double* rs = a.ring + (bid & (kRingCopies - 1)) * copy_stride + static_cast<int64_t>(slot) * 3 * G;
+  };
+  // this block's record of step t taken back (the step is run again)
+  auto retract_rec = [&](int64_t t) {
+    if (lane64 < kRingCopies) {
+      double* w = ring_entry(lane64, t);
+      const double nan = __longlong_as_double(static_cast<long long>(~0ull));
+      put(w, nan);
+      put(w + G, nan);
+      put(w + 2 * G, nan);
+    }
+  };
+  // each lane waits until the records of step t of its blocks (those
+  // wave_join_flat assigns it) are complete; they are joined as
+  // wave_join_flat joins them
+  auto poll_rec = [&](int64_t t, EnfRec& out) -> bool {
+    const double* rs = ring_entry(bid & (kRingCopies - 1), t) - bid;
     const int per = G > 64 ? (G >> 6) : 1;                     // blocks per lane: 4, 2 or 1
     const int i0 = G > 64 ? lane64 * per : lane64;
     const int cnt = G > 64 ? per : (lane64 < G ? 1 : 0);
@@ -1097,17 +1131,17 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   };
   // resampled blocks of step t from LDS to HBM
   auto write_out = [&](int64_t t) {
-    const int par = static_cast<int>(t & 1);
+    const int par = static_cast<int>(t & 1), sl = static_cast<int>(t % 3);
     Store* xo_blk = static_cast<Store*>(a.x1[par]) + static_cast<int64_t>(kbase) * N * DX;
-    for (int64_t w = lane64; w < res_words; w += 64) put(xo_blk + w, res[par * res_words + w]);
+    for (int64_t w = lane64; w < res_words; w += 64) put(xo_blk + w, res[sl * res_words + w]);
   };
-  // Publish step t, wait for the other blocks, decide s*_t and walk; sets
-  // s_ctl[1] when the run ends here (every island dead, or a barrier that
-  // did not complete).  Stage 1 needs only the blocks' level-1 records: they
-  // alone are published first, and the tree and the other levels' records
-  // follow (with a second barrier) only when stage 1 interacts, which every
-  // block decides alike.
-  auto control_step = [&](int64_t t) {
+  // Take the records of step t, decide s*_t and walk; sets s_ctl[1] when the
+  // run ends here (every island dead, or a wait that did not complete).
+  // Stage 1 needs only the blocks' level-1 records; the tree and the other
+  // levels' records follow (with a barrier) only when stage 1 interacts,
+  // which every block decides alike.  `next_out`: the record of step t+1 has
+  // gone out (it is taken back when step t interacts).
+  auto control_step = [&](int64_t t, bool next_out) {
     if (S == 0) {                                     // one island: no stages
       if (lane64 == 0) {
         s_ctl[0] = 0;
@@ -1118,7 +1152,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     }
     const int par = static_cast<int>(t & 1);
     EnfRec r1;
-    if (!level1(t, r1)) { s_ctl[1] = 1; return; }
+    if (!poll_rec(t, r1)) { s_ctl[1] = 1; return; }
     up_top = 0;
     int sstar = 0;
     for (int s = 1; s <= S; ++s) {
@@ -1129,7 +1163,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
         const double* ps = a.part[par] + static_cast<int64_t>(s - 1) * 3 * G;
         r = wave_reduce_enf(G, [&](int i) { return EnfRec{get(ps + i), get(ps + G + i), get(ps + 2 * G + i)}; });
       } else {
-        build_upper_to(par, s);
+        build_upper_to(t, s);
         const double* lvl = up + 2 * G - ((2 * G) >> (s - lc - 1));
         r = wave_reduce_enf(G >> (s - lc - 1), [&](int i) { return enf_leaf(lvl[i]); });
       }
@@ -1145,26 +1179,27 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       if (!enf_below(am, bm, a.tau)) break;
       sstar = s;
       if (s == 1) {
+        if (next_out) retract_rec(t + 1);
         write_out(t);
         publish(t, 2);
         if (!barrier()) { s_ctl[1] = 1; return; }
       }
     }
     if (sstar > 0) {
-      if (sstar + 1 > lc + 1) build_upper_to(par, sstar + 1);
+      if (sstar + 1 > lc + 1) build_upper_to(t, sstar + 1);
       for (int li = lane64; li < c; li += 64) {
         const int k = kbase + li;
         int cur = k;
         for (int s = sstar; s >= 1; --s) {
           const int pr = cur ^ (1 << (s - 1));
-          const double lc_ = lt_value(par, s, cur >> (s - 1));
-          const double lp_ = lt_value(par, s, pr >> (s - 1));
+          const double lc_ = lt_value(t, s, cur >> (s - 1));
+          const double lp_ = lt_value(t, s, pr >> (s - 1));
           uint32_t w[4];
           draw4(key, static_cast<uint32_t>(s), static_cast<uint32_t>(cur), static_cast<uint32_t>(t), kTagIsl, 0, w);
           if (uniform53(w[0], w[1]) < take_partner_prob(lc_, lp_)) cur = pr;
         }
         s_src[li] = cur;
-        s_lpre[li] = lt_value(par, sstar + 1, k >> sstar);
+        s_lpre[li] = lt_value(t, sstar + 1, k >> sstar);
         if (Rec && tr_pi) tr_pi[t * m + k] = cur;
       }
     } else if (Rec && tr_pi) {
@@ -1177,6 +1212,12 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   };
 
   // ================= the step loop =================
+  // Iteration n runs step n in the workers on the assumption that steps n-1
+  // and n-2 do not interact, while the control wave sends out the record of
+  // step n-1 and decides step n-2 from the records sent out one iteration
+  // earlier.  When step n-2 interacts, steps n-1 and n are run again (n-1
+  // from the walk's sources), the record of n-1 going out again beside the
+  // second run of n.
   if (ctl) {
     if (lane64 == 0) { s_ctl[0] = 0; s_ctl[1] = 0; }
     load_y(0);
@@ -1185,20 +1226,39 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   if (!ctl) run_passes(0, false);
   else if (T > kYChunk) load_y(1);
   __syncthreads();
-  for (int64_t n = 1; n < T; ++n) {
+  if (T > 1) {
+    if (ctl) publish_rec(0);
+    else run_passes(1, true);
+    __syncthreads();
+  }
+  for (int64_t n = 2; n < T; ++n) {
     if (ctl) {
-      control_step(n - 1);
+      publish_rec(n - 1);
+      control_step(n - 2, true);
       // chunk n/64 + 1 into the buffer of chunk n/64 - 1, whose last step
-      // (n - 1) is done
-      if (n % kYChunk == 0 && n + kYChunk < T) load_y(n / kYChunk + 1);
+      // (64 (n/64) - 1 = n - 2) this iteration no longer runs
+      if (n % kYChunk == 1 && n > kYChunk && n + kYChunk - 1 < T) load_y(n / kYChunk + 1);
     } else {
       run_passes(n, true);
     }
     __syncthreads();
     if (s_ctl[1]) return;
     if (s_ctl[0] > 0) {
-      // step n again, from the walk's sources
-      if (!ctl) run_passes(n, false);
+      // steps n-1 (from the walk's sources) and n again
+      if (!ctl) run_passes(n - 1, false);
+      __syncthreads();
+      if (ctl) publish_rec(n - 1);
+      else run_passes(n, true);
+      __syncthreads();
+    }
+  }
+  if (T > 1) {
+    // the last decision, s*_{T-2}; no record of step T-1 goes out
+    if (ctl) control_step(T - 2, false);
+    __syncthreads();
+    if (s_ctl[1]) return;
+    if (s_ctl[0] > 0) {
+      if (!ctl) run_passes(T - 1, false);
       __syncthreads();
     }
   }
@@ -1209,7 +1269,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   if (!barrier()) return;
   if (bid == 0) {
     up_top = 0;
-    build_upper_to(static_cast<int>((T - 1) & 1), S + 1);
+    build_upper_to(T - 1, S + 1);
     if (lane64 == 0) {
       *a.out_logz = up[2 * G - 2];
       if (Rec && tr_sstar) tr_sstar[T - 1] = 0;
@@ -1287,6 +1347,13 @@ inline size_t fwd_res_bytes(size_t store_bytes, int dx, int c, int N) {
   return b <= kResidentBudget ? b : 0;
 }
 
+// the pipelined kernel keeps three steps' resampled states (the steps being
+// decided, sent out and run) and island log-weights
+inline size_t pipe_res_bytes(size_t store_bytes, int dx, int c, int N) {
+  const size_t b = 3 * store_bytes * size_t(dx) * size_t(c) * size_t(N);
+  return b <= 3 * (kResidentBudget / 2) ? b : 0;
+}
+
 inline size_t fwd_smem_bytes(size_t store_bytes, int ppt, int dx, int c, int G) {
   const size_t sx = (store_bytes * kBlock * ppt * dx + 15) & ~size_t(15);
   return sx + 4 * size_t(kBlock) * ppt + 8 * 4 * size_t(c) + 8 * 2 * size_t(G);
@@ -1346,8 +1413,13 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
         pk = plain ? reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false, 32>)
                    : reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, true, 32>);
     }
-    const int G = fit_blocks(pk, kPipeBlock, L, a.m, tpb, L.max_blocks < 256 ? L.max_blocks : 256, smem_of, &smem);
-    if (G >= 1 && a.m / G <= kMaxIslandsPerBlock && fwd_res_bytes(sizeof(Store), Model::DX, a.m / G, a.N) > 0) {
+    auto pipe_smem_of = [&](int G) {
+      const int c = a.m / G;
+      return fwd_smem_bytes(sizeof(Store), PPT, Model::DX, c, G) + 8 * 2 * size_t(c) +
+             pipe_res_bytes(sizeof(Store), Model::DX, c, a.N);
+    };
+    const int G = fit_blocks(pk, kPipeBlock, L, a.m, tpb, L.max_blocks < 256 ? L.max_blocks : 256, pipe_smem_of, &smem);
+    if (G >= 1 && a.m / G <= kMaxIslandsPerBlock && pipe_res_bytes(sizeof(Store), Model::DX, a.m / G, a.N) > 0) {
       set_plan(G, smem);
       if (L.plan_only) return hipSuccess;
       return hipLaunchCooperativeKernel(pk, dim3(G), dim3(kPipeBlock), args, static_cast<unsigned>(smem), L.stream);

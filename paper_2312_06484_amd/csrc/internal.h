@@ -12,6 +12,7 @@ namespace airpf {
 // dealt to the eight XCDs round-robin), so the polls of the 256 blocks are
 // spread over eight sets of lines instead of converging on one
 constexpr int kRingCopies = 8;
+constexpr int kRingSlots = 5;               // steps of level-1 records the ring holds
 
 // Kernel argument block of the persistent forward launch (one problem).
 struct FwdArgs {
@@ -30,7 +31,7 @@ struct FwdArgs {
   double* part[2];            // [(lc+1)*3*G] per level: the blocks' ENF records (E, a, b)
   unsigned* bar;              // [G] grid-barrier flags, zero before the launch
   int* status;                // [1] 0 ok, 1 barrier timed out
-  double* ring;               // pipelined kernel: [kRingCopies][3 slots][E, a, b][G] level-1 ENF records, NaN before the launch
+  double* ring;               // pipelined kernel: [kRingCopies][kRingSlots][E, a, b][G] level-1 ENF records, NaN before the launch
   int check_y;                // 1: the observations came from the caller's device memory unchecked
   int* bad_y;                 // [1] set to 1 when such an observation is NaN or infinite
   double* out_logz;           // [1]

@@ -102,6 +102,28 @@ def test_batch_autotuned_tiling_changes_nothing(ctx, want_score):
             assert np.array_equal(gr0, gr1)
 
 
+def test_autotune_cache_file_persists_across_contexts(tmp_path, monkeypatch):
+    """With AIRPF_TUNE_CACHE naming a file, a fresh context's autotuned batch
+    appends its measured ratio there (one line per shape), and a second fresh
+    context finds it instead of measuring again; results are unchanged."""
+    from paper_2312_06484_amd import airpf
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("AIRPF_TUNE_CACHE", str(path))
+    items = sv_batch(6, seed=11)
+    out = []
+    for rep in range(2):
+        c = airpf.Context(0)
+        try:
+            out.append(c.run_batch(1, items, tau=0.4, autotune=True))
+        finally:
+            c.close()
+        lines = [l for l in path.read_text().splitlines() if l.strip()]
+        assert len(lines) == 1, lines
+        key, ratio = lines[0].split()
+        assert len(key) == 16 and float(ratio) > 0
+    assert np.array_equal(out[0][1], out[1][1]) and (out[0][3] == 0).all()
+
+
 def test_full_size_proposal_batch_score_matches_single(ctx):
     """The 64-chain proposal workload at full size (T up to 2000, m up to
     1024, many blocks per problem, checkpoints every 100 steps) with scores:
