@@ -25,11 +25,18 @@ METRIC = "particle-steps/s, fwd and fwd+score, batched vs plain AIRPF, at stated
 HBM_PEAK_GBS = 8000.0
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch from the committed counter record, or None when the
+# Peak issue rate of wave64 VALU instructions: 256 CUs x 4 SIMDs x 2.4 GHz,
+# one wave64 instruction occupying a 16-lane SIMD for 4 cycles.
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+
+
+def measured_counters(workload):
+    """The committed counter record of the benchmark kernel on this workload
+    (profiles/counters.json: HBM bytes per launch from FETCH_SIZE/WRITE_SIZE,
+    wave64 VALU instructions per launch from SQ_INSTS_VALU), or None when the
     kernel sources changed after the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
@@ -37,7 +44,7 @@ def measured_traffic(workload):
         h.update(open(os.path.join(ROOT, "paper_2312_06484_amd", "csrc", f), "rb").read())
     for key, rec in json.load(open(path)).items():
         if key.endswith(" " + workload) and rec.get("kernel_sources_sha256") == h.hexdigest():
-            return rec["traffic_bytes_per_launch"]
+            return rec
     return None
 
 
@@ -457,6 +464,7 @@ def main():
 
     extras = None if args.no_extras else measure_modes(ctx, torch)
 
+    counters = measured_counters(args.workload)
     out = {
         "metric": METRIC,
         "value": value,
@@ -468,13 +476,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if wl["f32"] else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "T": T, "m": m, "N_per_island": N, "tau": args.tau,
                    "state_storage": "f32" if wl["f32"] else "f64", "mode": "forward",
+                   "arithmetic": ("particles binary32, weights 40-bit fixed point (uint64), island "
+                                  "log-weights and log Zhat f64") if wl["f32"] else "particles, island "
+                                 "log-weights and log Zhat f64, weights 40-bit fixed point (uint64)",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counters["traffic_bytes_per_launch"] if counters else None,
+                     "valu_frac": (counters["valu_insts_per_launch"] / (avg_k * 1e-3) / VALU_PEAK_WAVE_INSTS
+                                   if counters else None),
+                     "valu_peak_wave_insts_per_s": VALU_PEAK_WAVE_INSTS,
                      "kernel": ("forward_kernel" if os.environ.get("AIRPF_PIPELINE", "1").startswith("0")
                                 else "forward_pipe_kernel"), "kernel_ms": avg_k,
                      "bytes_per_particle_step": bpp},

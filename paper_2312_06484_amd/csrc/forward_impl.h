@@ -1094,14 +1094,23 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     unsigned spins = 0;
     int ok = 1;
     while (got != all) {
+      // every word of the lane's blocks is loaded before any is tested: the
+      // records were sent out a step earlier and are mostly here, so a poll
+      // is one round trip, not one per block (a record already taken is
+      // read again, unused)
+      double e[4], va[4], vb[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (j < cnt && !(got & (1u << j))) {
-          const double e = get(rs + i0 + j), va = get(rs + G + i0 + j), vb = get(rs + 2 * G + i0 + j);
-          if (e == e && va == va && vb == vb) {
-            rec[j] = EnfRec{e, va, vb};
-            got |= 1u << j;
-          }
+        const bool want = j < cnt;
+        e[j] = want ? get(rs + i0 + j) : 0.0;
+        va[j] = want ? get(rs + G + i0 + j) : 0.0;
+        vb[j] = want ? get(rs + 2 * G + i0 + j) : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j < cnt && !(got & (1u << j)) && e[j] == e[j] && va[j] == va[j] && vb[j] == vb[j]) {
+          rec[j] = EnfRec{e[j], va[j], vb[j]};
+          got |= 1u << j;
         }
       }
       if (got == all) break;
