@@ -38,7 +38,7 @@ class _Problem(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("scheme", C.c_int32),
                 ("f32", C.c_int32), ("replay", C.c_int32),
-                ("exact_weights", C.c_int32)]
+                ("exact_weights", C.c_int32), ("ess_frac", C.c_double)]
 
 
 class _Trace(C.Structure):
@@ -240,17 +240,19 @@ class Trace:
         return t
 
 
-def _opts(tau, scheme, f32, replay=0):
+def _opts(tau, scheme, f32, replay=0, ess_frac=0.0):
     o = _Opts()
     o.tau, o.scheme, o.f32, o.replay, o.exact_weights = float(tau), int(scheme), int(f32), int(replay), 0
+    o.ess_frac = float(ess_frac)
     return o
 
 
-def run(prob, tau=0.3, scheme=0, f32=False, trace=None):
+def run(prob, tau=0.3, scheme=0, f32=False, trace=None, ess_frac=0.0):
     """Forward AIRPF; returns log Zhat (fixed-point weights).  ``f32``:
     binary32 particles (state, normals, model, weights; island log-weights
-    and log Zhat in double)."""
-    p, o = prob._c(), _opts(tau, scheme, f32)
+    and log Zhat in double).  ``ess_frac`` > 0: adaptive internal
+    resampling (an island resamples iff its ESS < ess_frac * N)."""
+    p, o = prob._c(), _opts(tau, scheme, f32, ess_frac=ess_frac)
     t = trace._c() if trace is not None else None
     return lib().orc_airpf_run(C.byref(p), C.byref(o), C.byref(t) if t is not None else None)
 

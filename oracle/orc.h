@@ -42,6 +42,11 @@ typedef struct {
   int32_t replay;        /* 1: ancestors, island maps, stage counts read
                             from the trace instead of being drawn            */
   int32_t exact_weights; /* 1: island weights from the unquantised sum       */
+  double ess_frac;       /* 0: every island resamples internally at every
+                            step.  rho > 0: adaptive internal resampling, an
+                            island resamples iff its ESS < rho N (ESS from the
+                            fixed-point weights truncated to 20 bits), else
+                            its particles keep their weights                 */
 } orc_opts;
 
 typedef struct {

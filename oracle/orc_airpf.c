@@ -205,6 +205,17 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
     Sfn = calloc((size_t)mN, sizeof(double));
   }
   const double cst_q = M.c_log - 40.0 * log(2.0) - log((double)N);
+  /* adaptive internal resampling (ess_frac > 0): a particle's carried
+     weight lc = log of its fixed-point weight at the last weighting (0 right
+     after a resampling), an island's carried normaliser dq = log Q - log N of
+     that weighting (0 after a resampling); both travel with the block */
+  const int adapt = O->ess_frac > 0.0;
+  const double logN = log((double)N);
+  double* lc = calloc((size_t)mN, sizeof(double));
+  double* lcn = calloc((size_t)mN, sizeof(double));
+  double* dq = calloc((size_t)m, sizeof(double));
+  double* dqn = calloc((size_t)m, sizeof(double));
+  int* resamp = malloc(sizeof(int) * m);
   const double cst_x = M.c_log - log((double)N);
 
   /* Initialisation: W^k_{0,0} = 1, xi^k_{0,0} ~ pi_0^{(x)M} */
@@ -233,6 +244,8 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
       double* lwk = lw + (int64_t)k * N;
       for (int32_t j = 0; j < N; ++j)
         lwk[j] = nan_to_ninf(orc_model_logpot(&M, x + ((int64_t)k * N + j) * dx, yn));
+      if (adapt)
+        for (int32_t j = 0; j < N; ++j) lwk[j] = lc[(int64_t)k * N + j] + lwk[j];
       double mx;
       orc_model_quantise(&M, lwk, N, q + (int64_t)k * N, &mx);
       uint64_t Q = 0;
@@ -250,6 +263,21 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
       }
       L[k] = (Q == 0) ? -INFINITY : L[k] + ((mx + orc_log((double)Q)) + cst_q);
       Lx[k] = (mx == -INFINITY) ? -INFINITY : Lx[k] + ((mx + orc_log(se)) + cst_x);
+      if (adapt) {
+        /* the carried normaliser: Algorithm 1's island weight update with the
+           particles' incoming weights q_prev / Q_prev instead of 1 / N */
+        if (Q != 0) L[k] = L[k] - dq[k];
+        if (mx != -INFINITY) Lx[k] = Lx[k] - dq[k];
+        /* the ESS of the island's weights, from the weights truncated to
+           their top 20 of 40 bits (exact integer sums) */
+        uint64_t Qt = 0, S2 = 0;
+        for (int32_t j = 0; j < N; ++j) {
+          const uint64_t qt = q[(int64_t)k * N + j] >> 20;
+          Qt += qt;
+          S2 += qt * qt;
+        }
+        resamp[k] = Q != 0 && S2 != 0 && (double)Qt * (double)Qt < O->ess_frac * (double)N * (double)S2;
+      }
       if (want_score) {
         double* dLk = dL + (int64_t)k * Pn;
         for (int32_t j = 0; j < N; ++j) {
@@ -316,7 +344,7 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
       int32_t* ak = anc + (int64_t)k * N;
       if (O->replay) {
         memcpy(ak, tr->anc + n * mN + (int64_t)k * N, sizeof(int32_t) * N);
-      } else if (Qk[k] == 0) {
+      } else if (Qk[k] == 0 || (adapt && !resamp[k])) {
         for (int32_t j = 0; j < N; ++j) ak[j] = j;
       } else if (O->scheme == 1) {
         multinomial(q + (int64_t)k * N, N, P->seed, n, k, Qk[k], ak);
@@ -377,14 +405,26 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
       tr->digest[2 * n + 1] = dp;
     }
 
+    /* carried weights after the internal step: 0 after a resampling, else
+       the log of the fixed-point weight */
+    if (adapt)
+      for (int32_t k = 0; k < m; ++k)
+        for (int32_t j = 0; j < N; ++j) {
+          const int64_t id = (int64_t)k * N + j;
+          lc[id] = resamp[k] ? 0.0 : orc_log((double)q[id]);
+          if (j == 0) dq[k] = resamp[k] ? 0.0 : orc_log((double)Qk[k]) - logN;
+        }
+
     /* mutation into step n+1 */
     for (int32_t k = 0; k < m; ++k) {
       orc_model_noise(&M, P->seed, n + 1, k, N, z);
       const int32_t sk = pi[k];
+      if (adapt) dqn[k] = dq[sk];
       for (int32_t j = 0; j < N; ++j) {
         const int64_t par = (int64_t)sk * N + anc[(int64_t)sk * N + j];
         const int64_t id = (int64_t)k * N + j;
         orc_model_prop(&M, x + par * dx, z + (size_t)j * nd, xn + id * dx);
+        if (adapt) lcn[id] = lc[par];
         if (want_score) {
           orc_model_prop_tangent(&M, x + par * dx, dX + par * dx * Pn, z + (size_t)j * nd,
                                  dXn + id * dx * Pn);
@@ -394,6 +434,10 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
       }
     }
     { double* t = x; x = xn; xn = t; }
+    if (adapt) {
+      double* t = lc; lc = lcn; lcn = t;
+      t = dq; dq = dqn; dqn = t;
+    }
     if (want_score) {
       double* t = dX; dX = dXn; dXn = t;
       t = Sp; Sp = Spn; Spn = t;
@@ -407,6 +451,7 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
   free(Lpre); free(Lnew); free(Lxnew); free(pi); free(pinew); free(src); free(z);
   free(dX); free(dXn); free(Sp); free(Spn); free(dL); free(dLn); free(dlw);
   free(Sf); free(Sfn);
+  free(lc); free(lcn); free(dq); free(dqn); free(resamp);
   return 0;
 }
 
