@@ -126,6 +126,19 @@ typedef struct {
   int32_t score_mode; /* airpf_score_mode (airpf_score, airpf_run_batch with scores) */
   int32_t ckpt_every; /* checkpoint interval of the score's recomputation (0: auto) */
   uint32_t flags;     /* AIRPF_FLAG_* */
+  double resample_ess; /* 0: every island resamples internally at every step
+                          (Algorithm 1).  rho > 0: adaptive internal
+                          resampling (the remark after Algorithm 1 that the
+                          analysis does not need a resampling at every step):
+                          an island resamples (systematically) iff the ESS of
+                          its fixed-point weights, truncated to their top 20
+                          of 40 bits, is below rho * N; otherwise its
+                          particles carry their weights into the next
+                          weighting, and the island weight is updated with
+                          those incoming weights.  airpf_run only (double
+                          states, systematic; score, batch and
+                          airpf_run_noalloc return AIRPF_E_UNSUPPORTED);
+                          negative or NaN: AIRPF_E_INVALID_ARG */
 } airpf_options;
 
 /* Optional per-call trace, host arrays (any may be NULL). */

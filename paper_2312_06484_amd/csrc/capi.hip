@@ -91,7 +91,7 @@ struct airpf_ctx {
   unsigned char* scratch = nullptr;   // this device's copy of the no-allocation scratch array
   hipEvent_t ev[2] = {nullptr, nullptr};
   double last_kernel_ms = 0.0;
-  DevBuf x1[2], tree[2], part[2], misc, ybuf;
+  DevBuf x1[2], tree[2], part[2], misc, ybuf, ad_lc[2], ad_dq[2];
   DevBuf t_sstar, t_enf, t_lpost, t_anc, t_pi, t_dig, t_fmean;
   DevBuf s_pi, s_sstar, s_lpre, s_ckx, s_ckL, s_recx, s_reca, s_lam[2], s_del[2], s_grad, s_nu;
   DevBuf dbg_in, dbg_in32, dbg_out, dbg_out2, dbg_out32;
@@ -142,6 +142,7 @@ extern "C" airpf_status airpf_ctx_destroy(airpf_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
   for (DevBuf* b : {&c->x1[0], &c->x1[1], &c->tree[0], &c->tree[1], &c->part[0], &c->part[1], &c->misc,
+                    &c->ad_lc[0], &c->ad_lc[1], &c->ad_dq[0], &c->ad_dq[1],
                     &c->ybuf, &c->t_sstar, &c->t_enf, &c->t_lpost, &c->t_anc, &c->t_pi, &c->t_dig, &c->t_fmean,
                     &c->dbg_in, &c->dbg_in32, &c->dbg_out, &c->dbg_out2, &c->dbg_out32, &c->s_pi,
                     &c->s_sstar, &c->s_lpre, &c->s_ckx, &c->s_ckL, &c->s_recx, &c->s_reca, &c->s_lam[0],
@@ -283,6 +284,7 @@ airpf_options default_options() {
   o.score_mode = AIRPF_PATHSPACE;
   o.ckpt_every = 0;
   o.flags = 0;
+  o.resample_ess = 0.0;
   return o;
 }
 
@@ -322,6 +324,12 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   if (!(opt.tau == opt.tau)) return AIRPF_E_INVALID_ARG;
   if (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) return AIRPF_E_INVALID_ARG;
   if (opt.resampling != AIRPF_SYSTEMATIC && opt.resampling != AIRPF_MULTINOMIAL) return AIRPF_E_INVALID_ARG;
+  if (!(opt.resample_ess >= 0.0) || !std::isfinite(opt.resample_ess)) return AIRPF_E_INVALID_ARG;
+  const bool adapt = opt.resample_ess > 0.0;
+  // adaptive internal resampling: systematic when an island resamples, states
+  // in double, every workspace from the context
+  if (adapt && (opt.resampling != AIRPF_SYSTEMATIC || fixed)) return AIRPF_E_UNSUPPORTED;
+  if (adapt) P->opt.precision = AIRPF_FP64;
 
   airpf::FwdArgs& a = P->a;
   std::memset(&a, 0, sizeof(a));
@@ -392,6 +400,16 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
     }
     ST_OK(ctx->misc.ensure(misc_bytes));
     misc = static_cast<unsigned char*>(ctx->misc.p);
+    if (adapt) {
+      for (int p = 0; p < 2; ++p) {
+        ST_OK(ctx->ad_lc[p].ensure(sizeof(double) * size_t(m) * N));
+        ST_OK(ctx->ad_dq[p].ensure(sizeof(double) * size_t(m)));
+        a.lc1[p] = static_cast<double*>(ctx->ad_lc[p].p);
+        a.dq1[p] = static_cast<double*>(ctx->ad_dq[p].p);
+      }
+      a.ess_frac = opt.resample_ess;
+      a.log_N = std::log(static_cast<double>(N));
+    }
     if (!y_dev) {
       ST_OK(ctx->ybuf.ensure(y_bytes));
       ybuf = ctx->ybuf.p;
@@ -520,6 +538,8 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   }
   // the reverse pass finds a particle's children as a run of sorted ancestors
   if (opt.resampling == AIRPF_MULTINOMIAL) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
+  // adaptive internal resampling: forward only
+  if (opt.resample_ess != 0.0) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
   // the word-driven models' mutations are not differentiable in theta
   if (model && (model->kind == AIRPF_BIN || model->kind == AIRPF_BCP)) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
   if (model && ((model->kind == AIRPF_LGD && N > 512) || (model->kind != AIRPF_LGD && N > 1024))) {
@@ -801,6 +821,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   if (!ctx || !model || B < 0 || (B > 0 && (!probs || !log_z_out || !item_status))) return AIRPF_E_INVALID_ARG;
   if (model->kind == AIRPF_BIN || model->kind == AIRPF_BCP) return AIRPF_E_UNSUPPORTED;   // single problems only
   const airpf_options opt = opt_in ? *opt_in : default_options();
+  if (opt.resample_ess != 0.0) return AIRPF_E_UNSUPPORTED;      // adaptive internal resampling: single problems
   if (want_score && !grad_out) return AIRPF_E_INVALID_ARG;
   if (!(opt.tau == opt.tau) || (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) || opt.ckpt_every < 0)
     return AIRPF_E_INVALID_ARG;

@@ -97,7 +97,9 @@ __device__ __forceinline__ void draw_noise(const Key& key, int64_t n, int k, int
 // registers they hold) exist in it.
 // Mult: multinomial internal resampling (a kernel of its own, so that the
 // systematic kernels carry none of its code or registers).
-template <class Model, typename Store, int PPT, bool Plain, bool Mult = false>
+// Adapt: adaptive internal resampling (systematic when an island resamples;
+// a kernel of its own, states in double, sources always from HBM).
+template <class Model, typename Store, int PPT, bool Plain, bool Mult = false, bool Adapt = false>
 __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;                 // normals per lane per step
@@ -355,6 +357,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       if (!pre && n < a.T - 1 && lane == 0) draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
       Store x[PPT][DX];
       double Lpre = 0.0;
+      double lcr[PPT];                        // Adapt: the particles' carried log-weights
+      double dqs = 0.0;                       // and the island's carried log normaliser
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) lcr[r] = 0.0;
       if (n == n0 && ck_in) {
         // restart from the checkpoint taken entering this step
         const Store* xc = static_cast<const Store*>(ck_x) + (n / ck_every) * (static_cast<int64_t>(m) * N * DX) +
@@ -372,6 +378,12 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       } else {
         const int src = spec ? k : s_src[active ? li : 0];
         if (lane == 0 && active) Lpre = spec ? lvp(ppar)[li] : s_lpre[li];
+        if constexpr (Adapt) {
+          const double* lin = a.lc1[ppar] + static_cast<int64_t>(src) * N;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r) lcr[r] = (j0 + r < N) ? get(lin + j0 + r) : 0.0;
+          if (lane == 0 && active) dqs = get(a.dq1[ppar] + src);
+        }
         // the source block's loads go out first; the normals do not need them.
         // A source island of this block is read from its LDS copy.
         Store xr[PPT][DX];
@@ -441,6 +453,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         const bool valid = active && (j0 + r < N);
         Store v = valid ? Model::template logpot<Store>(a.mp, x[r], yn) : neg_inf<Store>();
         if (!(v == v)) v = neg_inf<Store>();
+        if constexpr (Adapt) v = static_cast<Store>(lcr[r]) + v;     // the weight carried in
         lw[r] = v;
         mx = rmax(mx, v);
       }
@@ -457,9 +470,27 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
       const uint64_t Qk = TP == 64 ? readlane_u64(incl, 63)
                           : (TP < 64 ? __shfl(incl, (tid & 63) | (TP - 1), 64) : team_sum_u64(tsum, TP, red_u));
       if (lane == 0 && active && !replay) {
-        const double L = (Qk == 0) ? ninf() : Lpre + ((static_cast<double>(mx) + dlog(static_cast<double>(Qk))) + a.cst_q);
+        double L = (Qk == 0) ? ninf() : Lpre + ((static_cast<double>(mx) + dlog(static_cast<double>(Qk))) + a.cst_q);
+        if constexpr (Adapt) {
+          if (Qk != 0) L = L - dqs;                        // the incoming weights' normaliser
+        }
         lvp(par)[li] = L;
         if (tr_lpost) tr_lpost[n * m + k] = L;
+      }
+      // Adapt: whether the island resamples, from the ESS of its weights
+      // truncated to their top 20 of 40 bits (exact integer sums)
+      bool resamp = true;
+      if constexpr (Adapt) {
+        uint64_t t1 = 0, t2 = 0;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const uint64_t qt = q[r] >> 20;
+          t1 += qt;
+          t2 += qt * qt;
+        }
+        const uint64_t Qt = team_sum_u64(t1, TP, red_u), S2 = team_sum_u64(t2, TP, red_u);
+        resamp = Qk != 0 && S2 != 0 &&
+                 static_cast<double>(Qt) * static_cast<double>(Qt) < a.ess_frac * static_cast<double>(N) * static_cast<double>(S2);
       }
       if (tr_fmean) {
         // the island's estimate of the filtering mean of x[0]: sum_i q_i x_i / Q
@@ -555,7 +586,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           const int j = j0 + r;
-          if (active && j < N) sAt[j] = Qk > 0 ? (mk[r] > before ? mk[r] : before) : j;
+          if (active && j < N) sAt[j] = (Qk > 0 && resamp) ? (mk[r] > before ? mk[r] : before) : j;
         }
         }  // systematic
         // (each lane reads back only the ancestors of its own slots)
@@ -588,6 +619,18 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
               if (!spec) put(xo + w, v);
               if (a.res_lds) res[par * res_words + static_cast<int64_t>(li) * N * DX + w] = v;
             }
+          }
+        }
+        if constexpr (Adapt) {
+          // carried into the next weighting: nothing after a resampling,
+          // else each particle's log fixed-point weight and the island's
+          // log Q - log N
+          if (active) {
+            double* lo = a.lc1[par] + static_cast<int64_t>(k) * N;
+#pragma unroll
+            for (int r = 0; r < PPT; ++r)
+              if (j0 + r < N) put(lo + j0 + r, resamp ? 0.0 : dlog(static_cast<double>(q[r])));
+            if (lane == 0) put(a.dq1[par] + k, resamp ? 0.0 : dlog(static_cast<double>(Qk)) - a.log_N);
           }
         }
         team_sync(TP);
@@ -671,21 +714,22 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
 
 // ------------------------------------------------------------ pipelined forward
 // Untraced runs whose resampled states fit the block's LDS copy and whose
-// teams lie inside one wave (TP <= 64), with 1/(2m) < tau <= 1.
+// teams lie inside one wave (TP <= 64), with tau <= 1 (tau <= 1/(2m): no
+// stage can interact, and nothing is exchanged until the final log Zhat).
 //
 // Most steps do not interact, and then a block's next step needs nothing
 // from the other blocks.  A block of this kernel has four worker waves
 // (the island passes, exactly those of forward_body) and one control wave
 // that does everything involving other blocks.  Between two joins (block
-// barriers) the workers run step n under the assumption s*_{n-1} = 0 (every
-// island continues from its own resampled block with its own weight, both
-// in LDS), while the control wave builds the island tree and ENF records of
-// step n-1, publishes them, waits for the other blocks, and evaluates the
-// stages of step n-1 one at a time until one does not interact.  After the
-// join, a step whose cascade found s* > 0 is run again with the walk's
-// sources (all blocks have passed the barrier by then).  Every value is
-// computed by the same operations as in forward_body, so the results are
-// identical.
+// barriers) the workers run step n on the assumption that steps n-1 and
+// n-2 do not interact (every island continues from its own resampled block
+// with its own weight, all in LDS), while the control wave sends out its
+// level-1 ENF record of step n-1 and decides step n-2 from the records sent
+// out one iteration earlier, evaluating the stages one at a time until one
+// does not interact.  When step n-2 interacts, steps n-1 (from the walk's
+// sources; all blocks have passed the interaction's barrier by then) and n
+// are run again.  Every value is computed by the same operations as in
+// forward_body, so the results are identical.
 //
 // Stage 1 needs only the blocks' level-1 ENF records, so the control wave
 // publishes those alone (in a ring where a record is also the block's
@@ -1220,6 +1264,18 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     }
   };
 
+  // τ so small that no stage can ever interact: nothing is exchanged until
+  // the final log Zhat (the decisions are s* = 0 by definition)
+  const bool never = a.no_interaction;
+  auto settle = [&](int64_t t) {
+    if (lane64 == 0) {
+      s_ctl[0] = 0;
+      if (Rec && tr_sstar) tr_sstar[t] = 0;
+    }
+    if (Rec && tr_pi)
+      for (int li = lane64; li < c; li += 64) tr_pi[t * m + kbase + li] = kbase + li;
+  };
+
   // ================= the step loop =================
   // Iteration n runs step n in the workers on the assumption that steps n-1
   // and n-2 do not interact, while the control wave sends out the record of
@@ -1236,14 +1292,21 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   else if (T > kYChunk) load_y(1);
   __syncthreads();
   if (T > 1) {
-    if (ctl) publish_rec(0);
-    else run_passes(1, true);
+    if (ctl) {
+      if (!never) publish_rec(0);
+    } else {
+      run_passes(1, true);
+    }
     __syncthreads();
   }
   for (int64_t n = 2; n < T; ++n) {
     if (ctl) {
-      publish_rec(n - 1);
-      control_step(n - 2, true);
+      if (never) {
+        settle(n - 2);
+      } else {
+        publish_rec(n - 1);
+        control_step(n - 2, true);
+      }
       // chunk n/64 + 1 into the buffer of chunk n/64 - 1, whose last step
       // (64 (n/64) - 1 = n - 2) this iteration no longer runs
       if (n % kYChunk == 1 && n > kYChunk && n + kYChunk - 1 < T) load_y(n / kYChunk + 1);
@@ -1263,7 +1326,10 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   }
   if (T > 1) {
     // the last decision, s*_{T-2}; no record of step T-1 goes out
-    if (ctl) control_step(T - 2, false);
+    if (ctl) {
+      if (never) settle(T - 2);
+      else control_step(T - 2, false);
+    }
     __syncthreads();
     if (s_ctl[1]) return;
     if (s_ctl[0] > 0) {
@@ -1294,6 +1360,12 @@ __global__ __launch_bounds__(kPipeBlock) void forward_pipe_kernel(FwdArgs a) {
 template <class Model, typename Store, int PPT, bool Plain>
 __global__ __launch_bounds__(kBlock) void forward_kernel(FwdArgs a) {
   forward_body<Model, Store, PPT, Plain>(a, static_cast<int>(blockIdx.x));
+}
+
+// adaptive internal resampling (single problem, traced or not; double states)
+template <class Model, typename Store, int PPT>
+__global__ __launch_bounds__(kBlock) void forward_adapt_kernel(FwdArgs a) {
+  forward_body<Model, Store, PPT, false, false, true>(a, static_cast<int>(blockIdx.x));
 }
 
 // multinomial internal resampling (single problem, traced or not)
@@ -1344,7 +1416,7 @@ inline bool fwd_is_score_forward(const FwdArgs& a) {
 }
 
 inline bool fwd_pipe_candidate(const FwdArgs& a, int TP) {
-  if (!(fwd_is_plain(a) || fwd_is_score_forward(a)) || TP > 64 || a.no_interaction || a.shortcut_all ||
+  if (!(fwd_is_plain(a) || fwd_is_score_forward(a)) || TP > 64 || a.shortcut_all || a.ess_frac > 0.0 ||
       a.multinomial)
     return false;
   const char* e = std::getenv("AIRPF_PIPELINE");
@@ -1437,10 +1509,15 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
   const void* kern = a.multinomial    ? reinterpret_cast<const void*>(forward_mult_kernel<Model, Store, PPT>)
                      : fwd_is_plain(a) ? reinterpret_cast<const void*>(forward_kernel<Model, Store, PPT, true>)
                                        : reinterpret_cast<const void*>(forward_kernel<Model, Store, PPT, false>);
+  if (a.ess_frac > 0.0) {
+    if constexpr (std::is_same<Store, double>::value) kern = reinterpret_cast<const void*>(forward_adapt_kernel<Model, Store, PPT>);
+    else return hipErrorInvalidValue;                           // adaptive runs keep double states
+  }
   const int G = fit_blocks(kern, kBlock, L, a.m, tpb, L.max_blocks, smem_of, &smem);
   if (G < 1) return hipErrorCooperativeLaunchTooLarge;
   if (a.m / G > kMaxIslandsPerBlock) return hipErrorInvalidValue;     // islands per block are bounded by the LDS plan
   set_plan(G, smem);
+  if (a.ess_frac > 0.0) a.res_lds = 0;        // the adaptive kernel reads every source block from HBM
   if (L.plan_only) return hipSuccess;
   return hipLaunchCooperativeKernel(kern, dim3(G), dim3(kBlock), args, static_cast<unsigned>(smem), L.stream);
 }

@@ -42,6 +42,15 @@ struct FwdArgs {
   int32_t* tr_pi;
   unsigned long long* tr_digest;
   double* tr_fmean;           // [T*m] island weighted means of x[0] after each weighting
+  // adaptive internal resampling (ess_frac > 0; the serial kernel of its own):
+  // an island resamples iff the ESS of its 20-bit-truncated fixed-point
+  // weights is below ess_frac * N; otherwise its particles carry log q (lc1)
+  // and the island log Q - log N (dq1) into the next weighting; both by step
+  // parity, [m*N] and [m]
+  double ess_frac;
+  double log_N;
+  double* lc1[2];
+  double* dq1[2];
   // ---- what the score needs (all optional) ----
   int64_t n0, n1;             // steps [n0, n1) of this launch (0, T for a plain run)
   int replay_pi;              // 1: island maps from tr_pi, no cascade, no island weights

@@ -1,0 +1,88 @@
+"""Adaptive internal resampling on the GPU (the remark after Algorithm 1 that
+the analysis does not need every island to resample at every step) against
+the oracle: an island resamples iff the ESS of its 20-bit-truncated
+fixed-point weights is below rho N, otherwise its particles carry their
+weights.  Island log-weights after every weighting, ancestors (identity for
+an island that did not resample), island maps, s* and digests bit-exact, log
+Zhat to 1e-12; a threshold above every ESS is the plain filter bit for bit."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from test_gpu_forward import assert_parity, make_case  # noqa: E402
+
+from paper_2312_06484_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2312_06484_amd import airpf
+    c = airpf.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("model,m,N,T,tau,rho,dx", [
+    ("lg1", 16, 24, 40, 0.5, 0.5, None),
+    ("sv", 64, 37, 30, 0.7, 0.8, None),            # ragged island size
+    ("lgd", 16, 64, 20, 0.6, 0.6, 4),
+    ("lg1", 256, 256, 25, 0.9, 0.3, None),         # several blocks, interactions on most steps
+    ("lg1", 32, 16, 30, 0.0, 0.5, None),           # independent filters
+    ("sv", 4, 1000, 8, 2.0, 0.9, None),            # islands of several waves, every stage interacts
+])
+def test_adaptive_parity(ctx, orc, model, m, N, T, tau, rho, dx):
+    from paper_2312_06484_amd import airpf
+    g, P = make_case(orc, model, m, N, T, 6, dx)
+    print("case adaptive", model, dx, m, N, T, tau, rho, flush=True)
+    gt = airpf.Trace(T, m, N)
+    kw = dict(tau=tau, fp64=True, dx=g["dx"], dy=g["dy"], consts=g["consts"], resample_ess=rho)
+    _, lz = ctx.run(g["kind"], g["theta"], g["y"], m, N, 6, trace=gt, **kw)
+    ot = orc.Trace(P)
+    lo = orc.run(P, tau=tau, trace=ot, ess_frac=rho)
+    assert_parity(lz, gt, lo, ot, P)
+    a = gt.anc[: (T - 1) * m * N].reshape(T - 1, m, N)
+    kept = (a == np.arange(N)).all(axis=2).mean()
+    print("islands keeping their weights:", kept, flush=True)
+    _, lz2 = ctx.run(g["kind"], g["theta"], g["y"], m, N, 6, **kw)
+    assert lz2 == lz
+
+
+def test_adaptive_change_point_model(ctx, orc):
+    from paper_2312_06484_amd import airpf
+    y = W.bcp_data(60)
+    AB = [float(v) for v in W.BCP_AB]
+    m, N, T = 8, 16, 60
+    gt = airpf.Trace(T, m, N)
+    _, lz = ctx.run(airpf.BCP, [0.05], y, m, N, 2, tau=0.5, fp64=True, dx=2, dy=2, consts=AB, trace=gt,
+                    resample_ess=0.5)
+    P = orc.Problem(orc.BCP, [0.05], y, m, N, 2, dx=2, dy=2, consts=AB)
+    ot = orc.Trace(P)
+    lo = orc.run(P, tau=0.5, trace=ot, ess_frac=0.5)
+    assert_parity(lz, gt, lo, ot, P)
+
+
+def test_threshold_above_every_ess_is_the_plain_filter(ctx, orc):
+    g, P = make_case(orc, "lg1", 64, 32, 40, 3)
+    kw = dict(tau=0.5, fp64=True)
+    _, plain = ctx.run(g["kind"], g["theta"], g["y"], 64, 32, 3, **kw)
+    _, adapt = ctx.run(g["kind"], g["theta"], g["y"], 64, 32, 3, resample_ess=2.0, **kw)
+    assert plain == adapt
+
+
+def test_adaptive_unsupported_and_invalid(ctx):
+    from paper_2312_06484_amd import airpf
+    y = W.lg1_data(10)
+    kw = dict(raise_on_error=False)
+    assert ctx.run(0, W.LG1_THETA, y, 4, 16, 1, resample_ess=-1.0, **kw)[0] == airpf.E_INVALID_ARG
+    assert ctx.run(0, W.LG1_THETA, y, 4, 16, 1, resample_ess=0.5, resampling=airpf.MULTINOMIAL,
+                   **kw)[0] == airpf.E_UNSUPPORTED
+    assert ctx.run(0, W.LG1_THETA, y, 4, 16, 1, resample_ess=float("nan"), **kw)[0] == airpf.E_INVALID_ARG
+    assert ctx.score(0, W.LG1_THETA, y, 4, 16, 1, resample_ess=0.5, **kw)[0] == airpf.E_UNSUPPORTED
+    assert ctx.run_noalloc(0, W.LG1_THETA, y, 4, 16, 1, resample_ess=0.5, **kw)[0] == airpf.E_UNSUPPORTED
+    pr = [dict(theta=W.LG1_THETA, y=y, m=4, N=16, seed=1)]
+    assert ctx.run_batch(0, pr, resample_ess=0.5, **kw)[0] == airpf.E_UNSUPPORTED

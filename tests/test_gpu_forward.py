@@ -330,6 +330,7 @@ def test_untraced_run_without_interactions(ctx, orc, model, m, N, T, tau, f64, d
     ("sv", 16384, 16, 60, 0.8, False, None),       # 64 islands per block
     ("lg1", 65536, 4, 30, 0.6, False, None),       # 256 islands per block
     ("lgd", 2048, 64, 20, 1.5, False, 8),          # untraced serial kernel (every stage interacts) on 512 blocks
+    ("lg1", 1024, 256, 70, 0.0, False, None),      # independent filters: the pipelined kernel exchanges nothing
 ])
 def test_untraced_run_matches_traced(ctx, orc, model, m, N, T, tau, f64, dx):
     """An untraced run may take each step's passes before the step's
