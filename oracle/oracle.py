@@ -38,12 +38,13 @@ class _Problem(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("scheme", C.c_int32),
                 ("f32", C.c_int32), ("replay", C.c_int32),
-                ("exact_weights", C.c_int32), ("ess_frac", C.c_double)]
+                ("exact_weights", C.c_int32), ("ess_frac", C.c_double), ("arity", C.c_int32)]
 
 
 class _Trace(C.Structure):
     _fields_ = [("sstar", _i32p), ("enf", _dp), ("lpost", _dp), ("anc", _i32p),
-                ("pi", _i32p), ("digest", _u64p), ("x", _dp), ("logz_inc", _dp), ("fmean", _dp)]
+                ("pi", _i32p), ("digest", _u64p), ("x", _dp), ("logz_inc", _dp), ("fmean", _dp),
+                ("lpre", _dp)]
 
 
 _lib = None
@@ -212,7 +213,7 @@ class Trace:
     """Host arrays the oracle fills (or, in replay mode, reads)."""
 
     def __init__(self, prob, anc=True, pi=True, lpost=True, enf=True, digest=True,
-                 x=False, logz_inc=True, fmean=False):
+                 x=False, logz_inc=True, fmean=False, lpre=False):
         T, m, N = prob.T, prob.m, prob.N
         S = m.bit_length() - 1
         self.sstar = np.zeros(T, dtype=np.int32)
@@ -224,6 +225,7 @@ class Trace:
         self.x = np.zeros(T * m * N * prob.dx) if x else None
         self.logz_inc = np.zeros(T) if logz_inc else None
         self.fmean = np.zeros(T * m) if fmean else None
+        self.lpre = np.zeros(T * m) if lpre else None
         self.S = S
 
     def _c(self):
@@ -237,29 +239,31 @@ class Trace:
         t.x = _ptr(self.x, _dp)
         t.logz_inc = _ptr(self.logz_inc, _dp)
         t.fmean = _ptr(self.fmean, _dp)
+        t.lpre = _ptr(self.lpre, _dp)
         return t
 
 
-def _opts(tau, scheme, f32, replay=0, ess_frac=0.0):
+def _opts(tau, scheme, f32, replay=0, ess_frac=0.0, arity=2):
     o = _Opts()
     o.tau, o.scheme, o.f32, o.replay, o.exact_weights = float(tau), int(scheme), int(f32), int(replay), 0
-    o.ess_frac = float(ess_frac)
+    o.ess_frac, o.arity = float(ess_frac), int(arity)
     return o
 
 
-def run(prob, tau=0.3, scheme=0, f32=False, trace=None, ess_frac=0.0):
+def run(prob, tau=0.3, scheme=0, f32=False, trace=None, ess_frac=0.0, arity=2):
     """Forward AIRPF; returns log Zhat (fixed-point weights).  ``f32``:
     binary32 particles (state, normals, model, weights; island log-weights
     and log Zhat in double).  ``ess_frac`` > 0: adaptive internal
-    resampling (an island resamples iff its ESS < ess_frac * N)."""
-    p, o = prob._c(), _opts(tau, scheme, f32, ess_frac=ess_frac)
+    resampling (an island resamples iff its ESS < ess_frac * N).
+    ``arity`` r: islands interact in groups of r (m a power of r)."""
+    p, o = prob._c(), _opts(tau, scheme, f32, ess_frac=ess_frac, arity=arity)
     t = trace._c() if trace is not None else None
     return lib().orc_airpf_run(C.byref(p), C.byref(o), C.byref(t) if t is not None else None)
 
 
-def score(prob, tau=0.3, scheme=0, f32=False, trace=None):
+def score(prob, tau=0.3, scheme=0, f32=False, trace=None, arity=2):
     """Forward-mode score; returns (log Zhat, grad_pathwise, grad_pathspace)."""
-    p, o = prob._c(), _opts(tau, scheme, f32)
+    p, o = prob._c(), _opts(tau, scheme, f32, arity=arity)
     t = trace._c() if trace is not None else None
     gpw = np.zeros(prob.theta.size)
     gps = np.zeros(prob.theta.size)

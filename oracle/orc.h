@@ -47,6 +47,9 @@ typedef struct {
                             island resamples iff its ESS < rho N (ESS from the
                             fixed-point weights truncated to 20 bits), else
                             its particles keep their weights                 */
+  int32_t arity;         /* r of the interactions, m = r^(S_r): 0 or 2 the
+                            pairs of Algorithm 1; 4, 8, ... (powers of two)
+                            groups of r islands per stage                     */
 } orc_opts;
 
 typedef struct {
@@ -61,6 +64,8 @@ typedef struct {
   double* fmean;         /* [T*m]        island k's weighted mean of the first
                             state coordinate after the weighting:
                             sum_i q_i x_i / Q, summed in particle order     */
+  double* lpre;          /* [T*m]        island log-weights entering each
+                            weighting (after the previous step's stages)     */
 } orc_trace;
 
 /* ---- counter-based RNG (orc_rng.c) ---- */

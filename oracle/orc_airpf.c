@@ -29,6 +29,15 @@
  *        W'_k = W'_p = (W_k + W_p)/2         (the normaliser line),
  *        block k := block p with probability W_p / (W_k + W_p), drawn
  *        independently for every island, else block k is kept.
+ *      r-ary interactions (Section 2 allows m = r^S for any r >= 2; here r
+ *      a power of two): S_r = log_r m stages, A_s = I (x) (1/r)1_r (x)
+ *      I_{r^(s-1)}, so stage s groups the r islands whose base-r digits
+ *      agree except digit s-1.  Interacting: every member's new weight is
+ *      the group mean (r/2 pair means, then pair means of those, in digit
+ *      order), and block k := block of member d with probability
+ *      W_d / sum W: the first d whose running sum of exp(L_d - max L)
+ *      exceeds u times the total, u island k's uniform of the stage (the
+ *      last live member if rounding leaves none).
  *   7. Mutation into step n+1 (the final-stage line), also when m = 1 or
  *      when no stage interacted: x_{n+1}^{k,j} ~ K(block pi(k) slot j, .),
  *      where pi(k) is the original island whose (internally resampled)
@@ -125,6 +134,26 @@ static double prob_partner(double Lk, double Lp) {
   return 1.0 / (1.0 + orc_exp(Lk - Lp));
 }
 
+/* the member of island k's r-group that island k's stage draw u selects:
+   W_d / sum W by a running sum of exp(L_d - max); all dead: k's own digit */
+static int32_t pick_in_group(const double* L, int32_t base, int32_t b, int32_t r, int32_t own, double u) {
+  double hi = -INFINITY;
+  for (int32_t d = 0; d < r; ++d) if (L[base + d * b] > hi) hi = L[base + d * b];
+  if (hi == -INFINITY) return own;
+  double tot = 0.0;
+  for (int32_t d = 0; d < r; ++d) tot += orc_exp(L[base + d * b] - hi);
+  const double t = u * tot;
+  double run = 0.0;
+  int32_t last = own;
+  for (int32_t d = 0; d < r; ++d) {
+    const double w = orc_exp(L[base + d * b] - hi);
+    run += w;
+    if (w > 0.0) last = d;
+    if (t < run) return d;
+  }
+  return last;
+}
+
 /* log((W_k + W_p)/2), symmetric in its arguments */
 static double pair_mean(double a, double b) {
   const double hi = a > b ? a : b, lo = a > b ? b : a;
@@ -133,6 +162,15 @@ static double pair_mean(double a, double b) {
   t = 1.0 + t;
   t = orc_log(t);
   return (hi + t) - 0x1.62e42fefa39efp-1;
+}
+
+/* log of the mean of the r group members' weights: pair means of
+   neighbours in digit order, then of those, up to one value (gv: r slots) */
+static double group_mean(const double* L, int32_t base, int32_t b, int32_t r, double* gv) {
+  for (int32_t d = 0; d < r; ++d) gv[d] = L[base + d * b];
+  for (int32_t w = r; w > 1; w >>= 1)
+    for (int32_t i = 0; i < w / 2; ++i) gv[i] = pair_mean(gv[2 * i], gv[2 * i + 1]);
+  return gv[0];
 }
 
 static double lse(const double* L, int64_t m) {
@@ -166,6 +204,12 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
   const int32_t m = P->m, N = P->N, dx = P->dx, dy = P->dy;
   const int64_t T = P->T;
   const int S = ilog2(m);
+  /* r-ary interactions: r = 2^rb, m = r^Sr */
+  const int32_t r = O->arity == 0 ? 2 : O->arity;
+  if (r < 2 || (r & (r - 1)) != 0 || r > 65536) return -1;
+  const int rb = ilog2(r);
+  if (S % rb != 0) return -1;
+  const int Sr = S / rb;
   orc_model M;
   orc_model_setup(&M, P, O->f32);
   const int nd = orc_model_noise_dim(&M);
@@ -216,6 +260,7 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
   double* dq = calloc((size_t)m, sizeof(double));
   double* dqn = calloc((size_t)m, sizeof(double));
   int* resamp = malloc(sizeof(int) * m);
+  double* gv = malloc(sizeof(double) * r);
   const double cst_x = M.c_log - log((double)N);
 
   /* Initialisation: W^k_{0,0} = 1, xi^k_{0,0} ~ pi_0^{(x)M} */
@@ -236,6 +281,7 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
     const double* yn = P->y + n * dy;
     if (tr && tr->enf) tr->enf[n * (S + 1)] = enf_of(L, m);
     if (tr && tr->x) memcpy(tr->x + n * mN * dx, x, sizeof(double) * mN * dx);
+    if (tr && tr->lpre) memcpy(tr->lpre + n * m, L, sizeof(double) * m);
     const double lse_pre = lse(L, m);
     for (int32_t k = 0; k < m; ++k) Lpre[k] = Lx[k];
 
@@ -354,15 +400,44 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
       }
     }
 
-    /* filter interaction: stages s = 1..S */
+    /* filter interaction: stages s = 1..Sr (Sr = S for pairs) */
     for (int32_t k = 0; k < m; ++k) pi[k] = k;
     int sstar = 0;
-    for (int s = 1; s <= S; ++s) {
+    for (int s = 1; s <= Sr; ++s) {
       const double enf = enf_of(L, m);
       if (tr && tr->enf) tr->enf[n * (S + 1) + s] = enf;
       const int interact = O->replay ? (s <= tr->sstar[n]) : (enf < O->tau);
       if (!interact) continue;          /* alpha_s = I: weights and blocks unchanged */
       sstar = s;
+      if (rb > 1) {
+        /* groups of r: the members of island k's group are base + d b */
+        const int32_t b = 1 << ((s - 1) * rb);
+        for (int32_t k = 0; k < m; ++k) {
+          const int32_t own = (k / b) % r, base = k - own * b;
+          if (!O->replay) {
+            uint32_t w[4];
+            orc_draw(P->seed, (uint32_t)s, (uint32_t)k, (uint32_t)n, TAG_ISL, 0, w);
+            src[k] = base + b * pick_in_group(L, base, b, r, own, orc_u53(w[0], w[1]));
+          } else {
+            src[k] = k;
+          }
+          pinew[k] = pi[src[k]];
+          Lnew[k] = group_mean(L, base, b, r, gv);
+          Lxnew[k] = group_mean(Lx, base, b, r, gv);
+          if (want_score) {
+            double hi = -INFINITY, tot = 0.0;
+            for (int32_t d = 0; d < r; ++d) if (Lx[base + d * b] > hi) hi = Lx[base + d * b];
+            for (int pp = 0; pp < Pn; ++pp) dLn[(int64_t)k * Pn + pp] = 0.0;
+            for (int32_t d = 0; d < r; ++d) {
+              const int32_t l = base + d * b;
+              const double wl = (hi == -INFINITY) ? 1.0 : exp(Lx[l] - hi);
+              tot += wl;
+              for (int pp = 0; pp < Pn; ++pp) dLn[(int64_t)k * Pn + pp] += wl * dL[(int64_t)l * Pn + pp];
+            }
+            for (int pp = 0; pp < Pn; ++pp) dLn[(int64_t)k * Pn + pp] /= tot;
+          }
+        }
+      } else {
       const int32_t b = 1 << (s - 1);
       for (int32_t k = 0; k < m; ++k) {
         const int32_t p = k ^ b;
@@ -385,6 +460,7 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
             dLn[(int64_t)k * Pn + pp] = (wk * dL[(int64_t)k * Pn + pp] + wp * dL[(int64_t)p * Pn + pp]) / (wk + wp);
         }
       }
+      }  /* pairs */
       memcpy(pi, pinew, sizeof(int32_t) * m);
       memcpy(L, Lnew, sizeof(double) * m);
       memcpy(Lx, Lxnew, sizeof(double) * m);
@@ -451,7 +527,7 @@ static int airpf_core(const orc_problem* P, const orc_opts* O, orc_trace* tr,
   free(Lpre); free(Lnew); free(Lxnew); free(pi); free(pinew); free(src); free(z);
   free(dX); free(dXn); free(Sp); free(Spn); free(dL); free(dLn); free(dlw);
   free(Sf); free(Sfn);
-  free(lc); free(lcn); free(dq); free(dqn); free(resamp);
+  free(lc); free(lcn); free(dq); free(dqn); free(resamp); free(gv);
   return 0;
 }
 

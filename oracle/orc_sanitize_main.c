@@ -27,6 +27,10 @@ static void check(int ok, const char* what) {
   if (!ok) { fprintf(stderr, "FAILED: %s\n", what); ++fails; }
 }
 
+/* options the later cases set: r of the interactions, adaptive threshold */
+static int g_arity = 2;
+static double g_ess = 0.0;
+
 static void case_run(int kind, int dx, int dy, int m, int N, int T, double tau, int scheme, int f32) {
   double theta[64], consts[3 + 64];
   int dth = 3;
@@ -45,10 +49,10 @@ static void case_run(int kind, int dx, int dy, int m, int N, int T, double tau, 
   if (kind == ORC_BCP)
     for (int i = 0; i < T; ++i) { y[2 * i] = (double)(i % 7); y[2 * i + 1] = 20.0; }
   orc_problem P = {kind, dx, dy, dth, theta, consts, y, T, m, N, 12345};
-  orc_opts O = {tau, scheme, f32, 0, 0};
+  orc_opts O = {tau, scheme, f32, 0, 0, g_ess, g_arity};
   const int S = (int)round(log2((double)m));
   const size_t mN = (size_t)m * N;
-  orc_trace tr;
+  orc_trace tr = {0};
   tr.sstar = calloc((size_t)T, sizeof(int32_t));
   tr.enf = calloc((size_t)T * (S + 1), sizeof(double));
   tr.lpost = calloc((size_t)T * m, sizeof(double));
@@ -58,6 +62,7 @@ static void case_run(int kind, int dx, int dy, int m, int N, int T, double tau, 
   tr.x = calloc((size_t)T * mN * dx, sizeof(double));
   tr.logz_inc = calloc((size_t)T, sizeof(double));
   tr.fmean = calloc((size_t)T * m, sizeof(double));
+  tr.lpre = calloc((size_t)T * m, sizeof(double));
   const double lz = orc_airpf_run(&P, &O, &tr);
   check(lz == lz, "run returned NaN");
   if (kind != ORC_BIN && kind != ORC_BCP) {
@@ -82,7 +87,7 @@ static void case_run(int kind, int dx, int dy, int m, int N, int T, double tau, 
     free(anc);
   }
   free(tr.sstar); free(tr.enf); free(tr.lpost); free(tr.anc); free(tr.pi); free(tr.digest);
-  free(tr.x); free(tr.logz_inc); free(tr.fmean); free(y);
+  free(tr.x); free(tr.logz_inc); free(tr.fmean); free(tr.lpre); free(y);
 }
 
 int main(void) {
@@ -105,6 +110,16 @@ int main(void) {
   case_run(ORC_BIN, 1, 1, 1, 8, 5, 0.3, 0, 0);
   case_run(ORC_BCP, 2, 2, 8, 16, 12, 0.5, 0, 0);      /* Beta change points */
   case_run(ORC_BCP, 2, 2, 4, 5, 9, 2.0, 1, 0);
+  g_ess = 0.6;                                         /* adaptive internal resampling */
+  case_run(ORC_SV, 1, 1, 16, 37, 9, 0.7, 0, 0);
+  case_run(ORC_LGD, 3, 2, 4, 6, 5, 2.0, 0, 1);
+  g_ess = 0.0;
+  g_arity = 4;                                         /* groups of four islands */
+  case_run(ORC_LG1, 1, 1, 64, 7, 9, 0.9, 0, 0);
+  case_run(ORC_LGD, 3, 2, 16, 5, 6, 2.0, 1, 1);
+  g_arity = 16;
+  case_run(ORC_SV, 1, 1, 256, 3, 5, 0.95, 0, 0);
+  g_arity = 2;
   if (fails) return 1;
   printf("sanitised oracle run: ok\n");
   return 0;
