@@ -139,6 +139,22 @@ typedef struct {
                           states, systematic; score, batch and
                           airpf_run_noalloc return AIRPF_E_UNSUPPORTED);
                           negative or NaN: AIRPF_E_INVALID_ARG */
+  int32_t arity;       /* r of the island interactions (Section 2 allows
+                          m = r^S for any r >= 2): 0 or 2, the pairs of
+                          Algorithm 1; 4, 8, 16, ... (powers of two, m a
+                          power of r): S / log2(r) stages, stage s grouping
+                          the r islands whose base-r digits differ only in
+                          digit s-1 (A_s = I (x) (1/r)1_r (x) I); when it
+                          interacts every member takes the group mean
+                          weight and each island's block is drawn from its
+                          group with probability W_d / sum W (the first
+                          member whose running sum of exp(L_d - max L)
+                          exceeds u times the total, u the island's uniform
+                          of the stage).  The ENF of stage s is that of the
+                          weights after the stages below.  airpf_run and
+                          airpf_run_noalloc (the score and the batch return
+                          AIRPF_E_UNSUPPORTED); other values, or m not a
+                          power of r: AIRPF_E_INVALID_ARG */
 } airpf_options;
 
 /* Optional per-call trace, host arrays (any may be NULL). */

@@ -50,7 +50,7 @@ class _Model(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("tau", C.c_double), ("resampling", C.c_int32), ("precision", C.c_int32),
                 ("score_mode", C.c_int32), ("ckpt_every", C.c_int32), ("flags", C.c_uint32),
-                ("resample_ess", C.c_double)]
+                ("resample_ess", C.c_double), ("arity", C.c_int32)]
 
 
 class _Problem(C.Structure):
@@ -183,7 +183,7 @@ class Context:
 
     @staticmethod
     def _args(kind, theta, y, tau, fp64, dx, dy, consts, y_device_ptr, T, score_mode=PATHSPACE, ckpt_every=0,
-              resampling=SYSTEMATIC, resample_ess=0.0):
+              resampling=SYSTEMATIC, resample_ess=0.0, arity=2):
         theta = np.ascontiguousarray(theta, dtype=np.float64)
         model = _Model()
         model.kind, model.dx, model.dy = int(kind), int(dx), int(dy)
@@ -193,7 +193,7 @@ class Context:
         opt = _Options()
         opt.tau, opt.resampling, opt.precision = float(tau), int(resampling), FP64 if fp64 else FP32
         opt.score_mode, opt.ckpt_every, opt.flags = int(score_mode), int(ckpt_every), 0
-        opt.resample_ess = float(resample_ess)
+        opt.resample_ess, opt.arity = float(resample_ess), int(arity)
         if y_device_ptr is not None:
             ptr = C.c_void_p(int(y_device_ptr))
             opt.flags |= FLAG_Y_ON_DEVICE
@@ -206,15 +206,17 @@ class Context:
         return theta, model, cst, opt, ptr, Tn, yy
 
     def run(self, kind, theta, y, m, N, seed, tau=0.3, fp64=False, dx=1, dy=1, consts=None,
-            trace=None, y_device_ptr=None, T=None, raise_on_error=True, resampling=SYSTEMATIC, resample_ess=0.0):
+            trace=None, y_device_ptr=None, T=None, raise_on_error=True, resampling=SYSTEMATIC, resample_ess=0.0,
+            arity=2):
         """airpf_run: returns (status, log Zhat).  ``y`` is a host array, or
         pass ``y_device_ptr`` (int) and ``T`` for observations already in HBM.
         ``resampling``: SYSTEMATIC or MULTINOMIAL internal resampling;
         ``resample_ess`` > 0: adaptive internal resampling (an island
-        resamples iff its ESS < resample_ess * N)."""
+        resamples iff its ESS < resample_ess * N); ``arity`` r: islands
+        interact in groups of r (m a power of r)."""
         theta, model, cst, opt, ptr, Tn, keep = self._args(kind, theta, y, tau, fp64, dx, dy, consts,
                                                            y_device_ptr, T, resampling=resampling,
-                                                           resample_ess=resample_ess)
+                                                           resample_ess=resample_ess, arity=arity)
         out = C.c_double(np.nan)
         tr = trace._c() if trace is not None else None
         st = lib().airpf_run(self._h, C.byref(model), _p(theta, _dp), theta.size, ptr, Tn, int(m), int(N),
@@ -225,12 +227,13 @@ class Context:
         return st, out.value
 
     def run_noalloc(self, kind, theta, y, m, N, seed, tau=0.3, fp64=False, dx=1, dy=1, consts=None,
-                    y_device_ptr=None, T=None, raise_on_error=True, resampling=SYSTEMATIC, resample_ess=0.0):
+                    y_device_ptr=None, T=None, raise_on_error=True, resampling=SYSTEMATIC, resample_ess=0.0,
+                    arity=2):
         """airpf_run_noalloc (workspaces in the library's fixed device
         scratch, nothing allocated): returns (status, log Zhat)."""
         theta, model, cst, opt, ptr, Tn, keep = self._args(kind, theta, y, tau, fp64, dx, dy, consts,
                                                            y_device_ptr, T, resampling=resampling,
-                                                           resample_ess=resample_ess)
+                                                           resample_ess=resample_ess, arity=arity)
         out = C.c_double(np.nan)
         st = lib().airpf_run_noalloc(self._h, C.byref(model), _p(theta, _dp), theta.size, ptr, Tn, int(m), int(N),
                                      C.c_uint64(int(seed)), C.byref(opt), C.byref(out))
@@ -240,11 +243,11 @@ class Context:
 
     def score(self, kind, theta, y, m, N, seed, tau=0.3, fp64=False, dx=1, dy=1, consts=None,
               ckpt_every=0, score_mode=PATHSPACE, trace=None, y_device_ptr=None, T=None, raise_on_error=True,
-              resampling=SYSTEMATIC, resample_ess=0.0):
+              resampling=SYSTEMATIC, resample_ess=0.0, arity=2):
         """airpf_score: returns (status, log Zhat, gradient)."""
         theta, model, cst, opt, ptr, Tn, keep = self._args(kind, theta, y, tau, fp64, dx, dy, consts,
                                                            y_device_ptr, T, score_mode, ckpt_every, resampling,
-                                                           resample_ess)
+                                                           resample_ess, arity)
         out = C.c_double(np.nan)
         grad = np.full(theta.size, np.nan)
         tr = trace._c() if trace is not None else None
@@ -257,7 +260,7 @@ class Context:
 
     def run_batch(self, kind, problems, tau=0.3, fp64=False, dx=1, dy=1, consts=None, want_score=False,
                   ckpt_every=0, y_on_device=False, autotune=False, raise_on_error=True, resampling=SYSTEMATIC,
-                  score_mode=PATHSPACE, resample_ess=0.0):
+                  score_mode=PATHSPACE, resample_ess=0.0, arity=2):
         """airpf_run_batch.  ``problems``: dicts with theta, y (host array, or a
         device pointer int with ``y_on_device`` and then T), m, N, seed;
         ``autotune`` sets AIRPF_FLAG_AUTOTUNE (measured tiling, cached per
@@ -273,7 +276,7 @@ class Context:
         opt = _Options()
         opt.tau, opt.resampling, opt.precision = float(tau), int(resampling), FP64 if fp64 else FP32
         opt.score_mode, opt.ckpt_every = int(score_mode), int(ckpt_every)
-        opt.resample_ess = float(resample_ess)
+        opt.resample_ess, opt.arity = float(resample_ess), int(arity)
         opt.flags = (FLAG_Y_ON_DEVICE if y_on_device else 0) | (FLAG_AUTOTUNE if autotune else 0)
         arr = (_Problem * max(B, 1))()
         keep = []

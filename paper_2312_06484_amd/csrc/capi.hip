@@ -285,6 +285,7 @@ airpf_options default_options() {
   o.ckpt_every = 0;
   o.flags = 0;
   o.resample_ess = 0.0;
+  o.arity = 2;
   return o;
 }
 
@@ -330,9 +331,13 @@ airpf_status prepare(airpf_ctx* ctx, const airpf_model* model, const double* the
   // in double, every workspace from the context
   if (adapt && (opt.resampling != AIRPF_SYSTEMATIC || fixed)) return AIRPF_E_UNSUPPORTED;
   if (adapt) P->opt.precision = AIRPF_FP64;
+  // r-ary interactions: r a power of two and m a power of r
+  const int32_t arity = opt.arity == 0 ? 2 : opt.arity;
+  if (arity < 2 || !is_pow2(arity) || ilog2(m) % ilog2(arity) != 0) return AIRPF_E_INVALID_ARG;
 
   airpf::FwdArgs& a = P->a;
   std::memset(&a, 0, sizeof(a));
+  a.arity_log2 = ilog2(arity);
   a.multinomial = opt.resampling == AIRPF_MULTINOMIAL ? 1 : 0;
   const airpf_status st = prepare_model(model, theta, d_theta, N, &a.mp, &a.cst_q, &P->dx, &P->dy);
   if (st == AIRPF_E_DOMAIN) { *log_z_out = -INFINITY; return st; }
@@ -539,7 +544,7 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   // the reverse pass finds a particle's children as a run of sorted ancestors
   if (opt.resampling == AIRPF_MULTINOMIAL) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
   // adaptive internal resampling: forward only
-  if (opt.resample_ess != 0.0) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
+  if (opt.resample_ess != 0.0 || (opt.arity != 0 && opt.arity != 2)) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
   // the word-driven models' mutations are not differentiable in theta
   if (model && (model->kind == AIRPF_BIN || model->kind == AIRPF_BCP)) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
   if (model && ((model->kind == AIRPF_LGD && N > 512) || (model->kind != AIRPF_LGD && N > 1024))) {
@@ -821,7 +826,8 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   if (!ctx || !model || B < 0 || (B > 0 && (!probs || !log_z_out || !item_status))) return AIRPF_E_INVALID_ARG;
   if (model->kind == AIRPF_BIN || model->kind == AIRPF_BCP) return AIRPF_E_UNSUPPORTED;   // single problems only
   const airpf_options opt = opt_in ? *opt_in : default_options();
-  if (opt.resample_ess != 0.0) return AIRPF_E_UNSUPPORTED;      // adaptive internal resampling: single problems
+  // adaptive internal resampling and r-ary interactions: single problems
+  if (opt.resample_ess != 0.0 || (opt.arity != 0 && opt.arity != 2)) return AIRPF_E_UNSUPPORTED;
   if (want_score && !grad_out) return AIRPF_E_INVALID_ARG;
   if (!(opt.tau == opt.tau) || (opt.precision != AIRPF_FP32 && opt.precision != AIRPF_FP64) || opt.ckpt_every < 0)
     return AIRPF_E_INVALID_ARG;

@@ -28,7 +28,9 @@
 // walks each of its islands down the stages s*, ..., 1: at stage s island
 // cur takes its partner cur ^ 2^(s-1) with probability
 // W_p / (W_cur + W_p) (draw at (step, island cur, stage s)).  The island's
-// next weight is its 2^{s*}-block mean.
+// next weight is its 2^{s*}-block mean.  With r-ary interactions (r = 2^rb)
+// stage t reads tree level (t-1) rb + 1, and the walk's island takes the
+// member d of its r-group with probability W_d / sum W.
 //
 // ENF at stage s (W the weights after s-1 interacting stages, B_b the sums of
 // the aligned 2^{s-1}-blocks): every island holds its block mean, so
@@ -120,6 +122,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
   const int team = tid / TP, lane = tid & (TP - 1);
   const int wave = tid >> 6, lane64 = tid & 63;
   const int m = a.m, N = a.N, S = a.S, c = a.c, lc = a.lc, G = a.G;
+  const int rb = a.arity_log2 > 1 ? a.arity_log2 : 1, Sr = S / rb;   // r-ary interactions: Sr stages
   const int kbase = bid * c;
   const Key key = make_key(a.seed);
   const int passes = (c + tpb - 1) / tpb;
@@ -243,7 +246,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
           if (bid == 0 && tid == 0) *a.out_logz = ninf();
           return;
         }
-        sstar = S;
+        sstar = Sr;
       } else {
         // ENF of up to four stages at once, one per wave; a stage that does not
         // interact leaves every weight unchanged, so every later stage sees the
@@ -252,23 +255,27 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         // cover, so a step whose first stage does not interact never needs
         // the upper tree.
         bool stop = false;
-        int s_hi = lc + 1 < kWaves ? lc + 1 : kWaves;
-        if (s_hi > S) s_hi = S;
-        for (int s0 = 1; s0 <= S && !stop; s0 = s_hi + 1, s_hi = s0 + kWaves - 1 < S ? s0 + kWaves - 1 : S) {
-          if (s_hi > lc + 1) build_upper_to(ppar, s_hi);
+        // stage t reads tree level lev(t) = (t-1) rb + 1 (level t for pairs)
+        auto lev = [&](int t) { return (t - 1) * rb + 1; };
+        int s_hi = lc / rb + 1 < kWaves ? lc / rb + 1 : kWaves;
+        if (s_hi > Sr) s_hi = Sr;
+        for (int s0 = 1; s0 <= Sr && !stop; s0 = s_hi + 1, s_hi = s0 + kWaves - 1 < Sr ? s0 + kWaves - 1 : Sr) {
+          if (lev(s_hi) > lc + 1) build_upper_to(ppar, lev(s_hi));
           const int sw = s0 + wave;
           if (sw <= s_hi) {
+            const int lv = lev(sw);
             EnfRec r;
-            if (sw <= lc + 1) {
-              const double* ps = a.part[ppar] + static_cast<int64_t>(sw - 1) * 3 * G;
+            if (lv <= lc + 1) {
+              const double* ps = a.part[ppar] + static_cast<int64_t>(lv - 1) * 3 * G;
               r = wave_reduce_enf(G, [&](int i) { return EnfRec{get(ps + i), get(ps + G + i), get(ps + 2 * G + i)}; });
             } else {
-              const double* lvl = up + 2 * G - ((2 * G) >> (sw - lc - 1));
-              r = wave_reduce_enf(G >> (sw - lc - 1), [&](int i) { return enf_leaf(lvl[i]); });
+              const double* lvl = up + 2 * G - ((2 * G) >> (lv - lc - 1));
+              r = wave_reduce_enf(G >> (lv - lc - 1), [&](int i) { return enf_leaf(lvl[i]); });
             }
-            // after s-1 interacting stages every island holds its 2^{s-1}-block
-            // mean: sum_k W_k = 2^{s-1} sum_b w_b, sum_k W_k^2 = 2^{s-1} sum_b w_b^2
-            const double blk = static_cast<double>(1 << (sw - 1));
+            // after the interacting stages below, every island holds the mean
+            // of its aligned 2^{lv-1}-block: sum_k W_k = 2^{lv-1} sum_b w_b,
+            // sum_k W_k^2 = 2^{lv-1} sum_b w_b^2
+            const double blk = static_cast<double>(1 << (lv - 1));
             const double am = (blk * r.a) * __builtin_ldexp(1.0, -S), bm = (blk * r.b) * __builtin_ldexp(1.0, -S);   // m = 2^S: scaling by the exact reciprocal is the division
             if ((tid & 63) == 0) { s_enf[wave] = (am * am) / bm; s_encmax[wave] = r.E; }
           }
@@ -281,13 +288,13 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
             const double enf = s_enf[t - s0];
             const bool go = enf < a.tau;
             if (tr_enf && bid == 0 && tid == 0)
-              for (int q = t; q <= (go ? t : S); ++q) tr_enf[(n - 1) * (S + 1) + q] = enf;
+              for (int q = t; q <= (go ? t : Sr); ++q) tr_enf[(n - 1) * (S + 1) + q] = enf;
             if (!go) { stop = true; break; }
             sstar = t;
           }
           __syncthreads();
         }
-        if (sstar + 1 > lc + 1) build_upper_to(ppar, sstar + 1);
+        if (sstar * rb + 1 > lc + 1) build_upper_to(ppar, sstar * rb + 1);
       }
       if (bid == 0 && tid == 0) {
         if (tr_sstar) tr_sstar[n - 1] = sstar;
@@ -326,6 +333,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         if (replay) {
           cur = tr_pi[(n - 1) * m + k];
         } else {
+          if (rb == 1) {
           for (int s = sstar; s >= 1; --s) {
             const int pr = cur ^ (1 << (s - 1));
             const double lc_ = lt_value(ppar, s, cur >> (s - 1));
@@ -334,7 +342,45 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
             draw4(key, static_cast<uint32_t>(s), static_cast<uint32_t>(cur), static_cast<uint32_t>(n - 1), kTagIsl, 0, w);
             if (uniform53(w[0], w[1]) < take_partner_prob(lc_, lp_)) cur = pr;
           }
-          lpre = lt_value(ppar, sstar + 1, k >> sstar);
+          } else {
+            // r-ary: at stage s island cur takes member d of its group (the
+            // islands differing from it only in base-r digit s-1) with
+            // probability W_d / sum W: the first d whose running sum of
+            // exp(L_d - max L) exceeds u times the total (the last live
+            // member if rounding leaves none; all dead: itself)
+            const int ar = 1 << rb;
+            for (int s = sstar; s >= 1; --s) {
+              const int p = (s - 1) * rb;
+              const int own = (cur >> p) & (ar - 1);
+              const int b0 = (cur >> p) - own;               // the group's first member at level p + 1
+              uint32_t w[4];
+              draw4(key, static_cast<uint32_t>(s), static_cast<uint32_t>(cur), static_cast<uint32_t>(n - 1), kTagIsl, 0, w);
+              const double u = uniform53(w[0], w[1]);
+              double hi = ninf();
+              for (int d = 0; d < ar; ++d) {
+                const double v = lt_value(ppar, p + 1, b0 + d);
+                hi = v > hi ? v : hi;
+              }
+              int pick = own;
+              if (hi != ninf()) {
+                double tot = 0.0;
+                for (int d = 0; d < ar; ++d) tot += dexp(lt_value(ppar, p + 1, b0 + d) - hi);
+                const double t = u * tot;
+                double run = 0.0;
+                int last = own;
+                bool found = false;
+                for (int d = 0; d < ar && !found; ++d) {
+                  const double wd = dexp(lt_value(ppar, p + 1, b0 + d) - hi);
+                  run += wd;
+                  if (wd > 0.0) last = d;
+                  if (t < run) { pick = d; found = true; }
+                }
+                if (!found) pick = last;
+              }
+              cur = (b0 + pick) << p | (cur & ((1 << p) - 1));
+            }
+          }
+          lpre = lt_value(ppar, sstar * rb + 1, k >> (sstar * rb));
           if (tr_pi) tr_pi[(n - 1) * m + k] = cur;
           if (tr_digest) atomicAdd(&tr_digest[2 * (n - 1) + 1], digest_term(n - 1, k, 4095, cur));
         }
@@ -1417,7 +1463,7 @@ inline bool fwd_is_score_forward(const FwdArgs& a) {
 
 inline bool fwd_pipe_candidate(const FwdArgs& a, int TP) {
   if (!(fwd_is_plain(a) || fwd_is_score_forward(a)) || TP > 64 || a.shortcut_all || a.ess_frac > 0.0 ||
-      a.multinomial)
+      a.multinomial || (a.arity_log2 > 1 && !a.no_interaction))
     return false;
   const char* e = std::getenv("AIRPF_PIPELINE");
   return !(e && e[0] == '0');

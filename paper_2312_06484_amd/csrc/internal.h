@@ -49,6 +49,9 @@ struct FwdArgs {
   // parity, [m*N] and [m]
   double ess_frac;
   double log_N;
+  // r-ary interactions, r = 2^arity_log2 (0 or 1: the pairs of Algorithm 1):
+  // stage t groups the r islands that differ only in base-r digit t-1
+  int arity_log2;
   double* lc1[2];
   double* dq1[2];
   // ---- what the score needs (all optional) ----
