@@ -599,27 +599,37 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, const int bid) {
         // = 0 if N C <= U, else min(N, floor((N C - U - 1) / Q) + 1): each
         // particle marks the first slot of its run, and a slot's ancestor is
         // the last mark at or before it.  The quotient is estimated in double
-        // precision (within one of the exact one, as x / Q <= N) and
-        // corrected in integers.
+        // precision (within one of the exact one, as x / Q < N <= 2048, so
+        // 32 bits hold it) and corrected in integers.
         const double rQ = 1.0 / static_cast<double>(Qk);
         auto S_of = [&](uint64_t C) -> int {
           const uint64_t NC = static_cast<uint64_t>(N) * C;
           const uint64_t xq = NC > U ? NC - U - 1 : 0;
-          uint64_t qd = static_cast<uint64_t>(floor(static_cast<double>(xq) * rQ));
-          qd = qd * Qk > xq ? qd - 1 : qd;
-          qd = xq - qd * Qk >= Qk ? qd + 1 : qd;
-          const uint64_t sv = qd + 1;
-          return NC <= U ? 0 : (sv < static_cast<uint64_t>(N) ? static_cast<int>(sv) : N);
+          uint32_t qd = static_cast<uint32_t>(static_cast<double>(xq) * rQ);
+          uint64_t pr = static_cast<uint64_t>(qd) * Qk;
+          if (pr > xq) { qd -= 1u; pr -= Qk; }
+          if (xq - pr >= Qk) qd += 1u;
+          const uint32_t sv = qd + 1u;
+          return NC <= U ? 0 : (sv < static_cast<uint32_t>(N) ? static_cast<int>(sv) : N);
         };
-        uint64_t C = incl - tsum;                              // C_{j0-1}
-        int s_prev = S_of(C);
-        team_sync(TP);
+        // S at the lane's prefix sums; S of the sum before its first
+        // particle (C_{j0-1}) is its left neighbour's last, 0 at a team's
+        // first lane, evaluated where the neighbour is in another wave
+        const uint64_t C0 = incl - tsum;                       // C_{j0-1}
+        uint64_t C = C0;
+        int sc[PPT];
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           C += q[r];
-          const int s_cur = S_of(C);
-          if (active && Qk > 0 && j0 + r < N && s_cur > s_prev) sAt[s_prev] = j0 + r;
-          s_prev = s_cur;
+          sc[r] = S_of(C);
+        }
+        const int left = __shfl(sc[PPT - 1], lane64 == 0 ? 0 : lane64 - 1, 64);
+        int s_prev = lane == 0 ? 0 : (lane64 == 0 ? S_of(C0) : left);
+        team_sync(TP);
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          if (active && Qk > 0 && j0 + r < N && sc[r] > s_prev) sAt[s_prev] = j0 + r;
+          s_prev = sc[r];
         }
         team_sync(TP);
         int mk[PPT];
@@ -860,7 +870,13 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   int64_t sys_base = -1;                      // first step of the batch in sysw
   auto run_passes = [&](int64_t n, bool spec) {
     const int ppar = static_cast<int>((n & 1) ^ 1);                // HBM copies of step n-1, by parity
-    const int sl = static_cast<int>(n % 3), psl = static_cast<int>((n + 2) % 3);   // LDS slots of steps n, n-1
+    const int n32 = static_cast<int>(n);                           // steps are below 2^30
+    const int sl = n32 % 3, psl = (n32 + 2) % 3;                   // LDS slots of steps n, n-1
+    // the observation of step n, loaded ahead of the mutation (the kernel
+    // compiled for a team width runs the one-dimensional models, whose
+    // observations are one value)
+    double y_early = 0.0;
+    if constexpr (TPC > 0) y_early = s_y[(n32 / kYChunk) & 1][n32 % kYChunk];
     for (int p = 0; p < passes; ++p) {
       const int li = p * tpb + team;
       const bool active = li < c;
@@ -875,9 +891,16 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
             draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(base + lane), kTagSys, 0, sysw);
           sys_base = base;
         }
-        const int src_lane = (tid & 63 & ~(TP - 1)) | static_cast<int>(n - base);
+        if (TP == 64) {
+          // one team per wave: the step's lane is the same for every lane
+          const int sl_ = static_cast<int>(n - base);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) wsys[i] = static_cast<uint32_t>(__shfl(static_cast<int>(sysw[i]), src_lane, 64));
+          for (int i = 0; i < 4; ++i) wsys[i] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(sysw[i]), sl_));
+        } else {
+          const int src_lane = (tid & 63 & ~(TP - 1)) | static_cast<int>(n - base);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) wsys[i] = static_cast<uint32_t>(__shfl(static_cast<int>(sysw[i]), src_lane, 64));
+        }
       } else if (n < T - 1 && lane == 0) {
         draw4(key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, 0, wsys);
       }
@@ -934,13 +957,14 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
       }
 
       // ---- weighting ----
-      const double* yn = s_y[(n / kYChunk) & 1] + (n % kYChunk) * a.dy;
+      const double* yn = s_y[(n32 / kYChunk) & 1] + (n32 % kYChunk) * a.dy;
+      const double yreg[1] = {y_early};
       Store lw[PPT];
       Store mx = neg_inf<Store>();
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
         const bool valid = active && (j0 + r < N);
-        Store v = valid ? Model::template logpot<Store>(a.mp, x[r], yn) : neg_inf<Store>();
+        Store v = valid ? Model::template logpot<Store>(a.mp, x[r], TPC > 0 ? yreg : yn) : neg_inf<Store>();
         if (!(v == v)) v = neg_inf<Store>();
         lw[r] = v;
         mx = rmax(mx, v);
@@ -976,24 +1000,34 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
           U = bounded_u64_from(wsys, key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, Qk);
         U = team_bcast(U, TP, bc_u);
         const double rQ = 1.0 / static_cast<double>(Qk);
+        // x < N C <= N Q, so the quotient x / Q is below N <= 2048 and 32 bits
+        // hold it (and its estimate, within one of it)
         auto S_of = [&](uint64_t C) -> int {
           const uint64_t NC = static_cast<uint64_t>(N) * C;
           const uint64_t xq = NC > U ? NC - U - 1 : 0;
-          uint64_t qd = static_cast<uint64_t>(floor(static_cast<double>(xq) * rQ));
-          qd = qd * Qk > xq ? qd - 1 : qd;
-          qd = xq - qd * Qk >= Qk ? qd + 1 : qd;
-          const uint64_t sv = qd + 1;
-          return NC <= U ? 0 : (sv < static_cast<uint64_t>(N) ? static_cast<int>(sv) : N);
+          uint32_t qd = static_cast<uint32_t>(static_cast<double>(xq) * rQ);
+          uint64_t pr = static_cast<uint64_t>(qd) * Qk;
+          if (pr > xq) { qd -= 1u; pr -= Qk; }
+          if (xq - pr >= Qk) qd += 1u;
+          const uint32_t sv = qd + 1u;
+          return NC <= U ? 0 : (sv < static_cast<uint32_t>(N) ? static_cast<int>(sv) : N);
         };
+        // S at the lane's prefix sums; S of the sum before its first
+        // particle is its left neighbour's last (0 at a team's first lane)
         uint64_t C = incl - tsum;
-        int s_prev = S_of(C);
-        team_sync(TP);
+        int sc[PPT];
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
           C += q[r];
-          const int s_cur = S_of(C);
-          if (active && Qk > 0 && j0 + r < N && s_cur > s_prev) sAt[s_prev] = j0 + r;
-          s_prev = s_cur;
+          sc[r] = S_of(C);
+        }
+        const int left = __shfl(sc[PPT - 1], lane64 == 0 ? 0 : lane64 - 1, 64);
+        int s_prev = lane == 0 ? 0 : left;                     // (teams lie inside one wave)
+        team_sync(TP);
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          if (active && Qk > 0 && j0 + r < N && sc[r] > s_prev) sAt[s_prev] = j0 + r;
+          s_prev = sc[r];
         }
         team_sync(TP);
         int mk[PPT];
