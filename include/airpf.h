@@ -253,12 +253,15 @@ typedef struct {
  * Tiling: a problem's time is modelled as steps * (1 + r * passes) (a pass
  * is one round of island work of a block); with AIRPF_FLAG_AUTOTUNE in
  * opt->flags the library times the tilings of several r on the first (up to)
- * 32 steps of every problem, keeps the fastest and caches it in the context
- * for batches of the same shape (model, precision, score, and every
- * problem's T, m, N), so only the first such call pays for the probes; with
- * the environment variable AIRPF_TUNE_CACHE naming a file, measured ratios
- * are also appended there and read back by later processes (one text line
- * "<shape key, hex> <ratio>" per measurement).
+ * 32 steps of every problem, for four and for eight particles per lane when
+ * a forward-only systematic batch of a one-dimensional model allows both
+ * (islands of at most 1024 particles), keeps the fastest and caches it in
+ * the context for batches of the same shape (model, precision, score,
+ * resampling, and every problem's T, m, N), so only the first such call
+ * pays for the probes; with the environment variable AIRPF_TUNE_CACHE
+ * naming a file, the measured choices are also appended there and read
+ * back by later processes (one text line "<shape key, hex> <ratio>
+ * <particles per lane>" per measurement).
  * Tiling never changes results. */
 airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model, int32_t B,
                              const airpf_problem* probs, const airpf_options* opt,

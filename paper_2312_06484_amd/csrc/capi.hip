@@ -96,9 +96,10 @@ struct airpf_ctx {
   DevBuf s_pi, s_sstar, s_lpre, s_ckx, s_ckL, s_recx, s_reca, s_lam[2], s_del[2], s_grad, s_nu;
   DevBuf dbg_in, dbg_in32, dbg_out, dbg_out2, dbg_out32;
   DevBuf batch;
-  // tiler cost ratios (pass time / step overhead) measured by AIRPF_FLAG_AUTOTUNE,
-  // keyed by batch shape
+  // tiler cost ratios (pass time / step overhead) and particles per lane
+  // measured by AIRPF_FLAG_AUTOTUNE, keyed by batch shape
   std::map<uint64_t, double> tuned_ratio;
+  std::map<uint64_t, int> tuned_ppt;
 };
 
 #define HIP_OK(expr) do { if ((expr) != hipSuccess) return AIRPF_E_DEVICE; } while (0)
@@ -240,29 +241,38 @@ airpf_status prepare_model(const airpf_model* model, const double* theta, int32_
   return AIRPF_OK;
 }
 
-// AIRPF_TUNE_CACHE=<file>: the tiler's measured cost ratios persist across
-// processes in that text file, one line "<batch-shape key, hex> <ratio>"
-// per shape; it is read when the context's own cache misses and appended
-// after a measurement (an unreadable or absent file is a miss).
-bool tune_cache_lookup(uint64_t key, double* ratio) {
+// AIRPF_TUNE_CACHE=<file>: the tiler's measured choices persist across
+// processes in that text file, one line "<batch-shape key, hex> <ratio>
+// <particles per lane>" per shape (0, or a line without the third field:
+// the default rule); it is read when the context's own cache misses and
+// appended after a measurement (an unreadable or absent file is a miss).
+bool tune_cache_lookup(uint64_t key, double* ratio, int* ppt) {
   const char* path = std::getenv("AIRPF_TUNE_CACHE");
   if (!path || !*path) return false;
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
-  unsigned long long k = 0;
-  double r = 0.0;
+  char line[160];
   bool found = false;
-  while (std::fscanf(f, "%llx %lf", &k, &r) == 2)
-    if (k == key && r > 0.0 && std::isfinite(r)) { *ratio = r; found = true; }   // the last line of a key wins
+  while (std::fgets(line, sizeof(line), f)) {
+    unsigned long long k = 0;
+    double r = 0.0;
+    int p = 0;
+    const int got = std::sscanf(line, "%llx %lf %d", &k, &r, &p);
+    if (got < 2 || k != key || !(r > 0.0) || !std::isfinite(r)) continue;
+    if (got < 3 || (p != 4 && p != 8)) p = 0;
+    *ratio = r;                                        // the last line of a key wins
+    *ppt = p;
+    found = true;
+  }
   std::fclose(f);
   return found;
 }
 
-void tune_cache_store(uint64_t key, double ratio) {
+void tune_cache_store(uint64_t key, double ratio, int ppt) {
   const char* path = std::getenv("AIRPF_TUNE_CACHE");
   if (!path || !*path) return;
   if (FILE* f = std::fopen(path, "a")) {
-    std::fprintf(f, "%016llx %.17g\n", static_cast<unsigned long long>(key), ratio);
+    std::fprintf(f, "%016llx %.17g %d\n", static_cast<unsigned long long>(key), ratio, ppt);
     std::fclose(f);
   }
 }
@@ -873,26 +883,45 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   HIP_OK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
 
-  const int ppt_f = airpf::forward_ppt(model->kind, dx, n_max, !want_score);
+  const int ppt_rule = airpf::forward_ppt(model->kind, dx, n_max, !want_score);
+  int ppt_f = ppt_rule;
   const int ppt_b = want_score ? airpf::backward_ppt(model->kind, dx, n_max) : 0;
-  for (Item& it : items) {
-    it.TP = pow2_ceil_i((it.N + ppt_f - 1) / ppt_f);
-    it.tpb = 256 / it.TP;
-  }
   airpf::BatchLaunch BL;
   BL.kind = model->kind; BL.dx = dx; BL.fp64 = fp64; BL.n_max = n_max; BL.num_cus = ctx->num_cus;
-  BL.ppt = ppt_f;
   BL.plain = want_score ? 0 : 1;          // the score's forward launches record and replay
   BL.multinomial = mult;
   BL.stream = s; BL.blocks = 0; BL.probs = nullptr; BL.bmap = nullptr;
-  BL.smem = airpf::forward_smem(fp64, ppt_f, dx, 256, 256, airpf::kResidentBudget, mult);   // bound of any tiling below
   int cap_f = 0, cap_fp = 0;
-  HIP_OK(airpf::forward_batch_capacity(BL, &cap_f));
-  {
+  // particles per lane of the forward launches: the items' teams, the LDS
+  // bound of any tiling and the co-resident block counts follow from it
+  auto set_ppt = [&](int p) -> airpf_status {
+    ppt_f = p;
+    for (Item& it : items) {
+      it.TP = pow2_ceil_i((it.N + p - 1) / p);
+      it.tpb = 256 / it.TP;
+    }
+    BL.ppt = p;
+    BL.smem = airpf::forward_smem(fp64, p, dx, 256, 256, airpf::kResidentBudget, mult);   // bound of any tiling below
+    HIP_OK(airpf::forward_batch_capacity(BL, &cap_f));
     airpf::BatchLaunch BP = BL;
     BP.plain = 1;
     HIP_OK(airpf::forward_batch_capacity(BP, &cap_fp));
+    return AIRPF_OK;
+  };
+  // the autotuner's choices of particles per lane: a forward-only
+  // systematic batch of a one-dimensional model whose islands fit four per
+  // lane (at most 1024 particles) may take four or eight (results do not
+  // depend on it); otherwise the rule's
+  std::vector<int> ppt_cand{ppt_rule};
+  if ((opt.flags & AIRPF_FLAG_AUTOTUNE) && !std::getenv("AIRPF_TILER") && !want_score && !mult &&
+      model->kind != AIRPF_LGD && n_max <= 1024)
+    ppt_cand = {4, 8};
+  int cap_f_max = 0;
+  for (int p : ppt_cand) {
+    ST_OK(set_ppt(p));
+    cap_f_max = std::max(cap_f_max, cap_f);
   }
+  ST_OK(set_ppt(ppt_rule));
   int cap_b = 0;
   if (want_score) {
     airpf::BatchLaunch BB = BL;
@@ -928,7 +957,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   {
     int64_t blocks_max = 0;
     for (const Item& it : items) blocks_max += it.m;
-    o_bmap = ar.take(sizeof(int2) * size_t(std::min<int64_t>(blocks_max, int64_t(cap_f > cap_b ? cap_f : cap_b) + 1)));
+    o_bmap = ar.take(sizeof(int2) * size_t(std::min<int64_t>(blocks_max, int64_t(cap_f_max > cap_b ? cap_f_max : cap_b) + 1)));
   }
   for (Item& it : items) {
     const size_t mN = size_t(it.m) * it.N;
@@ -1067,22 +1096,33 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
   std::vector<int64_t> steps;
   for (Item& it : items) { all.push_back(&it); steps.push_back(it.T); }
 
-  // ---- AIRPF_FLAG_AUTOTUNE: time the tilings of a few cost ratios on the
-  // first (up to) 32 steps of every problem (plain forward runs whose
-  // results are discarded) and keep the fastest, cached per batch shape ----
+  // ---- AIRPF_FLAG_AUTOTUNE: time the tilings of a few cost ratios, for
+  // each choice of particles per lane, on the first (up to) 32 steps of
+  // every problem (plain forward runs whose results are discarded) and keep
+  // the fastest, cached per batch shape ----
   if ((opt.flags & AIRPF_FLAG_AUTOTUNE) && !std::getenv("AIRPF_TILER")) {
     uint64_t key = 0x9E3779B97F4A7C15ULL;
     auto mix = [&](uint64_t v) { key = (key ^ v) * 0xff51afd7ed558ccdULL; key ^= key >> 29; };
-    mix(uint64_t(model->kind)); mix(uint64_t(dx)); mix(uint64_t(fp64)); mix(uint64_t(want_score));
+    mix(uint64_t(model->kind)); mix(uint64_t(dx)); mix(uint64_t(fp64)); mix(uint64_t(want_score)); mix(uint64_t(mult));
     for (const Item& it : items) { mix(uint64_t(it.T)); mix(uint64_t(it.m)); mix(uint64_t(it.N)); }
     auto hit = ctx->tuned_ratio.find(key);
     double filed = 0.0;
-    if (hit == ctx->tuned_ratio.end() && tune_cache_lookup(key, &filed)) hit = ctx->tuned_ratio.emplace(key, filed).first;
+    int filed_ppt = 0;
+    if (hit == ctx->tuned_ratio.end() && tune_cache_lookup(key, &filed, &filed_ppt)) {
+      hit = ctx->tuned_ratio.emplace(key, filed).first;
+      ctx->tuned_ppt[key] = filed_ppt;
+    }
     if (hit != ctx->tuned_ratio.end()) {
       ratio = hit->second;
+      const auto hp = ctx->tuned_ppt.find(key);
+      const int p = hp == ctx->tuned_ppt.end() ? 0 : hp->second;
+      if (p != 0 && std::find(ppt_cand.begin(), ppt_cand.end(), p) != ppt_cand.end()) ST_OK(set_ppt(p));
     } else {
       const double cand[] = {1.0 / 32, 1.0 / 8, 1.0 / 3, 1.0, 4.0};
       double best_ms = -1.0, best = ratio;
+      int best_ppt = ppt_rule;
+      for (int p : ppt_cand) {
+      ST_OK(set_ppt(p));
       std::vector<std::vector<int>> seen;
       for (double r : cand) {
         ratio = r;
@@ -1102,11 +1142,14 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
         if (pst != AIRPF_OK) continue;
         float ms = 0.0f;
         HIP_OK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
-        if (best_ms < 0 || ms < best_ms) { best_ms = ms; best = r; }
+        if (best_ms < 0 || ms < best_ms) { best_ms = ms; best = r; best_ppt = p; }
+      }
       }
       ratio = best;
+      ST_OK(set_ppt(best_ppt));
       ctx->tuned_ratio[key] = ratio;
-      tune_cache_store(key, ratio);
+      ctx->tuned_ppt[key] = best_ppt;
+      tune_cache_store(key, ratio, best_ppt);
     }
   }
   HIP_OK(hipEventRecord(ctx->ev[0], s));

@@ -104,7 +104,8 @@ def test_batch_autotuned_tiling_changes_nothing(ctx, want_score):
 
 def test_autotune_cache_file_persists_across_contexts(tmp_path, monkeypatch):
     """With AIRPF_TUNE_CACHE naming a file, a fresh context's autotuned batch
-    appends its measured ratio there (one line per shape), and a second fresh
+    appends its measured ratio and particles per lane there (one line per
+    shape), and a second fresh
     context finds it instead of measuring again; results are unchanged."""
     from paper_2312_06484_amd import airpf
     path = tmp_path / "tune.txt"
@@ -119,8 +120,8 @@ def test_autotune_cache_file_persists_across_contexts(tmp_path, monkeypatch):
             c.close()
         lines = [l for l in path.read_text().splitlines() if l.strip()]
         assert len(lines) == 1, lines
-        key, ratio = lines[0].split()
-        assert len(key) == 16 and float(ratio) > 0
+        key, ratio, ppt = lines[0].split()
+        assert len(key) == 16 and float(ratio) > 0 and int(ppt) in (4, 8)
     assert np.array_equal(out[0][1], out[1][1]) and (out[0][3] == 0).all()
 
 
