@@ -551,8 +551,13 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
     set_nan(log_z_out);
     return AIRPF_E_INVALID_ARG;
   }
-  // the reverse pass finds a particle's children as a run of sorted ancestors
-  if (opt.resampling == AIRPF_MULTINOMIAL) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
+  // multinomial internal resampling: the reverse pass sorts each step's
+  // slots by ancestor (models whose gradient is an outer product of the
+  // slot sums keep those sums in slot order: not with multinomial draws)
+  if (opt.resampling == AIRPF_MULTINOMIAL && model && model->kind == AIRPF_LGD) {
+    set_nan(log_z_out);
+    return AIRPF_E_UNSUPPORTED;
+  }
   // adaptive internal resampling: forward only
   if (opt.resample_ess != 0.0 || (opt.arity != 0 && opt.arity != 2)) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
   // the word-driven models' mutations are not differentiable in theta
@@ -674,6 +679,7 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
   b.c_log = a.cst_q + 40.0 * std::log(2.0) + std::log(static_cast<double>(N));
   b.log_N = std::log(static_cast<double>(N));
   b.pathwise = opt.score_mode == AIRPF_PATHWISE ? 1 : 0;
+  b.multinomial = opt.resampling == AIRPF_MULTINOMIAL ? 1 : 0;
   b.nu[0] = static_cast<double*>(ctx->s_nu.p);
   b.nu[1] = b.nu[0] + m;
   b.logz = a.out_logz;

@@ -80,6 +80,8 @@ struct BwdArgs {
   double log_mN, c_log;       // log(m N) and the constant of log g
   double log_N;               // log N
   int pathwise;               // seed: 0 path-space (descendants' final weights), 1 pathwise (island weights)
+  int multinomial;            // 1: a step's ancestors are in no slot order (multinomial internal
+                              // resampling); the slots are sorted by ancestor before the runs are taken
   double* nu[2];              // pathwise: [m] d log Zhat / d (island log-weight after step n's weighting), by step parity
   const double* logz;         // [1] log Zhat of the forward run (device)
   int64_t n_lo, n_hi;

@@ -300,6 +300,47 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
         }
 
         // ---- back through the internal resampling: runs of equal ancestors ----
+        // Multinomial draws leave the ancestors in no order: the slots are
+        // sorted by (ancestor, slot) first (a bitonic sort of the team's keys
+        // in LDS; keys are distinct, so the order is fixed), and the runs are
+        // taken over the sorted slots, each slot's sums moved to its sorted
+        // position.
+        bool sorted_slots = false;
+        if constexpr (!Model::kThetaOuter) {
+          if (a.multinomial) {
+            constexpr int kNoKey = 0x7fffffff;
+#pragma unroll
+            for (int r = 0; r < PPT; ++r) {
+              const int j = j0 + r;
+              const int aj = sAt[j];
+              sAt[j] = (active && j < N) ? ((aj << 11) | j) : kNoKey;
+#pragma unroll
+              for (int v = 0; v < NV; ++v) sPt[j * NV + v] = sl[r][v];
+            }
+            team_sync(TP);
+            const int np = TP * PPT;
+            for (int kk = 2; kk <= np; kk <<= 1) {
+              for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int t = lane; t < np / 2; t += TP) {
+                  const int i0 = (t / jj) * 2 * jj + (t % jj), i1 = i0 + jj;
+                  const int k0 = sAt[i0], k1 = sAt[i1];
+                  if ((k0 > k1) == ((i0 & kk) == 0)) { sAt[i0] = k1; sAt[i1] = k0; }
+                }
+                team_sync(TP);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < PPT; ++r) {
+              const int key = sAt[j0 + r];
+              const int js = key & 2047;
+#pragma unroll
+              for (int v = 0; v < NV; ++v) sl[r][v] = key != kNoKey ? sPt[js * NV + v] : 0.0;
+            }
+            team_sync(TP);
+            sorted_slots = true;
+          }
+        }
+        auto anc_at = [&](int j) { return sorted_slots ? (sAt[j] >> 11) : sAt[j]; };
         double run_v[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) run_v[v] = 0.0;
@@ -324,9 +365,9 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
         for (int r = 0; r < PPT; ++r) {
           const int j = j0 + r;
           if (active && j < N) {
-            const int aj = sAt[j];
-            if (j == 0 || sAt[j - 1] != aj) sSt[aj] = j;
-            if (j == N - 1 || sAt[j + 1] != aj) sEt[aj] = j;
+            const int aj = anc_at(j);
+            if (j == 0 || anc_at(j - 1) != aj) sSt[aj] = j;
+            if (j == N - 1 || anc_at(j + 1) != aj) sEt[aj] = j;
           }
         }
         team_sync(TP);

@@ -86,6 +86,44 @@ def test_score_parity(ctx, orc, model, m, N, T, tau, f64, dx, K):
     assert_grad_close(grad_pw, gpw, tol)
 
 
+MULT_CASES = [
+    # model, m, N, T, tau, f64, ckpt_every
+    ("lg1", 8, 32, 40, 0.3, True, 0),
+    ("lg1", 16, 37, 25, 0.7, False, 5),          # ragged island size, segments
+    ("lg1", 64, 64, 20, 2.0, True, 6),           # every stage interacts
+    ("sv", 32, 128, 30, 0.6, True, 10),
+    ("sv", 8, 1000, 8, 0.9, False, 3),           # islands of four waves
+]
+
+
+@pytest.mark.parametrize("model,m,N,T,tau,f64,K", MULT_CASES)
+def test_multinomial_score_parity(ctx, orc, model, m, N, T, tau, f64, K):
+    """Multinomial internal resampling: the reverse pass sorts each step's
+    slots by ancestor before taking the runs; both seeds against the
+    oracle's tangents along the same (bit-exact) genealogy."""
+    from paper_2312_06484_amd import airpf
+    g, P = make_case(orc, model, m, N, T, 1)
+    print("case multinomial", model, m, N, T, tau, "f64" if f64 else "f32", "K", K, flush=True)
+    kw = dict(tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"], consts=g["consts"], resampling=airpf.MULTINOMIAL)
+    gt = airpf.Trace(T, m, N, enf=False, lpost=False, anc=False, digest=False)
+    _, lz, grad = ctx.score(g["kind"], g["theta"], g["y"], m, N, 1, ckpt_every=K, trace=gt, **kw)
+    _, lz_pw, grad_pw = ctx.score(g["kind"], g["theta"], g["y"], m, N, 1, ckpt_every=K,
+                                  score_mode=airpf.PATHWISE, **kw)
+    _, lz_run = ctx.run(g["kind"], g["theta"], g["y"], m, N, 1, **kw)
+    assert lz == lz_run == lz_pw
+    ot = orc.Trace(P)
+    lo, gpw, gps = orc.score(P, tau=tau, scheme=1, f32=not f64, trace=ot)
+    assert abs(lz - lo) <= 1e-12 * max(1.0, abs(lo))
+    if T > 1:
+        np.testing.assert_array_equal(gt.pi, ot.pi[: (T - 1) * m])
+    np.testing.assert_array_equal(gt.sstar, ot.sstar)
+    tol = 1e-9 if f64 else 1e-5
+    assert_grad_close(grad, gps, tol)
+    assert_grad_close(grad_pw, gpw, tol)
+    _, _, grad2 = ctx.score(g["kind"], g["theta"], g["y"], m, N, 1, ckpt_every=K, **kw)
+    assert np.array_equal(grad, grad2)                     # the sorted order is fixed
+
+
 def test_score_deterministic_and_segment_invariant(ctx):
     from paper_2312_06484_amd import workloads as W
     y = W.sv_data(40)

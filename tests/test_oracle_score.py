@@ -42,11 +42,12 @@ def ftilde(orc, P, tr, theta, S0, logw0):
 
 @pytest.mark.parametrize("name", ["lg1", "sv", "lgd"])
 @pytest.mark.parametrize("tau", [0.3, 2.0])
-def test_score_matches_frozen_finite_differences(orc, name, tau):
+@pytest.mark.parametrize("scheme", [0, 1])             # systematic, multinomial internal resampling
+def test_score_matches_frozen_finite_differences(orc, name, tau, scheme):
     P = problems(orc)[name]
     tr = orc.Trace(P)
-    lz, gpw, gps = orc.score(P, tau=tau, trace=tr)
-    assert lz == orc.run(P, tau=tau)                  # the score run is the forward run
+    lz, gpw, gps = orc.score(P, tau=tau, scheme=scheme, trace=tr)
+    assert lz == orc.run(P, tau=tau, scheme=scheme)   # the score run is the forward run
     F0, S0, logw0 = orc.frozen(P, tr)
     assert abs(F0 - lz) < 1e-9 * P.T                  # quantisation is negligible
     th0 = P.theta.copy()
