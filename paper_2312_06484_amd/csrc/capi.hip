@@ -849,7 +849,8 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
     return AIRPF_E_INVALID_ARG;
   if (opt.resampling != AIRPF_SYSTEMATIC && opt.resampling != AIRPF_MULTINOMIAL) return AIRPF_E_INVALID_ARG;
   // multinomial draws: forward only (the reverse pass needs sorted ancestors)
-  if (opt.resampling == AIRPF_MULTINOMIAL && want_score) return AIRPF_E_UNSUPPORTED;
+  // multinomial draws with scores: as airpf_score (not the d-dimensional model)
+  if (opt.resampling == AIRPF_MULTINOMIAL && want_score && model->kind == AIRPF_LGD) return AIRPF_E_UNSUPPORTED;
   const int mult = opt.resampling == AIRPF_MULTINOMIAL ? 1 : 0;
   if (want_score && opt.score_mode != AIRPF_PATHSPACE && opt.score_mode != AIRPF_PATHWISE) return AIRPF_E_INVALID_ARG;
   const bool y_dev = (opt.flags & AIRPF_FLAG_Y_ON_DEVICE) != 0;
@@ -1064,6 +1065,7 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
         b.c_log = it.cst_q + 40.0 * std::log(2.0) + std::log(static_cast<double>(it.N));
         b.log_N = std::log(static_cast<double>(it.N));
         b.pathwise = opt.score_mode == AIRPF_PATHWISE ? 1 : 0;
+        b.multinomial = mult;
         b.nu[0] = static_cast<double*>(at(it.o_nu));
         b.nu[1] = b.nu[0] + it.m;
         b.logz = static_cast<const double*>(at(o_logz)) + (&it - items.data());

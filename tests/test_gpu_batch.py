@@ -155,7 +155,7 @@ def test_full_size_proposal_batch_score_matches_single(ctx):
 def test_batch_multinomial_matches_single(ctx):
     # multinomial internal resampling in the batched forward: every item
     # bit-identical to the same problem run alone (whose ancestors are
-    # bit-exact with the oracle's multinomial scheme); scores unsupported
+    # bit-exact with the oracle's multinomial scheme), also with scores
     from paper_2312_06484_amd import airpf
     probs = [dict(theta=W.LG1_THETA, y=W.lg1_data(40), m=64, N=128, seed=1),
              dict(theta=W.LG1_THETA, y=W.lg1_data(25), m=16, N=37, seed=2),
@@ -171,5 +171,11 @@ def test_batch_multinomial_matches_single(ctx):
             assert s1 == airpf.OK and lz[i] == l1, (tau, i, lz[i], l1)
         _, lz_sys, _, _ = ctx.run_batch(0, probs, tau=tau)
         assert not np.array_equal(lz_sys, lz)           # a different scheme, a different estimate
-    st, _, _, _ = ctx.run_batch(0, probs, want_score=True, resampling=airpf.MULTINOMIAL, raise_on_error=False)
-    assert st == airpf.E_UNSUPPORTED
+    # with scores: every item's log Zhat and gradient bit-identical to its
+    # single multinomial score
+    st, lz, gr, ist = ctx.run_batch(0, probs, tau=0.3, want_score=True, ckpt_every=7, resampling=airpf.MULTINOMIAL)
+    assert st == airpf.OK and (ist == airpf.OK).all()
+    for i, p in enumerate(probs):
+        s1, l1, g1 = ctx.score(0, p["theta"], p["y"], p["m"], p["N"], p["seed"], tau=0.3, ckpt_every=7,
+                               resampling=airpf.MULTINOMIAL)
+        assert s1 == airpf.OK and lz[i] == l1 and np.array_equal(gr[i], g1), (i, gr[i], g1)
