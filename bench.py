@@ -396,7 +396,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the filter of one parameter value is one "
-              "device's work here (see DESIGN.md for how it would shard); got --gpus %d" % args.gpus,
+              "device's work here (no multi-GPU path is built); got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
