@@ -114,12 +114,9 @@ typedef struct {
                          AIRPF_SYSTEMATIC everywhere; AIRPF_MULTINOMIAL (slot j
                          takes the first particle whose cumulative fixed-point
                          weight exceeds its own uniform draw on [0, Q)) in
-                         airpf_run and airpf_run_batch, and with scores
-                         (airpf_score, a batch with want_score) for the
-                         one-dimensional models (the reverse pass sorts each
-                         step's slots by ancestor) -- scores of AIRPF_LGD
-                         return AIRPF_E_UNSUPPORTED for it; any other value
-                         is AIRPF_E_INVALID_ARG */
+                         airpf_run, airpf_run_batch and airpf_score (the
+                         reverse pass sorts each step's slots by ancestor);
+                         any other value is AIRPF_E_INVALID_ARG */
   int32_t precision;  /* precision of the particles: AIRPF_FP64 everything in
                          double; AIRPF_FP32 binary32 state, normals, model
                          and fixed-point weights (own single-precision exp,

@@ -551,13 +551,8 @@ extern "C" airpf_status airpf_score(airpf_ctx* ctx, const airpf_model* model, co
     set_nan(log_z_out);
     return AIRPF_E_INVALID_ARG;
   }
-  // multinomial internal resampling: the reverse pass sorts each step's
-  // slots by ancestor (models whose gradient is an outer product of the
-  // slot sums keep those sums in slot order: not with multinomial draws)
-  if (opt.resampling == AIRPF_MULTINOMIAL && model && model->kind == AIRPF_LGD) {
-    set_nan(log_z_out);
-    return AIRPF_E_UNSUPPORTED;
-  }
+  // (multinomial internal resampling: the reverse pass sorts each step's
+  // slots by ancestor)
   // adaptive internal resampling: forward only
   if (opt.resample_ess != 0.0 || (opt.arity != 0 && opt.arity != 2)) { set_nan(log_z_out); return AIRPF_E_UNSUPPORTED; }
   // the word-driven models' mutations are not differentiable in theta
@@ -849,8 +844,6 @@ extern "C" airpf_status airpf_run_batch(airpf_ctx* ctx, const airpf_model* model
     return AIRPF_E_INVALID_ARG;
   if (opt.resampling != AIRPF_SYSTEMATIC && opt.resampling != AIRPF_MULTINOMIAL) return AIRPF_E_INVALID_ARG;
   // multinomial draws: forward only (the reverse pass needs sorted ancestors)
-  // multinomial draws with scores: as airpf_score (not the d-dimensional model)
-  if (opt.resampling == AIRPF_MULTINOMIAL && want_score && model->kind == AIRPF_LGD) return AIRPF_E_UNSUPPORTED;
   const int mult = opt.resampling == AIRPF_MULTINOMIAL ? 1 : 0;
   if (want_score && opt.score_mode != AIRPF_PATHSPACE && opt.score_mode != AIRPF_PATHWISE) return AIRPF_E_INVALID_ARG;
   const bool y_dev = (opt.flags & AIRPF_FLAG_Y_ON_DEVICE) != 0;

@@ -306,7 +306,7 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
         // taken over the sorted slots, each slot's sums moved to its sorted
         // position.
         bool sorted_slots = false;
-        if constexpr (!Model::kThetaOuter) {
+        {
           if (a.multinomial) {
             constexpr int kNoKey = 0x7fffffff;
 #pragma unroll
@@ -381,6 +381,24 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, const int bid) {
             for (int v = 0; v < NV; ++v) tot[v] = sPt[e0 * NV + v] - (s0 > 0 ? sPt[(s0 - 1) * NV + v] : 0.0);
             Model::prop_vjp_x(a.mp, tot, lam[r]);
             D[r] = tot[DX];
+            if constexpr (Model::kThetaOuter) {
+              // sorted slots: the outer products below are taken per parent,
+              // its children's sums with its own state (the same sum grouped
+              // by parent)
+              if (sorted_slots) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sl[r][v] = tot[v];
+              }
+            }
+          } else if (sorted_slots) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sl[r][v] = 0.0;          // a parent without children
+          }
+          if constexpr (Model::kThetaOuter) {
+            if (sorted_slots) {
+#pragma unroll
+              for (int d = 0; d < DX; ++d) xp[r][d] = (active && i < N) ? x[r][d] : 0.0;
+            }
           }
         }
         if (a.pathwise) {

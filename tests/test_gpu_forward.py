@@ -403,12 +403,3 @@ def test_multinomial_parity(ctx, orc, model, m, N, T, tau, f64, dx):
     _, lz2 = ctx.run(g["kind"], g["theta"], g["y"], m, N, 4, **kw)
     assert lz2 == lz
 
-
-def test_multinomial_score_of_the_linear_gaussian_d_model_is_unsupported(ctx, orc):
-    """(The d-dimensional model's gradient is an outer product of the slots'
-    sums with their parents' states, kept in slot order.)"""
-    from paper_2312_06484_amd import airpf
-    g, _ = make_case(orc, "lgd", 4, 16, 10, 1, 3)
-    st, lz, gr = ctx.score(g["kind"], g["theta"], g["y"], 4, 16, 1, dx=3, dy=2, consts=g["consts"],
-                           resampling=airpf.MULTINOMIAL, raise_on_error=False)
-    assert st == airpf.E_UNSUPPORTED and np.isnan(gr).all()

@@ -87,23 +87,25 @@ def test_score_parity(ctx, orc, model, m, N, T, tau, f64, dx, K):
 
 
 MULT_CASES = [
-    # model, m, N, T, tau, f64, ckpt_every
-    ("lg1", 8, 32, 40, 0.3, True, 0),
-    ("lg1", 16, 37, 25, 0.7, False, 5),          # ragged island size, segments
-    ("lg1", 64, 64, 20, 2.0, True, 6),           # every stage interacts
-    ("sv", 32, 128, 30, 0.6, True, 10),
-    ("sv", 8, 1000, 8, 0.9, False, 3),           # islands of four waves
+    # model, m, N, T, tau, f64, dx, ckpt_every
+    ("lg1", 8, 32, 40, 0.3, True, None, 0),
+    ("lg1", 16, 37, 25, 0.7, False, None, 5),    # ragged island size, segments
+    ("lg1", 64, 64, 20, 2.0, True, None, 6),     # every stage interacts
+    ("sv", 32, 128, 30, 0.6, True, None, 10),
+    ("sv", 8, 1000, 8, 0.9, False, None, 3),     # islands of four waves
+    ("lgd", 16, 64, 12, 0.5, True, 8, 5),        # the gradient as outer products, per parent
+    ("lgd", 8, 33, 10, 0.8, False, 3, 4),
 ]
 
 
-@pytest.mark.parametrize("model,m,N,T,tau,f64,K", MULT_CASES)
-def test_multinomial_score_parity(ctx, orc, model, m, N, T, tau, f64, K):
+@pytest.mark.parametrize("model,m,N,T,tau,f64,dx,K", MULT_CASES)
+def test_multinomial_score_parity(ctx, orc, model, m, N, T, tau, f64, dx, K):
     """Multinomial internal resampling: the reverse pass sorts each step's
     slots by ancestor before taking the runs; both seeds against the
     oracle's tangents along the same (bit-exact) genealogy."""
     from paper_2312_06484_amd import airpf
-    g, P = make_case(orc, model, m, N, T, 1)
-    print("case multinomial", model, m, N, T, tau, "f64" if f64 else "f32", "K", K, flush=True)
+    g, P = make_case(orc, model, m, N, T, 1, dx)
+    print("case multinomial", model, dx, m, N, T, tau, "f64" if f64 else "f32", "K", K, flush=True)
     kw = dict(tau=tau, fp64=f64, dx=g["dx"], dy=g["dy"], consts=g["consts"], resampling=airpf.MULTINOMIAL)
     gt = airpf.Trace(T, m, N, enf=False, lpost=False, anc=False, digest=False)
     _, lz, grad = ctx.score(g["kind"], g["theta"], g["y"], m, N, 1, ckpt_every=K, trace=gt, **kw)
