@@ -93,6 +93,14 @@ def test_rary_independent_filters_are_the_pair_filter(ctx):
     assert a == b
 
 
+def test_rary_without_allocation(ctx):
+    """airpf_run_noalloc runs the same kernels: equal to airpf_run."""
+    y = W.lg1_data(30)
+    a = ctx.run(0, W.LG1_THETA, y, 256, 64, 7, tau=0.9, arity=4)[1]
+    b = ctx.run_noalloc(0, W.LG1_THETA, y, 256, 64, 7, tau=0.9, arity=4)[1]
+    assert a == b and np.isfinite(a)
+
+
 def test_rary_invalid_and_unsupported(ctx):
     from paper_2312_06484_amd import airpf
     y = W.lg1_data(10)
