@@ -34,6 +34,8 @@ def ctx():
     ("lg1", 256, 256, 25, 0.9, 0.3, None),         # several blocks, interactions on most steps
     ("lg1", 32, 16, 30, 0.0, 0.5, None),           # independent filters
     ("sv", 4, 1000, 8, 2.0, 0.9, None),            # islands of several waves, every stage interacts
+    ("lg1", 1, 64, 20, 0.3, 0.5, None),            # one island: no stages
+    ("sv", 8, 1, 10, 0.5, 0.9, None),              # one particle per island
 ])
 def test_adaptive_parity(ctx, orc, model, m, N, T, tau, rho, dx):
     from paper_2312_06484_amd import airpf

@@ -93,6 +93,15 @@ def test_rary_independent_filters_are_the_pair_filter(ctx):
     assert a == b
 
 
+def test_rary_one_island(ctx, orc):
+    """m = 1 is a power of every r: no stages, the bootstrap filter."""
+    y = W.lg1_data(15)
+    a = ctx.run(0, W.LG1_THETA, y, 1, 64, 3, tau=2.0, fp64=True, arity=8)[1]
+    b = ctx.run(0, W.LG1_THETA, y, 1, 64, 3, tau=2.0, fp64=True)[1]
+    P = orc.Problem(orc.LG1, W.LG1_THETA, y, 1, 64, 3)
+    assert a == b and abs(a - orc.run(P, tau=2.0, arity=8)) <= 1e-12 * abs(a)
+
+
 def test_rary_without_allocation(ctx):
     """airpf_run_noalloc runs the same kernels: equal to airpf_run."""
     y = W.lg1_data(30)
