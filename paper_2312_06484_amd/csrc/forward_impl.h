@@ -805,7 +805,9 @@ constexpr int kYChunk = 64;                 // observation steps per LDS chunk
 // TPC > 0: compiled for teams of TPC lanes and full islands (N = TPC * PPT),
 // so that the team reductions, scans and bounds are resolved at compile
 // time (no branch on the team width); 0: any width, read from the arguments.
-template <class Model, typename Store, int PPT, bool Rec, int TPC = 0>
+// Rary: r-ary interactions (r = 2^arity_log2): the control wave's cascade
+// and walk over the groups of r islands (untraced runs).
+template <class Model, typename Store, int PPT, bool Rec, int TPC = 0, bool Rary = false>
 __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;
@@ -1288,6 +1290,85 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
     if (!poll_rec(t, r1)) { s_ctl[1] = 1; return; }
     up_top = 0;
     int sstar = 0;
+    if constexpr (Rary) {
+      // stage u reads tree level (u-1) rb + 1; stage 1 is level 1 as for pairs
+      const int rb = a.arity_log2, Sr = S / rb, ar = 1 << rb;
+      for (int u = 1; u <= Sr; ++u) {
+        const int lv = (u - 1) * rb + 1;
+        EnfRec r;
+        if (u == 1) {
+          r = r1;
+        } else if (lv <= lc + 1) {
+          const double* ps = a.part[par] + static_cast<int64_t>(lv - 1) * 3 * G;
+          r = wave_reduce_enf(G, [&](int i) { return EnfRec{get(ps + i), get(ps + G + i), get(ps + 2 * G + i)}; });
+        } else {
+          build_upper_to(t, lv);
+          const double* lvl = up + 2 * G - ((2 * G) >> (lv - lc - 1));
+          r = wave_reduce_enf(G >> (lv - lc - 1), [&](int i) { return enf_leaf(lvl[i]); });
+        }
+        r = EnfRec{readlane_f64(r.E, 0), readlane_f64(r.a, 0), readlane_f64(r.b, 0)};
+        if (u == 1 && r.E == ninf()) {                                // every island dead
+          if (bid == 0 && lane64 == 0) *a.out_logz = ninf();
+          s_ctl[1] = 1;
+          return;
+        }
+        const double blk = static_cast<double>(1 << (lv - 1));
+        const double am = (blk * r.a) * __builtin_ldexp(1.0, -S), bm = (blk * r.b) * __builtin_ldexp(1.0, -S);
+        if (!enf_below(am, bm, a.tau)) break;
+        sstar = u;
+        if (u == 1) {
+          if (next_out) retract_rec(t + 1);
+          write_out(t);
+          publish(t, 2);
+          if (!barrier()) { s_ctl[1] = 1; return; }
+        }
+      }
+      if (sstar > 0) {
+        if (sstar * rb + 1 > lc + 1) build_upper_to(t, sstar * rb + 1);
+        for (int li = lane64; li < c; li += 64) {
+          const int k = kbase + li;
+          int cur = k;
+          // at stage u island cur takes member d of its group with
+          // probability W_d / sum W: the first d whose running sum of
+          // exp(L_d - max L) exceeds u times the total (the last live member
+          // if rounding leaves none; all dead: itself)
+          for (int u = sstar; u >= 1; --u) {
+            const int p = (u - 1) * rb;
+            const int own = (cur >> p) & (ar - 1);
+            const int b0 = (cur >> p) - own;
+            uint32_t w[4];
+            draw4(key, static_cast<uint32_t>(u), static_cast<uint32_t>(cur), static_cast<uint32_t>(t), kTagIsl, 0, w);
+            const double uu = uniform53(w[0], w[1]);
+            double hi = ninf();
+            for (int d = 0; d < ar; ++d) {
+              const double v = lt_value(t, p + 1, b0 + d);
+              hi = v > hi ? v : hi;
+            }
+            int pick = own;
+            if (hi != ninf()) {
+              double tot = 0.0;
+              for (int d = 0; d < ar; ++d) tot += dexp(lt_value(t, p + 1, b0 + d) - hi);
+              const double thr = uu * tot;
+              double run = 0.0;
+              int last = own;
+              bool found = false;
+              for (int d = 0; d < ar && !found; ++d) {
+                const double wd = dexp(lt_value(t, p + 1, b0 + d) - hi);
+                run += wd;
+                if (wd > 0.0) last = d;
+                if (thr < run) { pick = d; found = true; }
+              }
+              if (!found) pick = last;
+            }
+            cur = (b0 + pick) << p | (cur & ((1 << p) - 1));
+          }
+          s_src[li] = cur;
+          s_lpre[li] = lt_value(t, sstar * rb + 1, k >> (sstar * rb));
+        }
+      }
+      if (lane64 == 0) s_ctl[0] = sstar;
+      return;
+    }
     for (int s = 1; s <= S; ++s) {
       EnfRec r;
       if (s == 1) {
@@ -1432,9 +1513,9 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   }
 }
 
-template <class Model, typename Store, int PPT, bool Rec, int TPC = 0>
+template <class Model, typename Store, int PPT, bool Rec, int TPC = 0, bool Rary = false>
 __global__ __launch_bounds__(kPipeBlock) void forward_pipe_kernel(FwdArgs a) {
-  forward_pipe_body<Model, Store, PPT, Rec, TPC>(a, static_cast<int>(blockIdx.x));
+  forward_pipe_body<Model, Store, PPT, Rec, TPC, Rary>(a, static_cast<int>(blockIdx.x));
 }
 
 template <class Model, typename Store, int PPT, bool Plain>
@@ -1497,7 +1578,7 @@ inline bool fwd_is_score_forward(const FwdArgs& a) {
 
 inline bool fwd_pipe_candidate(const FwdArgs& a, int TP) {
   if (!(fwd_is_plain(a) || fwd_is_score_forward(a)) || TP > 64 || a.shortcut_all || a.ess_frac > 0.0 ||
-      a.multinomial || (a.arity_log2 > 1 && !a.no_interaction))
+      a.multinomial || (a.arity_log2 > 1 && !a.no_interaction && !fwd_is_plain(a)))
     return false;
   const char* e = std::getenv("AIRPF_PIPELINE");
   return !(e && e[0] == '0');
@@ -1566,7 +1647,9 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
                            : reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, true>);
     // binary32 1-D islands that fill 64- or 32-lane teams: the kernel
     // compiled for that width (same results)
-    if constexpr (std::is_same<Store, float>::value && PPT == 4 && Model::DX == 1) {
+    const bool rary = a.arity_log2 > 1 && !a.no_interaction;
+    if (rary) pk = reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false, 0, true>);
+    else if constexpr (std::is_same<Store, float>::value && PPT == 4 && Model::DX == 1) {
       if (a.N == 64 * PPT)
         pk = plain ? reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false, 64>)
                    : reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, true, 64>);
