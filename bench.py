@@ -168,7 +168,9 @@ def timed(torch, fn, spread=None):
 def measure_modes(ctx, torch):
     """Every configuration of the benchmark table besides the headline one,
     each timed once (wall clock, inputs resident in HBM) after one warm-up
-    call: the 1-D LG workload with interactions off, the SV workload forward
+    call: the 1-D LG workload with interactions off, with multinomial or
+    adaptive internal resampling and with groups of four islands, the SV
+    workload forward
     and forward + score, the 64-chain SV proposal batch forward alone and
     forward + score in one batched call, the latter also one theta at a
     time, 64 PMMH chains (random walk, and Langevin proposals from the
@@ -206,6 +208,19 @@ def measure_modes(ctx, torch):
                                                           device_ms=ctx.last_kernel_ms(),
                                                           logz_minus_kalman=lz - kalman.lg1(W.LG1_THETA, y1,
                                                                                             grad=False)[0], **sp)
+
+    # the variants of the internal step and of the interactions on the same
+    # workload: multinomial internal resampling, adaptive internal
+    # resampling (rho = 0.5, double states), groups of four islands
+    for name, kw, nb in (("multinomial", dict(resampling=1), fwd_bytes(1, 4)),
+                         ("adaptive_rho0.5", dict(resample_ess=0.5), fwd_bytes(1, 8) + 16),   # + carried log-weights
+                         ("arity4", dict(arity=4), fwd_bytes(1, 4))):
+        sp = {}
+        dt, lz = timed(torch, lambda w, kw=kw: ctx.run(0, W.LG1_THETA, None, m, N, 77 if w else 1, tau=0.3,
+                                                       y_device_ptr=yd.data_ptr(), T=T, **kw)[1], sp)
+        out["fwd_lg1_t1000_m1024_n256_" + name] = mode_record(
+            m * N * T, dt, nb, log_z=lz, device_ms=ctx.last_kernel_ms(),
+            logz_minus_kalman=lz - kalman.lg1(W.LG1_THETA, y1, grad=False)[0], **sp)
 
     # SV, T = 2000, 4096 x 128: forward, and forward + path-space score with checkpoints every 100 steps
     T, m, N = 2000, 4096, 128
