@@ -807,7 +807,9 @@ constexpr int kYChunk = 64;                 // observation steps per LDS chunk
 // time (no branch on the team width); 0: any width, read from the arguments.
 // Rary: r-ary interactions (r = 2^arity_log2): the control wave's cascade
 // and walk over the groups of r islands (untraced runs).
-template <class Model, typename Store, int PPT, bool Rec, int TPC = 0, bool Rary = false>
+// Mult: multinomial internal resampling in the workers' passes (untraced
+// runs), as in forward_body.
+template <class Model, typename Store, int PPT, bool Rec, int TPC = 0, bool Rary = false, bool Mult = false>
 __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bid) {
   constexpr int DX = Model::DX;
   constexpr int NZ = PPT * DX;
@@ -853,6 +855,9 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   double* up = lvb + 6 * c;                                                       // [2G]
   Store* res = reinterpret_cast<Store*>(up + 2 * G);                              // [3][c*N*DX]
   const int64_t res_words = static_cast<int64_t>(c) * N * DX;
+  // Mult: each team's inclusive cumulative weights ([kBlock*PPT] uint64)
+  [[maybe_unused]] uint64_t* sC = reinterpret_cast<uint64_t*>(
+      (reinterpret_cast<uintptr_t>(res + 3 * res_words) + 15) & ~static_cast<uintptr_t>(15));
   // a step's island log-weights (and local tree) and resampled states live
   // in slot step mod 3: the steps being decided, published and run
   auto lvp = [&](int sl) { return lvb + 2 * c * sl; };
@@ -997,6 +1002,37 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
           for (int d = 0; d < DX; ++d) sxt[(j0 + r) * DX + d] = static_cast<Store>(x[r][d]);
           sAt[j0 + r] = -1;
         }
+        if constexpr (Mult) {
+          // N independent draws: slot j takes the first particle whose
+          // cumulative weight exceeds U_j, uniform on [0, Q) (its own draw at
+          // (slot j, island, step)), found by binary search
+          uint64_t* sCt = sC + team * TP * PPT;
+          uint64_t Cr = incl - tsum;
+#pragma unroll
+          for (int r = 0; r < PPT; ++r) {
+            Cr += q[r];
+            sCt[j0 + r] = Cr;
+          }
+          team_sync(TP);
+#pragma unroll 1
+          for (int r = 0; r < PPT; ++r) {
+            const int j = j0 + r;
+            if (active && j < N) {
+              int anc = j;
+              if (Qk > 0) {
+                const uint64_t Uj = bounded_u64(key, static_cast<uint32_t>(j), static_cast<uint32_t>(k),
+                                                static_cast<uint32_t>(n), kTagMult, Qk);
+                int lo = 0, hi = N - 1;
+                while (lo < hi) {
+                  const int mid = (lo + hi) >> 1;
+                  if (sCt[mid] > Uj) hi = mid; else lo = mid + 1;
+                }
+                anc = lo;
+              }
+              sAt[j] = anc;
+            }
+          }
+        } else {
         uint64_t U = 0;
         if (lane == 0 && active && Qk > 0)
           U = bounded_u64_from(wsys, key, 0, static_cast<uint32_t>(k), static_cast<uint32_t>(n), kTagSys, Qk);
@@ -1044,6 +1080,7 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
           const int j = j0 + r;
           if (active && j < N) sAt[j] = Qk > 0 ? (mk[r] > before ? mk[r] : before) : j;
         }
+        }  // systematic
         team_sync(TP);
         if (active) {
 #pragma unroll
@@ -1513,9 +1550,9 @@ __device__ __forceinline__ void forward_pipe_body(const FwdArgs& a, const int bi
   }
 }
 
-template <class Model, typename Store, int PPT, bool Rec, int TPC = 0, bool Rary = false>
+template <class Model, typename Store, int PPT, bool Rec, int TPC = 0, bool Rary = false, bool Mult = false>
 __global__ __launch_bounds__(kPipeBlock) void forward_pipe_kernel(FwdArgs a) {
-  forward_pipe_body<Model, Store, PPT, Rec, TPC, Rary>(a, static_cast<int>(blockIdx.x));
+  forward_pipe_body<Model, Store, PPT, Rec, TPC, Rary, Mult>(a, static_cast<int>(blockIdx.x));
 }
 
 template <class Model, typename Store, int PPT, bool Plain>
@@ -1578,7 +1615,8 @@ inline bool fwd_is_score_forward(const FwdArgs& a) {
 
 inline bool fwd_pipe_candidate(const FwdArgs& a, int TP) {
   if (!(fwd_is_plain(a) || fwd_is_score_forward(a)) || TP > 64 || a.shortcut_all || a.ess_frac > 0.0 ||
-      a.multinomial || (a.arity_log2 > 1 && !a.no_interaction && !fwd_is_plain(a)))
+      (a.multinomial && (!fwd_is_plain(a) || a.arity_log2 > 1)) ||
+      (a.arity_log2 > 1 && !a.no_interaction && !fwd_is_plain(a)))
     return false;
   const char* e = std::getenv("AIRPF_PIPELINE");
   return !(e && e[0] == '0');
@@ -1648,7 +1686,8 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
     // binary32 1-D islands that fill 64- or 32-lane teams: the kernel
     // compiled for that width (same results)
     const bool rary = a.arity_log2 > 1 && !a.no_interaction;
-    if (rary) pk = reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false, 0, true>);
+    if (a.multinomial) pk = reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false, 0, false, true>);
+    else if (rary) pk = reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false, 0, true>);
     else if constexpr (std::is_same<Store, float>::value && PPT == 4 && Model::DX == 1) {
       if (a.N == 64 * PPT)
         pk = plain ? reinterpret_cast<const void*>(forward_pipe_kernel<Model, Store, PPT, false, 64>)
@@ -1660,7 +1699,8 @@ static hipError_t launch_t(const FwdLaunch& L, FwdArgs a, FwdPlan* plan) {
     auto pipe_smem_of = [&](int G) {
       const int c = a.m / G;
       return fwd_smem_bytes(sizeof(Store), PPT, Model::DX, c, G) + 8 * 2 * size_t(c) +
-             pipe_res_bytes(sizeof(Store), Model::DX, c, a.N);
+             pipe_res_bytes(sizeof(Store), Model::DX, c, a.N) +
+             (a.multinomial ? 16 + 8 * size_t(kBlock) * PPT : 0);     // the cumulative weights of multinomial draws
     };
     const int G = fit_blocks(pk, kPipeBlock, L, a.m, tpb, L.max_blocks < 256 ? L.max_blocks : 256, pipe_smem_of, &smem);
     if (G >= 1 && a.m / G <= kMaxIslandsPerBlock && pipe_res_bytes(sizeof(Store), Model::DX, a.m / G, a.N) > 0) {
