@@ -12,6 +12,11 @@
 * One item of each (N, m) class of the 64-proposal batch at T = 500, run as
   one forward-only batch (the eight-particles-per-lane batch kernel), each
   log Zhat against the oracle's to 1e-12.
+* The variants the benchmark times at the 1-D width (1024 x 256): the
+  multinomial and r-ary instantiations of the pipelined kernel and the
+  adaptive kernel, untraced as timed, log Zhat against the oracle's to
+  1e-12 and equal to the traced run's, whose stage counts and island maps
+  equal the oracle's.
 """
 import os
 import sys
@@ -96,3 +101,26 @@ def test_proposal_batch_classes_against_oracle(ctx):
         ref = pool.map(_oracle_logz, [(it["theta"], T, it["m"], it["N"], it["seed"]) for it in items])
     for it, v, r in zip(items, lz, ref):
         assert abs(v - r) <= 1e-12 * abs(r), (it["m"], it["N"], v, r)
+
+
+@pytest.mark.parametrize("variant", ["multinomial", "arity4", "adaptive"])
+def test_variants_at_benchmark_width(ctx, orc, variant):
+    from paper_2312_06484_amd import airpf
+    m, N, T, tau, seed = 1024, 256, 40, 0.3, 2
+    y = W.lg1_data(T)
+    P = orc.Problem(orc.LG1, W.LG1_THETA, y, m, N, seed)
+    kw, okw, f64 = {
+        "multinomial": (dict(resampling=airpf.MULTINOMIAL), dict(scheme=1), False),
+        "arity4": (dict(arity=4), dict(arity=4), False),
+        "adaptive": (dict(resample_ess=0.5), dict(ess_frac=0.5), True),
+    }[variant]
+    print("case variant", variant, m, N, T, tau, flush=True)
+    _, lz = ctx.run(0, W.LG1_THETA, y, m, N, seed, tau=tau, fp64=f64, **kw)
+    gt = airpf.Trace(T, m, N, enf=False, lpost=False, anc=False)
+    _, lz_traced = ctx.run(0, W.LG1_THETA, y, m, N, seed, tau=tau, fp64=f64, trace=gt, **kw)
+    assert lz == lz_traced
+    ot = orc.Trace(P, anc=False, lpost=False, enf=False)
+    lo = orc.run(P, tau=tau, f32=not f64, trace=ot, **okw)
+    assert abs(lz - lo) <= 1e-12 * abs(lo), (lz, lo)
+    np.testing.assert_array_equal(gt.sstar, ot.sstar)
+    np.testing.assert_array_equal(gt.pi, ot.pi[: (T - 1) * m])
